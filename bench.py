@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark: time stepping of the 3-D acoustic wave equation on one MI355X.
+
+Workload (default): 512^3 total grid with a 20-cell damping layer, seeded
+8-layer velocity model with a 5 % smoothed perturbation, 15 Hz Ricker source
+5 cells below the layer, a line of 512 receivers, float32 fields.  One bench
+"step" is one full time step of the hot path: the sweep over every point
+(inner region and damping layer), the source add, the receiver sample and the
+rotation of the time levels.
+
+Prints one JSON line: throughput in Gpoints/s (grid points x steps / time),
+the sweep kernel against the HBM roofline (algorithmic bytes / measured
+kernel time), and the float64 CPU oracle timed on a bounded sample of the
+same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0   # MI355X HBM3E nameplate
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    p = os.path.join(ROOT, "paper_2009_04619_amd", "csrc", "wave_kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str, launches_bytes: float):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", f"traffic_sweep_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        t = json.load(open(p))
+    except Exception:
+        return None
+    if t.get("kernel_sha") != kernel_source_sha():
+        return None
+    return float(t["hbm_bytes_per_launch"])
+
+
+def copy_bandwidth(W, torch, nbytes=2 << 30, reps=10):
+    """Plain streaming copy (the measured-bandwidth reference)."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    for _ in range(2):
+        W.wave_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, s.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        W.wave_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, s.cuda_stream)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms / 1e3) / 1e9
+
+
+def cpu_baseline(shot, budget_s: float):
+    """The float64 oracle as it stands on the host cores, on a bounded number
+    of steps of the same grid (calibrated to about `budget_s` seconds)."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    s = shot
+    t0 = time.perf_counter()
+    st = oracle.run_shot(s, steps=1, precision="f64")
+    t1 = time.perf_counter()
+    # one step includes set-up (vp, damping profile); time the rest alone
+    state = dict(u=st["u"], u_prev=st["u_prev"], phi=st["phi"])
+    del st
+    n = 2
+    t2 = time.perf_counter()
+    oracle.run_shot(s, steps=n, precision="f64", state=state, n0=1)
+    per = (time.perf_counter() - t2) / n
+    steps = max(1, min(40, int(budget_s / max(per, 1e-3))))
+    t3 = time.perf_counter()
+    oracle.run_shot(s, steps=steps, precision="f64", state=state, n0=1)
+    dt = time.perf_counter() - t3
+    gpts = s.points * steps / dt / 1e9
+    return {"value": round(gpts, 5), "unit": "Gpoints/s", "cores": threads, "kind": "oracle",
+            "sample": f"float64 oracle, same {s.nx}x{s.ny}x{s.nz} w{s.w} grid and model, "
+                      f"{steps} steps after 1 set-up step ({t1 - t0:.1f} s incl. set-up), "
+                      f"{threads} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--n", type=int, default=512, help="grid extent per axis")
+    ap.add_argument("--w", type=int, default=20, help="damping layer width")
+    ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"])
+    ap.add_argument("--kernel", default="1,1,16,0",
+                    help="variant,rows_per_wave,waves_per_group,zchunk")
+    ap.add_argument("--roofline-steps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-copy", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "z-slab decomposition is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    from paper_2009_04619_amd import wave as W
+
+    log(f"[bench] building workload {args.n}^3 w{args.w}")
+    total = args.warmup + args.steps
+    shot = synth.config_c2(steps=total, n=args.n, w=args.w)
+    sh = W.shot_from_synth(shot, storage=args.storage, max_steps=total + args.roofline_steps)
+    k = [int(v) for v in args.kernel.split(",")]
+    sh.set_kernel(*k)
+    stream = sh.stream
+    log(f"[bench] warmup {args.warmup} steps")
+    sh.step(args.warmup)
+    sh.sync()
+
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record(stream)
+    sh.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1)
+    log(f"[bench] timed {args.steps} steps: {ms:.2f} ms (wall {wall * 1e3:.2f} ms)")
+    pts = shot.points
+    gpts = pts * args.steps / (ms / 1e3) / 1e9
+
+    # roofline of the sweep kernel: its own launches bracketed by HIP events
+    # on the stream it runs on
+    sh.set_timing(True)
+    sh.step(args.roofline_steps)
+    kms, launches = sh.read_timing()
+    sh.set_timing(False)
+    avg_ms = kms / max(launches, 1)
+    alg_bytes = sh.sweep_bytes()
+    achieved = alg_bytes / (avg_ms / 1e3) / 1e9
+    workload = f"{args.n}cube_w{args.w}_{args.storage}"
+    traffic = measured_traffic(workload, alg_bytes)
+    log(f"[bench] sweep kernel avg {avg_ms:.4f} ms over {launches} launches, "
+        f"{alg_bytes / pts:.2f} B/pt algorithmic -> {achieved:.0f} GB/s")
+    tr = sh.traces()
+    assert np.isfinite(tr).all()
+    sh.close()
+    del sh
+
+    copy_gbs = None if args.no_copy else copy_bandwidth(W, torch)
+    if copy_gbs:
+        log(f"[bench] stream copy {copy_gbs:.0f} GB/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (float64 oracle)")
+        cpu = cpu_baseline(synth.config_c2(steps=64, n=args.n, w=args.w), args.cpu_budget)
+
+    line = {
+        "metric": "Gpoints/s & % HBM roofline (plain vs batched/BF16); shots/s + p50/p99 latency",
+        "value": round(gpts, 3),
+        "unit": "Gpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.storage == "f32" else f"f32 math, {args.storage} storage",
+        "data": "synthetic (seeded layered velocity model, Ricker source)",
+        "config": {"workload": f"acoustic 25-pt leapfrog, {args.n}^3 grid incl. {args.w}-cell "
+                               f"damping layer, 1 source, {args.n} receivers",
+                   "grid": [args.n, args.n, args.n], "layer": args.w,
+                   "storage": args.storage, "kernel": args.kernel},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic / 1e9, 4),
+                     "kernel": "k_sweep_stream", "algorithmic_bytes_per_launch": alg_bytes,
+                     "avg_kernel_ms": round(avg_ms, 5)},
+        "copy_gbps": None if copy_gbs is None else round(copy_gbs, 1),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,231 @@
+/*
+ * wave.h -- C ABI of the MI355X (gfx950) acoustic wave-propagation library.
+ *
+ * The library time-steps the 3-D constant-density acoustic wave equation
+ * (paper Sec. III-A, Eq. 1) discretised with the 25-point radius-4
+ * 8th-order Laplacian (Eq. 3) and second-order leapfrog in time (Eq. 2),
+ * with a damping (PML) layer around the inner region (Sec. III-A, last
+ * paragraphs; Sec. III-B), point sources added after each sweep (Alg. 1)
+ * and receivers sampled after the source add.
+ *
+ * Conventions for every entry point
+ *  - Return value: 0 (WAVE_OK) or a negative wave_status.  No exception or
+ *    C++ type crosses this interface.  wave_last_error() gives a message for
+ *    the last failure on the calling thread.
+ *  - A HIP runtime failure inside a call returns WAVE_EDEVICE and marks the
+ *    context broken; every later call on it returns WAVE_ESTATE, except
+ *    wave_free.
+ *  - Arrays passed as host pointers are read or written during the call and
+ *    not retained.  Host arrays are [nz][ny][nx] with x fastest (Sec. IV,
+ *    one flat array with x innermost) unless stated otherwise.
+ *  - Grid indices (i, j, k) are (x, y, z), 0-based, and count the damping
+ *    layer: the total extent includes it, and the inner region is
+ *    [w, n - w) on every axis (Table III is reproduced by a 1000^3 total grid
+ *    with a 27-cell layer).
+ *  - Device memory is a caller-owned arena (one device allocation of at
+ *    least wave_bytes_required() bytes, e.g. a torch uint8 tensor).  The
+ *    library carves every device array from it, never frees it, and the
+ *    arena must outlive the context.  The context object itself is a small
+ *    host allocation owned by the library until wave_free.
+ *  - Work is enqueued on the HIP stream given to wave_alloc; calls that
+ *    return data to the host synchronise that stream first.
+ *  - One context must not be used from two threads at once.
+ */
+#ifndef WAVE_H
+#define WAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum wave_status {
+    WAVE_OK = 0,
+    WAVE_EINVAL = -1,    /* bad argument: sizes, indices, pointers, counts */
+    WAVE_ENOMEM = -2,    /* arena smaller than wave_bytes_required() */
+    WAVE_EUNSTABLE = -3, /* time step violates the stability bound */
+    WAVE_EDEVICE = -4,   /* a HIP call failed (context is now broken) */
+    WAVE_ESTATE = -5,    /* context broken by an earlier device failure */
+    WAVE_EBUDGET = -6    /* request can never fit the memory budget */
+} wave_status;
+
+/* Storage type of the wavefield u (arithmetic is always float32). */
+typedef enum wave_storage { WAVE_F32 = 0, WAVE_BF16 = 1, WAVE_F16 = 2 } wave_storage;
+
+/* wave_desc.flags */
+#define WAVE_DAMPING_OFF 1 /* eta := 0: Eq. 2 on every point */
+
+typedef struct wave_desc {
+    int32_t nx, ny, nz;  /* total extents incl. the layer, 1..32768, and
+                            one padded xy plane below 2 GiB               */
+    int32_t w;           /* layer width per face, 0 <= 2w <= min(nx,ny,nz) */
+    double dx, dy, dz;   /* grid spacing (m), > 0                          */
+    double dt;           /* time step (s), > 0                             */
+    int32_t storage;     /* wave_storage of u                              */
+    int32_t flags;       /* WAVE_DAMPING_OFF or 0                          */
+    double refl;         /* target reflection of the default eta profile,
+                            0 < refl < 1 (1e-3 is typical)                 */
+    int32_t max_src;     /* source table capacity, >= 0                    */
+    int32_t max_rec;     /* receiver table capacity, >= 0                  */
+    int32_t max_steps;   /* wavelet length and trace capacity (steps) >= 0 */
+    int32_t reserved;    /* must be 0                                      */
+} wave_desc;
+
+typedef struct wave_ctx wave_ctx;
+
+/* ---- host-only calls (no device work; usable without a GPU) ------------ */
+
+/* Bytes of device arena that wave_alloc needs for `d` (fields u^n, u^{n-1},
+ * vp, eta, phi in the padded device layout, plus source, receiver, trace
+ * and reduction tables).  Returns 0 if `d` is invalid. */
+size_t wave_bytes_required(const wave_desc *d);
+
+/* The 13 float32 stencil weights of Eq. 3 used by the kernels:
+ * out[0] = c_xyz, out[1..4] = c_x1..4, out[5..8] = c_y1..4,
+ * out[9..12] = c_z1..4.  Weights are the standard 8th-order central
+ * second-difference weights C_m / h^2 (the paper calls them discretisation
+ * parameters without values); c_xyz = C_0 (1/dx^2 + 1/dy^2 + 1/dz^2). */
+int wave_coefficients(const wave_desc *d, float out[13]);
+
+/* Stability number of the scheme for peak velocity vmax (m/s): the
+ * leapfrog scheme with Eq. 3 is stable when this is <= 1.  Returns a
+ * negative value for an invalid descriptor. */
+double wave_stability(const wave_desc *d, double vmax);
+
+/* The default damping profile used when wave_alloc gets no eta: quadratic
+ * in the depth into the layer on each axis, summed over axes, scaled by dt
+ * (eta = dt * d, dimensionless), zero in the inner region.  out is a host
+ * float array [nz][ny][nx]. */
+int wave_eta_default(const wave_desc *d, double vmax, float *out);
+
+/* ---- context lifetime -------------------------------------------------- */
+
+/* Create a simulation context (Alg. 1 initial state u^0 = u^{-1} = 0,
+ * phi = 0, step counter n = 0).
+ *   vel_host   velocity V (m/s), float [nz][ny][nx], finite and > 0.
+ *              vp = (V dt)^2 (the dt^2 V^2 factor of Eq. 2) is computed
+ *              from it in double and rounded once to float.
+ *   eta_host   damping eta >= 0 per point, float [nz][ny][nx], or NULL for
+ *              the default profile (wave_eta_default with vmax = max V).
+ *              Ignored with WAVE_DAMPING_OFF.
+ *   dev_arena  device pointer, 256-byte aligned, arena_bytes long.
+ *   hip_stream hipStream_t (NULL = the null stream).
+ * Errors: EINVAL (descriptor, pointers, alignment, non-finite input),
+ * ENOMEM (arena too small), EUNSTABLE (wave_stability > 1), EDEVICE. */
+int wave_alloc(const wave_desc *d, const float *vel_host, const float *eta_host,
+               void *dev_arena, size_t arena_bytes, void *hip_stream, wave_ctx **out);
+
+/* Release the context (host memory only; the arena stays the caller's).
+ * Synchronises the stream first.  NULL is accepted. */
+int wave_free(wave_ctx *ctx);
+
+/* ---- sources and receivers ---------------------------------------------- */
+
+/* Add a point source at (i, j, k) with wavelet samples w[n], n = 0 ..
+ * nsamples-1 (zero afterwards).  After the sweep of step n the library adds
+ * vp(s) * w[n] into u^{n+1}(s) (Alg. 1 source add, scaled per Eq. 2).
+ * Several sources at one cell are added in the order they were given.
+ * Errors: EINVAL (index outside the grid, nsamples > max_steps, table
+ * full). */
+int wave_inject(wave_ctx *ctx, int32_t i, int32_t j, int32_t k,
+                const float *samples_host, int32_t nsamples);
+
+/* Set the receiver list (replacing any earlier one) and clear the traces.
+ * After each step n the library records u^{n+1}(rec_r) (after the source
+ * add) as float64 into traces[t][r], t counting steps since this call.
+ * ijk_host is int32 [nrec][3] = (i, j, k).  Errors: EINVAL (index outside
+ * the grid, nrec > max_rec). */
+int wave_record(wave_ctx *ctx, const int32_t *ijk_host, int32_t nrec);
+
+/* ---- time stepping ------------------------------------------------------ */
+
+/* Enqueue n time steps (Alg. 1 loop body n times) on the context stream and
+ * return without waiting.  Each step: one sweep over every grid point
+ * (Eq. 2 in the inner region, the layer update elsewhere), then the source
+ * add, then the receiver sample, then the time levels rotate.
+ * Errors: EINVAL (n < 0, or receivers set and the trace buffer would
+ * overflow max_steps). */
+int wave_step(wave_ctx *ctx, int32_t n);
+
+/* Wait for all enqueued work of the context. */
+int wave_sync(wave_ctx *ctx);
+
+/* Number of steps taken so far (the time level n of u^n). */
+int64_t wave_step_count(const wave_ctx *ctx);
+
+/* ---- state access --------------------------------------------------------- */
+
+/* Field ids for wave_read_field / wave_write_field */
+#define WAVE_FIELD_U 0      /* u^n (current)                     */
+#define WAVE_FIELD_UPREV 1  /* u^{n-1}                           */
+#define WAVE_FIELD_PHI 2    /* phi^n (layer auxiliary field)     */
+#define WAVE_FIELD_VP 3     /* vp = (V dt)^2 (read only)         */
+#define WAVE_FIELD_ETA 4    /* eta (read only)                   */
+
+/* Copy a field to a host float array [nz][ny][nx] (16-bit storage is
+ * widened exactly).  Synchronises.  Errors: EINVAL. */
+int wave_read_field(wave_ctx *ctx, int32_t which, float *host_out);
+
+/* Overwrite u^n, u^{n-1} or phi^n from a host float array [nz][ny][nx]
+ * (rounded to nearest-even into 16-bit storage).  For restarts and tests.
+ * Synchronises.  Errors: EINVAL (read-only field, non-finite values). */
+int wave_write_field(wave_ctx *ctx, int32_t which, const float *host_in);
+
+/* Copy the traces recorded since wave_record: float64 [steps][nrec].
+ * *steps_out receives the number of recorded steps (host_out may be NULL to
+ * query it).  Synchronises. */
+int wave_read_traces(wave_ctx *ctx, double *host_out, int32_t *steps_out);
+
+/* Discrete energy of the current state in float64 on the device:
+ *   E = sum_p (u^n_p - u^{n-1}_p)^2 / vp_p - sum_p u^n_p (lap u^{n-1})_p
+ * with lap = Eq. 3 evaluated in float64.  With damping off and no source
+ * it is conserved by Eq. 2 up to the rounding of the stored fields; it is a
+ * check quantity, not part of the time step.  Deterministic (fixed
+ * reduction order).  Synchronises. */
+int wave_energy(wave_ctx *ctx, double *out);
+
+/* ---- kernel selection and timing ----------------------------------------- */
+
+/* Kernel variants for the sweep. */
+#define WAVE_KERNEL_DIRECT 0 /* one thread per point, all reads from memory */
+#define WAVE_KERNEL_STREAM 1 /* xy tile in LDS, z neighbours in registers,
+                                streamed along z (default)               */
+
+/* Select the sweep kernel and its tile: rows_per_wave (RY) and
+ * waves_per_group (NW) give a 64 x (RY*NW) xy tile; zchunk is the number of
+ * z planes one workgroup streams (0 = automatic).  Only compiled
+ * combinations are accepted (EINVAL otherwise): (RY, NW) in
+ * {(1,16), (1,8), (2,8), (2,16), (4,4)}; the default is (1,16).  Results do not depend on the
+ * choice: every variant evaluates each point with the same operations in
+ * the same order. */
+int wave_set_kernel(wave_ctx *ctx, int32_t variant, int32_t rows_per_wave,
+                    int32_t waves_per_group, int32_t zchunk);
+
+/* When on, wave_step brackets every sweep-kernel launch with HIP events on
+ * the context stream; wave_read_timing returns the summed kernel time (ms)
+ * and the launch count since timing was switched on, and synchronises. */
+int wave_set_timing(wave_ctx *ctx, int32_t on);
+int wave_read_timing(wave_ctx *ctx, double *ms_total, int64_t *launches);
+
+/* Algorithmic HBM bytes one sweep of this context moves: every array read
+ * or written once per point (16 bytes per inner point and 28 per layer
+ * point in float32 storage; u is 2 bytes per access with 16-bit storage). */
+double wave_sweep_bytes(const wave_ctx *ctx);
+
+/* Device-to-device copy of `bytes` (multiple of 16, both pointers 16-byte
+ * aligned) with a plain streaming kernel on `hip_stream`: the reference
+ * point for measured memory bandwidth.  Does not wait. */
+int wave_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+/* ---- diagnostics ----------------------------------------------------------- */
+
+const char *wave_strerror(int status);
+const char *wave_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WAVE_H */

@@ -1,0 +1,98 @@
+// wave_internal.h -- shared declarations between the host runtime and the
+// kernels of the wave library (not part of the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace wave {
+
+// Radius of the Eq. 3 stencil along each axis.
+constexpr int kR = 4;
+// Width of one wavefront along x: the x extent of every tile.
+constexpr int kTX = 64;
+
+// Padded device layout of every field (same for all arrays of a context):
+//   element (x, y, z) lives at  base + ((z + 4) * rows + (y + 4)) * pitch + x
+//   pitch = round_up(nx + 8, 64) elements, rows = ny + 8, planes = nz + 8.
+// x in [nx, pitch) of each row is zero: those cells are the +x ghosts of the
+// row and the -x ghosts of the next row (x = -4..-1 wrap into the previous
+// row's tail).  Rows y = -4..-1, ny..ny+3 and planes z = -4..-1, nz..nz+3 are
+// zero.  Ghost cells are never written, so the stencil needs no bounds tests.
+// `base` leaves kGuard zero elements before the first plane and after the
+// last so that the x-halo wrap of the first/last row stays inside.
+constexpr int64_t kGuard = 64;
+
+struct Layout {
+  int32_t nx, ny, nz;
+  int32_t pitch;        // elements per row
+  int64_t plane;        // elements per plane = (ny + 8) * pitch
+  int64_t origin;       // element index of (0, 0, 0) from the array start
+  int64_t elems;        // total elements of one array incl. guards
+};
+
+inline Layout make_layout(int32_t nx, int32_t ny, int32_t nz) {
+  Layout L;
+  L.nx = nx; L.ny = ny; L.nz = nz;
+  L.pitch = ((nx + 8 + 63) / 64) * 64;
+  L.plane = (int64_t)(ny + 8) * L.pitch;
+  L.origin = kGuard + 4 * L.plane + 4 * (int64_t)L.pitch;
+  L.elems = 2 * kGuard + (int64_t)(nz + 8) * L.plane;
+  return L;
+}
+
+// Everything one sweep kernel needs.  Pointers are element pointers already
+// offset to (0, 0, 0).
+struct SweepArgs {
+  const void* cur;      // u^n     (storage type)
+  void* nxt;            // u^{n-1} on entry, u^{n+1} on exit (storage type)
+  const float* vp;      // (V dt)^2
+  const float* eta;     // damping eta
+  float* phi;           // phi^n on entry, phi^{n+1} on exit
+  int32_t nx, ny, nz, w;
+  int32_t pitch;
+  int64_t plane;
+  float c[13];          // Eq. 3 weights (float32)
+  float q[3];           // 1 / (4 h_a^2)
+  int32_t damping;      // 0: Eq. 2 everywhere
+};
+
+struct InjectArgs {
+  void* u;              // u^{n+1} (storage type), offset to (0,0,0)
+  const float* vp;
+  int32_t nsrc;
+  const int64_t* src_off;     // element offsets of the sources
+  const float* wavelet;       // [max_src][max_steps]
+  int32_t max_steps;
+  int32_t step;               // time step index n (w[n] is added)
+  int32_t nrec;
+  const int64_t* rec_off;
+  double* traces;             // [max_steps][nrec] row `trace_row`
+  int32_t trace_row;
+};
+
+struct EnergyArgs {
+  const void* cur;      // u^n
+  const void* prev;     // u^{n-1}
+  const float* vp;
+  int32_t nx, ny, nz;
+  int32_t pitch;
+  int64_t plane;
+  double c[13];         // Eq. 3 weights in float64
+  double* partial;      // [nz*ny][2] (kinetic, potential) per row
+  double* result;       // [2]
+};
+
+// Kernel launchers (defined in wave_kernels.hip).  storage: 0 f32, 1 bf16,
+// 2 f16.  Return the hipError_t of the launch.
+hipError_t launch_sweep_direct(const SweepArgs& a, int storage, hipStream_t s);
+hipError_t launch_sweep_stream(const SweepArgs& a, int storage, int ry, int nw,
+                               int zchunk, hipStream_t s);
+bool stream_config_supported(int ry, int nw);
+int auto_zchunk(int nx, int ny, int nz, int ry, int nw);
+hipError_t launch_inject_record(const InjectArgs& a, int storage, hipStream_t s);
+hipError_t launch_energy(const EnergyArgs& a, int storage, hipStream_t s);
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+}  // namespace wave

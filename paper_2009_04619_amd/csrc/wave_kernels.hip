@@ -1,0 +1,582 @@
+// wave_kernels.hip -- gfx950 kernels of one time step of the 3-D acoustic
+// wave equation (paper Sec. III-A, Eq. 2-3; damping layer after Sec. III-B).
+//
+// Per-point arithmetic (identical in every sweep variant, so results do not
+// depend on tiling): float32, explicit fused multiply-adds only where written
+// (the library is built with -ffp-contract=off), correctly rounded division:
+//   lap = c_xyz * u
+//   lap = fma(c_am, u(+m) + u(-m), lap)      axis x, then y, then z; m = 1..4
+//   inner: u' = fma(vp, lap, fma(2, u, -u_prev))
+//   layer: a  = fma(-eta, eta, fma(2, eta, 2))
+//          u' = fma(vp, lap + phi, fma(a, u, -u_prev)) / fma(2, eta, 1)
+//          g  = ((eta(+x) - eta(-x)) * q_x) * (u(+x) - u(-x))
+//          g  = fma((eta(+y) - eta(-y)) * q_y, u(+y) - u(-y), g)
+//          g  = fma((eta(+z) - eta(-z)) * q_z, u(+z) - u(-z), g)
+//          phi' = (phi - g) / (1 + eta)
+// The layer form with eta = phi = 0 gives the inner form bit for bit, which
+// is the reduction of the damped update to Eq. 2.
+#include <type_traits>
+
+#include "wave_internal.h"
+
+namespace wave {
+namespace {
+
+// ---- wavefield storage types ------------------------------------------------
+struct StF32 {
+  using T = float;
+  static __device__ __forceinline__ float ld(const T* p, int64_t i) { return p[i]; }
+  static __device__ __forceinline__ void st(T* p, int64_t i, float v) { p[i] = v; }
+  static __device__ __forceinline__ float cvt(T v) { return v; }
+  static __device__ __forceinline__ T enc(float v) { return v; }
+  static __device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t boff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)boff, 0, 0));
+  }
+  static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t boff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)boff, 0, 0);
+  }
+};
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+struct StBF16 {
+  using T = uint16_t;
+  static __device__ __forceinline__ float ld(const T* p, int64_t i) {
+    return __uint_as_float((uint32_t)p[i] << 16);
+  }
+  static __device__ __forceinline__ void st(T* p, int64_t i, float v) { p[i] = f32_to_bf16_rne(v); }
+  static __device__ __forceinline__ float cvt(T v) { return __uint_as_float((uint32_t)v << 16); }
+  static __device__ __forceinline__ T enc(float v) { return f32_to_bf16_rne(v); }
+  static __device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t boff) {
+    return cvt((uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)boff, 0, 0));
+  }
+  static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t boff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b16(enc(v), r, (int)boff, 0, 0);
+  }
+};
+
+struct StF16 {
+  using T = _Float16;
+  static __device__ __forceinline__ float ld(const T* p, int64_t i) { return (float)p[i]; }
+  static __device__ __forceinline__ void st(T* p, int64_t i, float v) { p[i] = (_Float16)v; }
+  static __device__ __forceinline__ float cvt(T v) { return (float)v; }
+  static __device__ __forceinline__ T enc(float v) { return (_Float16)v; }
+  static __device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t boff) {
+    return cvt(__builtin_bit_cast(_Float16,
+                                  (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)boff, 0, 0)));
+  }
+  static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t boff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, enc(v)), r, (int)boff, 0, 0);
+  }
+};
+
+// ---- per-point update ---------------------------------------------------------
+__device__ __forceinline__ float upd_inner(float c, float pu, float vp, float lap) {
+  return __builtin_fmaf(vp, lap, __builtin_fmaf(2.0f, c, -pu));
+}
+
+__device__ __forceinline__ float upd_layer(float c, float pu, float vp, float lap, float e,
+                                           float ph) {
+  const float a = __builtin_fmaf(-e, e, __builtin_fmaf(2.0f, e, 2.0f));
+  const float num = __builtin_fmaf(vp, lap + ph, __builtin_fmaf(a, c, -pu));
+  return num / __builtin_fmaf(2.0f, e, 1.0f);
+}
+
+__device__ __forceinline__ float upd_phi(float ph, float e, float dex, float dux, float dey,
+                                         float duy, float dez, float duz, float qx, float qy,
+                                         float qz) {
+  float g = (dex * qx) * dux;
+  g = __builtin_fmaf(dey * qy, duy, g);
+  g = __builtin_fmaf(dez * qz, duz, g);
+  return (ph - g) / (1.0f + e);
+}
+
+__device__ __forceinline__ bool in_layer(const SweepArgs& a, int x, int y, int z) {
+  return x < a.w || x >= a.nx - a.w || y < a.w || y >= a.ny - a.w || z < a.w ||
+         z >= a.nz - a.w;
+}
+
+// ---- variant 0: one thread per point, every operand read from memory -------
+template <class S>
+__global__ __launch_bounds__(256) void k_sweep_direct(SweepArgs a) {
+  using T = typename S::T;
+  const int x = blockIdx.x * kTX + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= a.nx || y >= a.ny) return;
+  const T* u = static_cast<const T*>(a.cur);
+  T* un = static_cast<T*>(a.nxt);
+  const int64_t P = a.pitch, Q = a.plane;
+  const int64_t p = (int64_t)z * Q + (int64_t)y * P + x;
+  const float c = S::ld(u, p);
+  float lap = a.c[0] * c;
+#pragma unroll
+  for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(a.c[m], S::ld(u, p + m) + S::ld(u, p - m), lap);
+#pragma unroll
+  for (int m = 1; m <= kR; ++m)
+    lap = __builtin_fmaf(a.c[4 + m], S::ld(u, p + m * P) + S::ld(u, p - m * P), lap);
+#pragma unroll
+  for (int m = 1; m <= kR; ++m)
+    lap = __builtin_fmaf(a.c[8 + m], S::ld(u, p + m * Q) + S::ld(u, p - m * Q), lap);
+  const float pu = S::ld(un, p);
+  const float vp = a.vp[p];
+  float r;
+  if (a.damping && in_layer(a, x, y, z)) {
+    const float e = a.eta[p];
+    const float ph = a.phi[p];
+    r = upd_layer(c, pu, vp, lap, e, ph);
+    a.phi[p] = upd_phi(ph, e, a.eta[p + 1] - a.eta[p - 1], S::ld(u, p + 1) - S::ld(u, p - 1),
+                       a.eta[p + P] - a.eta[p - P], S::ld(u, p + P) - S::ld(u, p - P),
+                       a.eta[p + Q] - a.eta[p - Q], S::ld(u, p + Q) - S::ld(u, p - Q), a.q[0],
+                       a.q[1], a.q[2]);
+  } else {
+    r = upd_inner(c, pu, vp, lap);
+  }
+  S::st(un, p, r);
+}
+
+// ---- variant 1: 2.5-D streaming ------------------------------------------------
+// A workgroup of NW wavefronts owns a 64 x TY xy tile (TY = RY * NW; each
+// wavefront owns RY rows, one x column per lane) and streams it through the
+// planes [zb, ze) of one z chunk.  Per plane:
+//  * the 9 z-values u(z-4..z+4) of every owned column sit in registers (a
+//    10-slot queue, the 10th slot receives the prefetch of u(z+5));
+//  * the centre plane of the tile plus its 4-wide x and y halos is staged in
+//    LDS (double-buffered: one barrier per plane), from which the x and y
+//    neighbours are read;
+//  * u_prev, vp and the halo of plane z+1 are prefetched while plane z is
+//    computed.
+// The loop is unrolled by 10 so every queue/buffer index is a compile-time
+// constant (no register moves, no modulo).  Blocks are remapped so that
+// consecutive tiles (which share halos) run on the same XCD and its L2.
+// Buffer resource over memory starting at p (gfx9 family: stride 0, no range
+// limit, dword 3 = 0x00020000).  Built from a wave-uniform pointer it lives in
+// scalar registers; accesses then take an unsigned 32-bit byte offset per lane.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_at(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)0xffffffff,
+                                           0x00020000);
+}
+__device__ __forceinline__ float bld_f32(__amdgpu_buffer_rsrc_t r, uint32_t boff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)boff, 0, 0));
+}
+__device__ __forceinline__ void bst_f32(__amdgpu_buffer_rsrc_t r, uint32_t boff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)boff, 0, 0);
+}
+
+template <class S, int RY, int NW>
+__global__ __launch_bounds__(64 * NW) void k_sweep_stream(SweepArgs a, int tiles_x, int tiles_y,
+                                                          int zchunk) {
+  using T = typename S::T;
+  constexpr int TY = RY * NW;
+  constexpr int LW = kTX + 2 * kR;   // LDS row length
+  constexpr int LR = TY + 2 * kR;    // LDS rows
+  constexpr int NT = 64 * NW;
+  constexpr int NYH = 2 * kR * kTX;  // y-halo elements per plane
+  constexpr int NHALO = NYH + 2 * kR * TY;
+  constexpr int HPT = (NHALO + NT - 1) / NT;
+  constexpr int LSZ = LR * LW + 64;  // + a dump row for idle halo lanes
+  constexpr uint32_t ES = sizeof(T);
+  __shared__ float sm[2][LSZ];
+
+  // XCD-aware tile order: dispatch sends block b to XCD b % 8; give each XCD
+  // a contiguous range of logical tiles.
+  const int nb = gridDim.x, bid = blockIdx.x;
+  const int per = nb >> 3, rem = nb & 7, xcd = bid & 7, slot = bid >> 3;
+  const int logical = (xcd < rem) ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+  const int tx = logical % tiles_x;
+  const int t2 = logical / tiles_x;
+  const int ty = t2 % tiles_y;
+  const int ch = t2 / tiles_y;
+  const int x0 = tx * kTX, y0 = ty * TY;
+  const int zb = ch * zchunk;
+  const int ze = min(zb + zchunk, a.nz);
+  if (zb >= ze) return;
+
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int x = x0 + lane;
+  const bool xin = x < a.nx;
+  const int P = a.pitch;
+  const int64_t Q = a.plane;
+  // Addresses: a uniform per-plane base at (x = 0, y = -4, z) plus an unsigned
+  // 32-bit in-plane byte offset ((y + 4) * pitch + x) * size per lane.  Every
+  // accessed cell has y >= -4, and x < 0 only on rows y >= 0, so the offset
+  // is never negative.  Rows past the grid are clamped to the last ghost row
+  // y = ny + 3 (all zero), which keeps every load in bounds and branch-free;
+  // such rows store zero there.
+  const int64_t b4 = 4 * (int64_t)P;
+  const T* u = static_cast<const T*>(a.cur) - b4;
+  T* un = static_cast<T*>(a.nxt) - b4;
+  const float* vpa = a.vp - b4;
+  const int ylast = a.ny + kR - 1;
+
+  uint32_t ro[RY];   // in-plane element offset of (x, y_r)
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const int y = min(y0 + wv * RY + r, ylast);
+    ro[r] = (uint32_t)((y + kR) * P + x);
+  }
+
+  // halo bookkeeping: LDS index and in-plane element offset
+  int hl[HPT];
+  uint32_t ho[HPT];
+#pragma unroll
+  for (int k = 0; k < HPT; ++k) {
+    const int h = threadIdx.x + k * NT;
+    int rl, cl, gy, gx;
+    if (h < NYH) {
+      const int hr = h / kTX, hc = h % kTX;
+      rl = (hr < kR) ? hr : TY + hr;
+      gy = (hr < kR) ? y0 - kR + hr : y0 + TY + (hr - kR);
+      cl = kR + hc;
+      gx = x0 + hc;
+    } else if (h < NHALO) {
+      const int kk = h - NYH;
+      const int row = kk / (2 * kR), cc = kk % (2 * kR);
+      rl = kR + row;
+      gy = y0 + row;
+      cl = (cc < kR) ? cc : kTX + cc;
+      gx = (cc < kR) ? x0 - kR + cc : x0 + kTX + (cc - kR);
+    } else {
+      rl = LR;  // dump row
+      cl = lane;
+      gy = ylast;
+      gx = x0 + lane;
+    }
+    gy = min(gy, ylast);
+    hl[k] = rl * LW + cl;
+    ho[k] = (uint32_t)((gy + kR) * P + gx);
+  }
+
+  float q[10][RY];
+  float pv[2][RY], vv[2][RY];
+  float hh[2][HPT];
+
+  // prologue: planes zb-4 .. zb+4 into queue slots 0..8; plane zb operands
+#pragma unroll
+  for (int j = 0; j < 2 * kR + 1; ++j) {
+    const auto ru = rsrc_at(u + (int64_t)(zb - kR + j) * Q);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) q[j][r] = S::bld(ru, ro[r] * ES);
+  }
+  {
+    const auto ru = rsrc_at(u + (int64_t)zb * Q);
+    const auto rp = rsrc_at(un + (int64_t)zb * Q);
+    const auto rv = rsrc_at(vpa + (int64_t)zb * Q);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      pv[0][r] = S::bld(rp, ro[r] * ES);
+      vv[0][r] = bld_f32(rv, ro[r] * 4u);
+    }
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) hh[0][k] = S::bld(ru, ho[k] * ES);
+  }
+
+  const bool damp = a.damping != 0;
+  const float c0 = a.c[0];
+  const bool xl = x < a.w || x >= a.nx - a.w;
+  const uint32_t P4 = (uint32_t)P * 4u;
+
+  auto body = [&](auto SC, const int z) {
+    constexpr int Sl = decltype(SC)::value;
+    constexpr int B = Sl & 1;        // buffers of this plane
+    constexpr int NB = B ^ 1;        // buffers of the next plane
+    // prefetch plane z+1 operands and u(z+5), unconditionally so that the
+    // number of loads in flight is the same on every path (the last plane
+    // clamps to ghost planes, which stay inside the allocation)
+    {
+      const int z1 = z + 1;                   // <= nz: a ghost plane at most
+      const int z5 = min(z + 1 + kR, a.nz + kR - 1);
+      const auto ru1 = rsrc_at(u + (int64_t)z1 * Q);
+      const auto ru5 = rsrc_at(u + (int64_t)z5 * Q);
+      const auto rp1 = rsrc_at(un + (int64_t)z1 * Q);
+      const auto rv1 = rsrc_at(vpa + (int64_t)z1 * Q);
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        q[(Sl + 9) % 10][r] = S::bld(ru5, ro[r] * ES);
+        pv[NB][r] = S::bld(rp1, ro[r] * ES);
+        vv[NB][r] = bld_f32(rv1, ro[r] * 4u);
+      }
+#pragma unroll
+      for (int k = 0; k < HPT; ++k) hh[NB][k] = S::bld(ru1, ho[k] * ES);
+    }
+    // stage the centre plane and its halo
+    float* s = sm[B];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) s[(kR + wv * RY + r) * LW + kR + lane] = q[(Sl + kR) % 10][r];
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) s[hl[k]] = hh[B][k];
+    __syncthreads();
+
+    const bool zl = z < a.w || z >= a.nz - a.w;
+    const auto rn = rsrc_at(un + (int64_t)z * Q);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int y = y0 + wv * RY + r;
+      const bool yin = y < a.ny;
+      const float* row = s + (kR + wv * RY + r) * LW + kR + lane;
+      const float c = q[(Sl + kR) % 10][r];
+      float lap = c0 * c;
+#pragma unroll
+      for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(a.c[m], row[m] + row[-m], lap);
+#pragma unroll
+      for (int m = 1; m <= kR; ++m)
+        lap = __builtin_fmaf(a.c[4 + m], row[m * LW] + row[-m * LW], lap);
+#pragma unroll
+      for (int m = 1; m <= kR; ++m)
+        lap = __builtin_fmaf(a.c[8 + m], q[(Sl + kR + m) % 10][r] + q[(Sl + kR - m) % 10][r], lap);
+      const float pu = pv[B][r];
+      const float vp = vv[B][r];
+      const bool lay = damp && xin && yin && (zl || y < a.w || y >= a.ny - a.w || xl);
+      float res;
+      if (lay) {
+        const float* ez = a.eta - b4 + (int64_t)z * Q;
+        const auto re = rsrc_at(ez);
+        const auto rem1 = rsrc_at(ez - Q);
+        const auto rep1 = rsrc_at(ez + Q);
+        const auto rph = rsrc_at(a.phi - b4 + (int64_t)z * Q);
+        const uint32_t o = ro[r] * 4u;
+        const float e = bld_f32(re, o);
+        const float ph = bld_f32(rph, o);
+        res = upd_layer(c, pu, vp, lap, e, ph);
+        bst_f32(rph, o,
+                upd_phi(ph, e, bld_f32(re, o + 4u) - bld_f32(re, o - 4u), row[1] - row[-1],
+                        bld_f32(re, o + P4) - bld_f32(re, o - P4), row[LW] - row[-LW],
+                        bld_f32(rep1, o) - bld_f32(rem1, o),
+                        q[(Sl + kR + 1) % 10][r] - q[(Sl + kR - 1) % 10][r], a.q[0], a.q[1],
+                        a.q[2]));
+      } else {
+        res = upd_inner(c, pu, vp, lap);
+      }
+      // lanes past the grid (x >= nx, or a row clamped to the ghost row
+      // ny + 3) write zero into zero ghost cells: no branch around the store
+      S::bst(rn, ro[r] * ES, (xin && yin) ? res : 0.0f);
+    }
+  };
+
+  using std::integral_constant;
+  for (int z = zb; z < ze; z += 10) {
+    body(integral_constant<int, 0>{}, z);
+    if (z + 1 >= ze) break;
+    body(integral_constant<int, 1>{}, z + 1);
+    if (z + 2 >= ze) break;
+    body(integral_constant<int, 2>{}, z + 2);
+    if (z + 3 >= ze) break;
+    body(integral_constant<int, 3>{}, z + 3);
+    if (z + 4 >= ze) break;
+    body(integral_constant<int, 4>{}, z + 4);
+    if (z + 5 >= ze) break;
+    body(integral_constant<int, 5>{}, z + 5);
+    if (z + 6 >= ze) break;
+    body(integral_constant<int, 6>{}, z + 6);
+    if (z + 7 >= ze) break;
+    body(integral_constant<int, 7>{}, z + 7);
+    if (z + 8 >= ze) break;
+    body(integral_constant<int, 8>{}, z + 8);
+    if (z + 9 >= ze) break;
+    body(integral_constant<int, 9>{}, z + 9);
+  }
+}
+
+// ---- source add and receiver sample (after the sweep, Alg. 1) --------------
+template <class S>
+__global__ __launch_bounds__(256) void k_inject_record(InjectArgs a) {
+  using T = typename S::T;
+  T* u = static_cast<T*>(a.u);
+  if (threadIdx.x == 0) {
+    // sequential so that several sources on one cell add in list order
+    for (int s = 0; s < a.nsrc; ++s) {
+      const int64_t p = a.src_off[s];
+      const float wv = (a.step < a.max_steps) ? a.wavelet[(int64_t)s * a.max_steps + a.step] : 0.0f;
+      S::st(u, p, __builtin_fmaf(a.vp[p], wv, S::ld(u, p)));
+    }
+  }
+  __syncthreads();
+  if (a.traces) {
+    double* row = a.traces + (int64_t)a.trace_row * a.nrec;
+    for (int r = threadIdx.x; r < a.nrec; r += blockDim.x) row[r] = (double)S::ld(u, a.rec_off[r]);
+  }
+}
+
+// ---- float64 energy (check quantity) -----------------------------------------
+template <class S>
+__global__ __launch_bounds__(256) void k_energy_rows(EnergyArgs a) {
+  using T = typename S::T;
+  const int y = blockIdx.x, z = blockIdx.y;
+  const T* un = static_cast<const T*>(a.cur);
+  const T* u = static_cast<const T*>(a.prev);
+  const int64_t P = a.pitch, Q = a.plane;
+  double kin = 0.0, pot = 0.0;
+  for (int x = threadIdx.x; x < a.nx; x += blockDim.x) {
+    const int64_t p = (int64_t)z * Q + (int64_t)y * P + x;
+    const double vn = S::ld(un, p), v0 = S::ld(u, p);
+    const double d = vn - v0;
+    kin += d * d / (double)a.vp[p];
+    double L = a.c[0] * v0;
+    for (int m = 1; m <= kR; ++m) {
+      L += a.c[m] * ((double)S::ld(u, p + m) + (double)S::ld(u, p - m));
+      L += a.c[4 + m] * ((double)S::ld(u, p + m * P) + (double)S::ld(u, p - m * P));
+      L += a.c[8 + m] * ((double)S::ld(u, p + m * Q) + (double)S::ld(u, p - m * Q));
+    }
+    pot += vn * L;
+  }
+  __shared__ double sk[256], sp[256];
+  sk[threadIdx.x] = kin;
+  sp[threadIdx.x] = pot;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sk[threadIdx.x] += sk[threadIdx.x + h];
+      sp[threadIdx.x] += sp[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int64_t row = (int64_t)z * a.ny + y;
+    a.partial[2 * row] = sk[0];
+    a.partial[2 * row + 1] = sp[0];
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_energy_final(double* partial, int64_t nrows,
+                                                       double* result) {
+  __shared__ double sk[1024], sp[1024];
+  double kin = 0.0, pot = 0.0;
+  for (int64_t r = threadIdx.x; r < nrows; r += blockDim.x) {
+    kin += partial[2 * r];
+    pot += partial[2 * r + 1];
+  }
+  sk[threadIdx.x] = kin;
+  sp[threadIdx.x] = pot;
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sk[threadIdx.x] += sk[threadIdx.x + h];
+      sp[threadIdx.x] += sp[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    result[0] = sk[0];
+    result[1] = sp[0];
+  }
+}
+
+// ---- plain copy (bandwidth reference) -------------------------------------------
+__global__ __launch_bounds__(256) void k_stream_copy(const float4* __restrict__ s,
+                                                     float4* __restrict__ d, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) d[i] = s[i];
+}
+
+template <class S>
+hipError_t sweep_direct_t(const SweepArgs& a, hipStream_t st) {
+  dim3 block(kTX, 4, 1);
+  dim3 grid((a.nx + kTX - 1) / kTX, (a.ny + 3) / 4, a.nz);
+  hipLaunchKernelGGL(k_sweep_direct<S>, grid, block, 0, st, a);
+  return hipGetLastError();
+}
+
+template <class S, int RY, int NW>
+hipError_t sweep_stream_t(const SweepArgs& a, int zchunk, hipStream_t st) {
+  constexpr int TY = RY * NW;
+  const int tiles_x = (a.nx + kTX - 1) / kTX;
+  const int tiles_y = (a.ny + TY - 1) / TY;
+  const int chunks = (a.nz + zchunk - 1) / zchunk;
+  const int64_t blocks = (int64_t)tiles_x * tiles_y * chunks;
+  if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_sweep_stream<S, RY, NW>), dim3((unsigned)blocks), dim3(64 * NW), 0, st, a,
+                     tiles_x, tiles_y, zchunk);
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t sweep_stream_s(const SweepArgs& a, int ry, int nw, int zchunk, hipStream_t st) {
+  if (ry == 1 && nw == 16) return sweep_stream_t<S, 1, 16>(a, zchunk, st);
+  if (ry == 1 && nw == 8) return sweep_stream_t<S, 1, 8>(a, zchunk, st);
+  if (ry == 2 && nw == 8) return sweep_stream_t<S, 2, 8>(a, zchunk, st);
+  if (ry == 2 && nw == 16) return sweep_stream_t<S, 2, 16>(a, zchunk, st);
+  if (ry == 4 && nw == 4) return sweep_stream_t<S, 4, 4>(a, zchunk, st);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool stream_config_supported(int ry, int nw) {
+  return (ry == 1 && nw == 16) || (ry == 1 && nw == 8) || (ry == 2 && nw == 8) ||
+         (ry == 2 && nw == 16) || (ry == 4 && nw == 4);
+}
+
+int auto_zchunk(int nx, int ny, int nz, int ry, int nw) {
+  // enough workgroups to give every CU several (256 CUs), but chunks long
+  // enough that the 8-plane queue warm-up stays a small overhead
+  const int64_t tiles = (int64_t)((nx + kTX - 1) / kTX) * ((ny + ry * nw - 1) / (ry * nw));
+  int64_t chunks = (2048 + tiles - 1) / tiles;
+  if (chunks < 1) chunks = 1;
+  int zc = (int)((nz + chunks - 1) / chunks);
+  const int minz = nz < 32 ? nz : 32;
+  if (zc < minz) zc = minz;
+  return zc;
+}
+
+hipError_t launch_sweep_direct(const SweepArgs& a, int storage, hipStream_t s) {
+  switch (storage) {
+    case 0: return sweep_direct_t<StF32>(a, s);
+    case 1: return sweep_direct_t<StBF16>(a, s);
+    case 2: return sweep_direct_t<StF16>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep_stream(const SweepArgs& a, int storage, int ry, int nw, int zchunk,
+                               hipStream_t s) {
+  if (zchunk <= 0) return hipErrorInvalidValue;
+  switch (storage) {
+    case 0: return sweep_stream_s<StF32>(a, ry, nw, zchunk, s);
+    case 1: return sweep_stream_s<StBF16>(a, ry, nw, zchunk, s);
+    case 2: return sweep_stream_s<StF16>(a, ry, nw, zchunk, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_inject_record(const InjectArgs& a, int storage, hipStream_t s) {
+  switch (storage) {
+    case 0: hipLaunchKernelGGL(k_inject_record<StF32>, dim3(1), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_inject_record<StBF16>, dim3(1), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_inject_record<StF16>, dim3(1), dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_energy(const EnergyArgs& a, int storage, hipStream_t s) {
+  dim3 grid(a.ny, a.nz);
+  switch (storage) {
+    case 0: hipLaunchKernelGGL(k_energy_rows<StF32>, grid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_energy_rows<StBF16>, grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_energy_rows<StF16>, grid, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(1024), 0, s, a.partial,
+                     (int64_t)a.ny * a.nz, a.result);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const int64_t n = (int64_t)(bytes / 16);
+  if (n == 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 256 * 16) blocks = 256 * 16;
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, s,
+                     static_cast<const float4*>(src), static_cast<float4*>(dst), n);
+  return hipGetLastError();
+}
+
+}  // namespace wave

@@ -1,0 +1,710 @@
+// wave_runtime.hip -- host side of the C ABI declared in include/wave.h:
+// argument checking, arena layout, set-up of vp and eta, step enqueueing,
+// state transfers and timing.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "wave.h"
+#include "wave_internal.h"
+
+using wave::Layout;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+// Eq. 3 weights: standard 8th-order central second-difference weights.
+constexpr double kW0 = -205.0 / 72.0;
+constexpr double kWm[4] = {8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int storage_bytes(int32_t storage) { return storage == WAVE_F32 ? 4 : 2; }
+
+bool desc_ok(const wave_desc* d, std::string* why) {
+  auto bad = [&](const char* m) {
+    if (why) *why = m;
+    return false;
+  };
+  if (!d) return bad("descriptor is NULL");
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1) return bad("extents must be >= 1");
+  if (d->nx > 32768 || d->ny > 32768 || d->nz > 32768) return bad("extent above 32768");
+  {
+    // in-plane byte offsets are unsigned 32-bit in the kernels
+    const Layout L = wave::make_layout(d->nx, d->ny, d->nz);
+    if ((int64_t)L.plane * 4 > 0x7fffffffLL) return bad("one z plane exceeds 2 GiB");
+  }
+  if (d->w < 0 || 2 * (int64_t)d->w > std::min({d->nx, d->ny, d->nz}))
+    return bad("layer width must satisfy 0 <= 2w <= min extent");
+  if (!(d->dx > 0 && d->dy > 0 && d->dz > 0) || !isfinite(d->dx) || !isfinite(d->dy) ||
+      !isfinite(d->dz))
+    return bad("grid spacing must be finite and > 0");
+  if (!(d->dt > 0) || !isfinite(d->dt)) return bad("dt must be finite and > 0");
+  if (d->storage != WAVE_F32 && d->storage != WAVE_BF16 && d->storage != WAVE_F16)
+    return bad("unknown storage type");
+  if (d->flags & ~WAVE_DAMPING_OFF) return bad("unknown flags");
+  if (!(d->flags & WAVE_DAMPING_OFF) && d->w > 0 && !(d->refl > 0 && d->refl < 1))
+    return bad("refl must be in (0, 1)");
+  if (d->max_src < 0 || d->max_rec < 0 || d->max_steps < 0) return bad("negative capacity");
+  if (d->reserved != 0) return bad("reserved must be 0");
+  return true;
+}
+
+bool damping_on(const wave_desc* d) { return !(d->flags & WAVE_DAMPING_OFF) && d->w > 0; }
+
+struct ArenaPlan {
+  size_t u[2], vp, eta, phi, src_off, wavelet, rec_off, traces, partial, eres, total;
+};
+
+ArenaPlan plan_arena(const wave_desc* d) {
+  const Layout L = wave::make_layout(d->nx, d->ny, d->nz);
+  ArenaPlan a;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    off = align_up(off, 256);
+    size_t o = off;
+    off += bytes;
+    return o;
+  };
+  const size_t es = storage_bytes(d->storage);
+  a.u[0] = take((size_t)L.elems * es);
+  a.u[1] = take((size_t)L.elems * es);
+  a.vp = take((size_t)L.elems * 4);
+  const bool damp = damping_on(d);
+  a.eta = damp ? take((size_t)L.elems * 4) : (size_t)-1;
+  a.phi = damp ? take((size_t)L.elems * 4) : (size_t)-1;
+  a.src_off = take((size_t)std::max(d->max_src, 1) * 8);
+  a.wavelet = take((size_t)std::max(d->max_src, 1) * std::max(d->max_steps, 1) * 4);
+  a.rec_off = take((size_t)std::max(d->max_rec, 1) * 8);
+  a.traces = take((size_t)std::max(d->max_rec, 1) * std::max(d->max_steps, 1) * 8);
+  a.partial = take((size_t)d->ny * d->nz * 2 * 8);
+  a.eres = take(2 * 8);
+  a.total = align_up(off, 256);
+  return a;
+}
+
+void coefficients64(const wave_desc* d, double c[13]) {
+  const double ix = 1.0 / (d->dx * d->dx), iy = 1.0 / (d->dy * d->dy), iz = 1.0 / (d->dz * d->dz);
+  c[0] = kW0 * (ix + iy + iz);
+  for (int m = 0; m < 4; ++m) {
+    c[1 + m] = kWm[m] / (d->dx * d->dx);
+    c[5 + m] = kWm[m] / (d->dy * d->dy);
+    c[9 + m] = kWm[m] / (d->dz * d->dz);
+  }
+}
+
+// Depth into the layer (cells) of index i on an axis of extent n.
+double depth_cells(int i, int n, int w) {
+  if (i < w) return (double)(w - i);
+  if (i > n - 1 - w) return (double)(i - (n - 1 - w));
+  return 0.0;
+}
+
+// One z plane of the default eta profile (float [ny][nx]).
+void eta_plane(const wave_desc* d, double vmax, int k, float* out) {
+  const double h[3] = {d->dx, d->dy, d->dz};
+  double d0[3];
+  for (int a = 0; a < 3; ++a) d0[a] = 3.0 * vmax * log(1.0 / d->refl) / (2.0 * ((double)d->w * h[a]));
+  const double cz = depth_cells(k, d->nz, d->w);
+  for (int j = 0; j < d->ny; ++j) {
+    const double cy = depth_cells(j, d->ny, d->w);
+    for (int i = 0; i < d->nx; ++i) {
+      const double cx = depth_cells(i, d->nx, d->w);
+      const double cells[3] = {cx, cy, cz};
+      double s = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        if (cells[a] > 0.0) {
+          const double r = cells[a] / (double)d->w;
+          s += d0[a] * r * r;
+        }
+      }
+      out[(size_t)j * d->nx + i] = (float)(d->dt * s);
+    }
+  }
+}
+
+uint16_t host_bf16(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+float host_from_bf16(uint16_t b) {
+  uint32_t u = (uint32_t)b << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+
+}  // namespace
+
+struct wave_ctx {
+  wave_desc d;
+  Layout L;
+  ArenaPlan plan;
+  hipStream_t stream;
+  char* arena;
+  int es;                 // bytes per u element
+  int cur;                // index of u^n among the two u buffers
+  int64_t step;           // time level n
+  bool broken;
+  bool damp;
+  float c[13];
+  float q[3];
+  double c64[13];
+  int nsrc, nrec, trace_count;
+  int variant, ry, nw, zchunk;
+  bool timing;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  size_t events_used;
+  double timing_ms;
+  int64_t timing_launches;
+
+  char* at(size_t off) const { return arena + off; }
+  char* u_base(int idx) const { return at(plan.u[idx]); }
+  void* u_origin(int idx) const { return u_base(idx) + (size_t)L.origin * es; }
+  float* f_origin(size_t off) const {
+    return off == (size_t)-1 ? nullptr : reinterpret_cast<float*>(at(off)) + L.origin;
+  }
+};
+
+namespace {
+
+int dev_fail(wave_ctx* c, hipError_t e, const char* what) {
+  if (c) c->broken = true;
+  return fail(WAVE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define CHECK_CTX(c)                                                       \
+  do {                                                                     \
+    if (!(c)) return fail(WAVE_EINVAL, "context is NULL");                 \
+    if ((c)->broken) return fail(WAVE_ESTATE, "context broken by an earlier device error"); \
+  } while (0)
+
+#define HIPCHK(c, expr, what)                     \
+  do {                                            \
+    hipError_t _e = (expr);                       \
+    if (_e != hipSuccess) return dev_fail((c), _e, (what)); \
+  } while (0)
+
+// Copy a compact host plane sequence into a padded device array.
+int upload_plane(wave_ctx* c, char* dev_base, int esz, int k, const void* host_plane) {
+  const Layout& L = c->L;
+  char* dst = dev_base + ((size_t)L.origin + (size_t)k * L.plane) * esz;
+  HIPCHK(c,
+         hipMemcpy2DAsync(dst, (size_t)L.pitch * esz, host_plane, (size_t)L.nx * esz,
+                          (size_t)L.nx * esz, L.ny, hipMemcpyHostToDevice, c->stream),
+         "hipMemcpy2DAsync H2D");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  return WAVE_OK;
+}
+
+int download_plane(wave_ctx* c, const char* dev_base, int esz, int k, void* host_plane) {
+  const Layout& L = c->L;
+  const char* src = dev_base + ((size_t)L.origin + (size_t)k * L.plane) * esz;
+  HIPCHK(c,
+         hipMemcpy2DAsync(host_plane, (size_t)L.nx * esz, src, (size_t)L.pitch * esz,
+                          (size_t)L.nx * esz, L.ny, hipMemcpyDeviceToHost, c->stream),
+         "hipMemcpy2DAsync D2H");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  return WAVE_OK;
+}
+
+// Upload a float field into a u buffer, rounding to the storage format.
+int upload_u(wave_ctx* c, int idx, const float* host) {
+  const size_t pn = (size_t)c->L.nx * c->L.ny;
+  std::vector<uint16_t> tmp;
+  if (c->es == 2) tmp.resize(pn);
+  for (int k = 0; k < c->L.nz; ++k) {
+    const float* src = host + (size_t)k * pn;
+    const void* plane = src;
+    if (c->d.storage == WAVE_BF16) {
+      for (size_t p = 0; p < pn; ++p) tmp[p] = host_bf16(src[p]);
+      plane = tmp.data();
+    } else if (c->d.storage == WAVE_F16) {
+      for (size_t p = 0; p < pn; ++p) {
+        _Float16 h = (_Float16)src[p];
+        memcpy(&tmp[p], &h, 2);
+      }
+      plane = tmp.data();
+    }
+    int rc = upload_plane(c, c->u_base(idx), c->es, k, plane);
+    if (rc) return rc;
+  }
+  return WAVE_OK;
+}
+
+int download_u(wave_ctx* c, int idx, float* host) {
+  const size_t pn = (size_t)c->L.nx * c->L.ny;
+  std::vector<uint16_t> tmp;
+  if (c->es == 2) tmp.resize(pn);
+  for (int k = 0; k < c->L.nz; ++k) {
+    float* dst = host + (size_t)k * pn;
+    int rc = download_plane(c, c->u_base(idx), c->es, k, c->es == 4 ? (void*)dst : (void*)tmp.data());
+    if (rc) return rc;
+    if (c->d.storage == WAVE_BF16) {
+      for (size_t p = 0; p < pn; ++p) dst[p] = host_from_bf16(tmp[p]);
+    } else if (c->d.storage == WAVE_F16) {
+      for (size_t p = 0; p < pn; ++p) {
+        _Float16 h;
+        memcpy(&h, &tmp[p], 2);
+        dst[p] = (float)h;
+      }
+    }
+  }
+  return WAVE_OK;
+}
+
+int64_t offset_of(const wave_ctx* c, int i, int j, int k) {
+  return (int64_t)k * c->L.plane + (int64_t)j * c->L.pitch + i;
+}
+
+bool in_grid(const wave_ctx* c, int i, int j, int k) {
+  return i >= 0 && i < c->d.nx && j >= 0 && j < c->d.ny && k >= 0 && k < c->d.nz;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t wave_bytes_required(const wave_desc* d) {
+  std::string why;
+  if (!desc_ok(d, &why)) {
+    g_last_error = why;
+    return 0;
+  }
+  return plan_arena(d).total;
+}
+
+int wave_coefficients(const wave_desc* d, float out[13]) {
+  std::string why;
+  if (!desc_ok(d, &why)) return fail(WAVE_EINVAL, why);
+  if (!out) return fail(WAVE_EINVAL, "out is NULL");
+  double c[13];
+  coefficients64(d, c);
+  for (int m = 0; m < 13; ++m) out[m] = (float)c[m];
+  return WAVE_OK;
+}
+
+double wave_stability(const wave_desc* d, double vmax) {
+  std::string why;
+  if (!desc_ok(d, &why) || !(vmax > 0) || !isfinite(vmax)) {
+    g_last_error = why.empty() ? "vmax must be finite and > 0" : why;
+    return -1.0;
+  }
+  // symbol of Eq. 3 at the Nyquist wavenumber, per unit h^-2
+  double s = kW0;
+  for (int m = 0; m < 4; ++m) s += 2.0 * kWm[m] * (((m + 1) & 1) ? -1.0 : 1.0);
+  s = fabs(s);
+  const double k = s / (d->dx * d->dx) + s / (d->dy * d->dy) + s / (d->dz * d->dz);
+  return vmax * d->dt * sqrt(k) / 2.0;
+}
+
+int wave_eta_default(const wave_desc* d, double vmax, float* out) {
+  std::string why;
+  if (!desc_ok(d, &why)) return fail(WAVE_EINVAL, why);
+  if (!out || !(vmax > 0) || !isfinite(vmax)) return fail(WAVE_EINVAL, "bad vmax or out");
+  const size_t pn = (size_t)d->nx * d->ny;
+  if (d->w == 0) {
+    memset(out, 0, pn * d->nz * sizeof(float));
+    return WAVE_OK;
+  }
+  for (int k = 0; k < d->nz; ++k) eta_plane(d, vmax, k, out + (size_t)k * pn);
+  return WAVE_OK;
+}
+
+int wave_alloc(const wave_desc* d, const float* vel, const float* eta, void* dev_arena,
+               size_t arena_bytes, void* hip_stream, wave_ctx** out) {
+  std::string why;
+  if (!out) return fail(WAVE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!desc_ok(d, &why)) return fail(WAVE_EINVAL, why);
+  if (!vel) return fail(WAVE_EINVAL, "velocity is NULL");
+  if (!dev_arena || ((uintptr_t)dev_arena & 255)) return fail(WAVE_EINVAL, "arena NULL or not 256-byte aligned");
+  const ArenaPlan plan = plan_arena(d);
+  if (arena_bytes < plan.total)
+    return fail(WAVE_ENOMEM, "arena of " + std::to_string(arena_bytes) + " bytes < required " +
+                                 std::to_string(plan.total));
+  const size_t n = (size_t)d->nx * d->ny * d->nz;
+  double vmax = 0.0;
+  for (size_t p = 0; p < n; ++p) {
+    const float v = vel[p];
+    if (!(v > 0.0f) || !isfinite(v)) return fail(WAVE_EINVAL, "velocity must be finite and > 0");
+    vmax = std::max(vmax, (double)v);
+  }
+  const bool damp = damping_on(d);
+  if (damp && eta) {
+    for (size_t p = 0; p < n; ++p)
+      if (!(eta[p] >= 0.0f) || !isfinite(eta[p])) return fail(WAVE_EINVAL, "eta must be finite and >= 0");
+  }
+  const double stab = wave_stability(d, vmax);
+  if (stab > 1.0)
+    return fail(WAVE_EUNSTABLE, "stability number " + std::to_string(stab) + " > 1 (reduce dt)");
+
+  wave_ctx* c = new wave_ctx();
+  c->d = *d;
+  c->L = wave::make_layout(d->nx, d->ny, d->nz);
+  c->plan = plan;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->arena = static_cast<char*>(dev_arena);
+  c->es = storage_bytes(d->storage);
+  c->cur = 0;
+  c->step = 0;
+  c->broken = false;
+  c->damp = damp;
+  coefficients64(d, c->c64);
+  for (int m = 0; m < 13; ++m) c->c[m] = (float)c->c64[m];
+  c->q[0] = (float)(1.0 / (4.0 * d->dx * d->dx));
+  c->q[1] = (float)(1.0 / (4.0 * d->dy * d->dy));
+  c->q[2] = (float)(1.0 / (4.0 * d->dz * d->dz));
+  c->nsrc = c->nrec = c->trace_count = 0;
+  c->variant = WAVE_KERNEL_STREAM;
+  c->ry = 1;
+  c->nw = 16;
+  c->zchunk = 0;
+  c->timing = false;
+  c->events_used = 0;
+  c->timing_ms = 0.0;
+  c->timing_launches = 0;
+
+  auto bail = [&](int rc) {
+    delete c;
+    return rc;
+  };
+  hipError_t e = hipMemsetAsync(c->arena, 0, plan.total, c->stream);
+  if (e != hipSuccess) return bail(dev_fail(nullptr, e, "hipMemsetAsync"));
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return bail(dev_fail(nullptr, e, "hipStreamSynchronize"));
+
+  // vp = (V dt)^2 in double, rounded once to float
+  const size_t pn = (size_t)d->nx * d->ny;
+  std::vector<float> plane(pn);
+  for (int k = 0; k < d->nz; ++k) {
+    const float* vk = vel + (size_t)k * pn;
+    for (size_t p = 0; p < pn; ++p) {
+      const double v = (double)vk[p] * d->dt;
+      plane[p] = (float)(v * v);
+    }
+    int rc = upload_plane(c, c->at(plan.vp), 4, k, plane.data());
+    if (rc) return bail(rc);
+  }
+  if (damp) {
+    for (int k = 0; k < d->nz; ++k) {
+      const float* src;
+      if (eta) {
+        src = eta + (size_t)k * pn;
+      } else {
+        eta_plane(d, vmax, k, plane.data());
+        src = plane.data();
+      }
+      int rc = upload_plane(c, c->at(plan.eta), 4, k, src);
+      if (rc) return bail(rc);
+    }
+  }
+  *out = c;
+  return WAVE_OK;
+}
+
+int wave_free(wave_ctx* c) {
+  if (!c) return WAVE_OK;
+  if (!c->broken) (void)hipStreamSynchronize(c->stream);
+  for (auto& ev : c->events) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  delete c;
+  return WAVE_OK;
+}
+
+int wave_inject(wave_ctx* c, int32_t i, int32_t j, int32_t k, const float* samples,
+                int32_t nsamples) {
+  CHECK_CTX(c);
+  if (!in_grid(c, i, j, k)) return fail(WAVE_EINVAL, "source index outside the grid");
+  if (nsamples < 0 || nsamples > c->d.max_steps) return fail(WAVE_EINVAL, "nsamples outside [0, max_steps]");
+  if (nsamples > 0 && !samples) return fail(WAVE_EINVAL, "samples is NULL");
+  if (c->nsrc >= c->d.max_src) return fail(WAVE_EINVAL, "source table full (max_src)");
+  for (int s = 0; s < nsamples; ++s)
+    if (!isfinite(samples[s])) return fail(WAVE_EINVAL, "non-finite wavelet sample");
+  std::vector<float> row((size_t)std::max(c->d.max_steps, 1), 0.0f);
+  if (nsamples) memcpy(row.data(), samples, (size_t)nsamples * 4);
+  const int64_t off = offset_of(c, i, j, k);
+  float* wl = reinterpret_cast<float*>(c->at(c->plan.wavelet)) + (size_t)c->nsrc * std::max(c->d.max_steps, 1);
+  int64_t* so = reinterpret_cast<int64_t*>(c->at(c->plan.src_off)) + c->nsrc;
+  HIPCHK(c, hipMemcpyAsync(wl, row.data(), row.size() * 4, hipMemcpyHostToDevice, c->stream), "hipMemcpyAsync");
+  HIPCHK(c, hipMemcpyAsync(so, &off, 8, hipMemcpyHostToDevice, c->stream), "hipMemcpyAsync");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  c->nsrc += 1;
+  return WAVE_OK;
+}
+
+int wave_record(wave_ctx* c, const int32_t* ijk, int32_t nrec) {
+  CHECK_CTX(c);
+  if (nrec < 0 || nrec > c->d.max_rec) return fail(WAVE_EINVAL, "nrec outside [0, max_rec]");
+  if (nrec > 0 && !ijk) return fail(WAVE_EINVAL, "receiver list is NULL");
+  std::vector<int64_t> off((size_t)std::max(nrec, 1));
+  for (int r = 0; r < nrec; ++r) {
+    if (!in_grid(c, ijk[3 * r], ijk[3 * r + 1], ijk[3 * r + 2]))
+      return fail(WAVE_EINVAL, "receiver index outside the grid");
+    off[r] = offset_of(c, ijk[3 * r], ijk[3 * r + 1], ijk[3 * r + 2]);
+  }
+  if (nrec > 0) {
+    HIPCHK(c, hipMemcpyAsync(c->at(c->plan.rec_off), off.data(), (size_t)nrec * 8, hipMemcpyHostToDevice, c->stream),
+           "hipMemcpyAsync");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  }
+  c->nrec = nrec;
+  c->trace_count = 0;
+  return WAVE_OK;
+}
+
+int wave_step(wave_ctx* c, int32_t n) {
+  CHECK_CTX(c);
+  if (n < 0) return fail(WAVE_EINVAL, "n < 0");
+  if (c->nrec > 0 && (int64_t)c->trace_count + n > c->d.max_steps)
+    return fail(WAVE_EINVAL, "trace buffer would overflow max_steps");
+  if (c->step + n > 0x7fffffff) return fail(WAVE_EINVAL, "step counter overflow");
+  const Layout& L = c->L;
+  wave::SweepArgs sa;
+  sa.vp = c->f_origin(c->plan.vp);
+  sa.eta = c->f_origin(c->plan.eta);
+  sa.phi = c->f_origin(c->plan.phi);
+  sa.nx = L.nx;
+  sa.ny = L.ny;
+  sa.nz = L.nz;
+  sa.w = c->d.w;
+  sa.pitch = L.pitch;
+  sa.plane = L.plane;
+  memcpy(sa.c, c->c, sizeof(sa.c));
+  memcpy(sa.q, c->q, sizeof(sa.q));
+  sa.damping = c->damp ? 1 : 0;
+  const int zc = c->zchunk > 0 ? c->zchunk : wave::auto_zchunk(L.nx, L.ny, L.nz, c->ry, c->nw);
+
+  wave::InjectArgs ia;
+  ia.vp = sa.vp;
+  ia.nsrc = c->nsrc;
+  ia.src_off = reinterpret_cast<const int64_t*>(c->at(c->plan.src_off));
+  ia.wavelet = reinterpret_cast<const float*>(c->at(c->plan.wavelet));
+  ia.max_steps = std::max(c->d.max_steps, 1);
+  ia.nrec = c->nrec;
+  ia.rec_off = reinterpret_cast<const int64_t*>(c->at(c->plan.rec_off));
+
+  for (int t = 0; t < n; ++t) {
+    sa.cur = c->u_origin(c->cur);
+    sa.nxt = c->u_origin(1 - c->cur);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+      if (c->events_used == c->events.size()) {
+        hipEvent_t a, b;
+        HIPCHK(c, hipEventCreate(&a), "hipEventCreate");
+        HIPCHK(c, hipEventCreate(&b), "hipEventCreate");
+        c->events.emplace_back(a, b);
+      }
+      e0 = c->events[c->events_used].first;
+      e1 = c->events[c->events_used].second;
+      c->events_used += 1;
+      HIPCHK(c, hipEventRecord(e0, c->stream), "hipEventRecord");
+    }
+    hipError_t e = (c->variant == WAVE_KERNEL_DIRECT)
+                       ? wave::launch_sweep_direct(sa, c->d.storage, c->stream)
+                       : wave::launch_sweep_stream(sa, c->d.storage, c->ry, c->nw, zc, c->stream);
+    if (e != hipSuccess) return dev_fail(c, e, "sweep launch");
+    if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream), "hipEventRecord");
+    if (c->nsrc > 0 || c->nrec > 0) {
+      ia.u = sa.nxt;
+      ia.step = (int32_t)c->step;
+      ia.traces = c->nrec > 0 ? reinterpret_cast<double*>(c->at(c->plan.traces)) : nullptr;
+      ia.trace_row = c->trace_count;
+      e = wave::launch_inject_record(ia, c->d.storage, c->stream);
+      if (e != hipSuccess) return dev_fail(c, e, "inject/record launch");
+    }
+    c->cur = 1 - c->cur;
+    c->step += 1;
+    if (c->nrec > 0) c->trace_count += 1;
+  }
+  return WAVE_OK;
+}
+
+int wave_sync(wave_ctx* c) {
+  CHECK_CTX(c);
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  return WAVE_OK;
+}
+
+int64_t wave_step_count(const wave_ctx* c) { return c ? c->step : -1; }
+
+int wave_read_field(wave_ctx* c, int32_t which, float* out) {
+  CHECK_CTX(c);
+  if (!out) return fail(WAVE_EINVAL, "out is NULL");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  const size_t pn = (size_t)c->L.nx * c->L.ny;
+  switch (which) {
+    case WAVE_FIELD_U: return download_u(c, c->cur, out);
+    case WAVE_FIELD_UPREV: return download_u(c, 1 - c->cur, out);
+    case WAVE_FIELD_PHI:
+    case WAVE_FIELD_VP:
+    case WAVE_FIELD_ETA: {
+      const size_t off = which == WAVE_FIELD_PHI ? c->plan.phi : which == WAVE_FIELD_VP ? c->plan.vp : c->plan.eta;
+      if (off == (size_t)-1) {
+        memset(out, 0, pn * c->L.nz * sizeof(float));
+        return WAVE_OK;
+      }
+      for (int k = 0; k < c->L.nz; ++k) {
+        int rc = download_plane(c, c->at(off), 4, k, out + (size_t)k * pn);
+        if (rc) return rc;
+      }
+      return WAVE_OK;
+    }
+  }
+  return fail(WAVE_EINVAL, "unknown field id");
+}
+
+int wave_write_field(wave_ctx* c, int32_t which, const float* in) {
+  CHECK_CTX(c);
+  if (!in) return fail(WAVE_EINVAL, "input is NULL");
+  const size_t n = (size_t)c->L.nx * c->L.ny * c->L.nz;
+  for (size_t p = 0; p < n; ++p)
+    if (!isfinite(in[p])) return fail(WAVE_EINVAL, "non-finite value");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  const size_t pn = (size_t)c->L.nx * c->L.ny;
+  switch (which) {
+    case WAVE_FIELD_U: return upload_u(c, c->cur, in);
+    case WAVE_FIELD_UPREV: return upload_u(c, 1 - c->cur, in);
+    case WAVE_FIELD_PHI: {
+      if (c->plan.phi == (size_t)-1) return fail(WAVE_EINVAL, "no phi field with damping off");
+      for (int k = 0; k < c->L.nz; ++k) {
+        int rc = upload_plane(c, c->at(c->plan.phi), 4, k, in + (size_t)k * pn);
+        if (rc) return rc;
+      }
+      return WAVE_OK;
+    }
+  }
+  return fail(WAVE_EINVAL, "field is read-only or unknown");
+}
+
+int wave_read_traces(wave_ctx* c, double* out, int32_t* steps_out) {
+  CHECK_CTX(c);
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  if (steps_out) *steps_out = c->trace_count;
+  if (out && c->nrec > 0 && c->trace_count > 0) {
+    HIPCHK(c,
+           hipMemcpyAsync(out, c->at(c->plan.traces), (size_t)c->trace_count * c->nrec * 8,
+                          hipMemcpyDeviceToHost, c->stream),
+           "hipMemcpyAsync");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  }
+  return WAVE_OK;
+}
+
+int wave_energy(wave_ctx* c, double* out) {
+  CHECK_CTX(c);
+  if (!out) return fail(WAVE_EINVAL, "out is NULL");
+  wave::EnergyArgs ea;
+  ea.cur = c->u_origin(c->cur);
+  ea.prev = c->u_origin(1 - c->cur);
+  ea.vp = c->f_origin(c->plan.vp);
+  ea.nx = c->L.nx;
+  ea.ny = c->L.ny;
+  ea.nz = c->L.nz;
+  ea.pitch = c->L.pitch;
+  ea.plane = c->L.plane;
+  memcpy(ea.c, c->c64, sizeof(ea.c));
+  ea.partial = reinterpret_cast<double*>(c->at(c->plan.partial));
+  ea.result = reinterpret_cast<double*>(c->at(c->plan.eres));
+  hipError_t e = wave::launch_energy(ea, c->d.storage, c->stream);
+  if (e != hipSuccess) return dev_fail(c, e, "energy launch");
+  double r[2];
+  HIPCHK(c, hipMemcpyAsync(r, ea.result, 16, hipMemcpyDeviceToHost, c->stream), "hipMemcpyAsync");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  *out = r[0] - r[1];
+  return WAVE_OK;
+}
+
+int wave_set_kernel(wave_ctx* c, int32_t variant, int32_t ry, int32_t nw, int32_t zchunk) {
+  CHECK_CTX(c);
+  if (variant == WAVE_KERNEL_DIRECT) {
+    c->variant = variant;
+    return WAVE_OK;
+  }
+  if (variant != WAVE_KERNEL_STREAM) return fail(WAVE_EINVAL, "unknown kernel variant");
+  if (!wave::stream_config_supported(ry, nw)) return fail(WAVE_EINVAL, "tile (rows_per_wave, waves) not compiled");
+  if (zchunk < 0) return fail(WAVE_EINVAL, "zchunk < 0");
+  c->variant = variant;
+  c->ry = ry;
+  c->nw = nw;
+  c->zchunk = zchunk;
+  return WAVE_OK;
+}
+
+int wave_set_timing(wave_ctx* c, int32_t on) {
+  CHECK_CTX(c);
+  c->timing = on != 0;
+  c->events_used = 0;
+  c->timing_ms = 0.0;
+  c->timing_launches = 0;
+  return WAVE_OK;
+}
+
+int wave_read_timing(wave_ctx* c, double* ms_total, int64_t* launches) {
+  CHECK_CTX(c);
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  for (size_t k = 0; k < c->events_used; ++k) {
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->events[k].first, c->events[k].second), "hipEventElapsedTime");
+    c->timing_ms += ms;
+    c->timing_launches += 1;
+  }
+  c->events_used = 0;
+  if (ms_total) *ms_total = c->timing_ms;
+  if (launches) *launches = c->timing_launches;
+  return WAVE_OK;
+}
+
+double wave_sweep_bytes(const wave_ctx* c) {
+  if (!c) return -1.0;
+  const double total = (double)c->d.nx * c->d.ny * c->d.nz;
+  double inner = total;
+  if (c->damp) {
+    const double w2 = 2.0 * c->d.w;
+    inner = (c->d.nx - w2) * (c->d.ny - w2) * (c->d.nz - w2);
+  }
+  const double layer = total - inner;
+  const double es = c->es;
+  return inner * (3.0 * es + 4.0) + layer * (3.0 * es + 16.0);
+}
+
+int wave_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
+  if (!dst || !src || (bytes % 16) || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15))
+    return fail(WAVE_EINVAL, "copy needs 16-byte aligned pointers and a multiple of 16 bytes");
+  hipError_t e = wave::launch_stream_copy(dst, src, bytes, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return dev_fail(nullptr, e, "copy launch");
+  return WAVE_OK;
+}
+
+const char* wave_strerror(int s) {
+  switch (s) {
+    case WAVE_OK: return "ok";
+    case WAVE_EINVAL: return "invalid argument";
+    case WAVE_ENOMEM: return "arena too small";
+    case WAVE_EUNSTABLE: return "time step violates the stability bound";
+    case WAVE_EDEVICE: return "device error";
+    case WAVE_ESTATE: return "context broken by an earlier device error";
+    case WAVE_EBUDGET: return "request can never fit the memory budget";
+  }
+  return "unknown status";
+}
+
+const char* wave_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

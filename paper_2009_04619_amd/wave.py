@@ -1,0 +1,335 @@
+"""ctypes binding of the C ABI in include/wave.h (argument marshalling only).
+
+Every function of the header is exposed under the same name and returns the
+same status codes (a non-zero status raises `WaveError` in the `Shot`
+convenience class; the plain functions return it).  All computation runs in
+the HIP kernels of `libwave.so`; there is no fallback: importing this module
+fails loudly when the library is missing.
+
+PyTorch serves only as the device allocator (the arena is a torch uint8
+tensor) and as the source of the HIP stream.  torch is imported before the
+library is loaded so that both share one HIP runtime.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwave.so")
+
+WAVE_OK, WAVE_EINVAL, WAVE_ENOMEM, WAVE_EUNSTABLE = 0, -1, -2, -3
+WAVE_EDEVICE, WAVE_ESTATE, WAVE_EBUDGET = -4, -5, -6
+WAVE_F32, WAVE_BF16, WAVE_F16 = 0, 1, 2
+WAVE_DAMPING_OFF = 1
+WAVE_FIELD_U, WAVE_FIELD_UPREV, WAVE_FIELD_PHI, WAVE_FIELD_VP, WAVE_FIELD_ETA = 0, 1, 2, 3, 4
+WAVE_KERNEL_DIRECT, WAVE_KERNEL_STREAM = 0, 1
+STORAGE = {"f32": WAVE_F32, "bf16": WAVE_BF16, "f16": WAVE_F16}
+
+EXPORTED = [
+    "wave_bytes_required", "wave_coefficients", "wave_stability", "wave_eta_default",
+    "wave_alloc", "wave_free", "wave_inject", "wave_record", "wave_step", "wave_sync",
+    "wave_step_count", "wave_read_field", "wave_write_field", "wave_read_traces",
+    "wave_energy", "wave_set_kernel", "wave_set_timing", "wave_read_timing",
+    "wave_sweep_bytes", "wave_stream_copy", "wave_strerror", "wave_last_error",
+]
+
+
+class wave_desc(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("w", C.c_int32),
+        ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("dt", C.c_double),
+        ("storage", C.c_int32), ("flags", C.c_int32), ("refl", C.c_double),
+        ("max_src", C.c_int32), ("max_rec", C.c_int32), ("max_steps", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+
+class WaveError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {wave_strerror(status)} ({status}): {wave_last_error()}")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2009_04619_amd.build` "
+            "(there is no fallback path)")
+    lib = C.CDLL(LIB_PATH)
+    P, i32, i64, f64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
+    D = C.POINTER(wave_desc)
+    sig = {
+        "wave_bytes_required": (sz, [D]),
+        "wave_coefficients": (C.c_int, [D, P]),
+        "wave_stability": (f64, [D, f64]),
+        "wave_eta_default": (C.c_int, [D, f64, P]),
+        "wave_alloc": (C.c_int, [D, P, P, P, sz, P, C.POINTER(P)]),
+        "wave_free": (C.c_int, [P]),
+        "wave_inject": (C.c_int, [P, i32, i32, i32, P, i32]),
+        "wave_record": (C.c_int, [P, P, i32]),
+        "wave_step": (C.c_int, [P, i32]),
+        "wave_sync": (C.c_int, [P]),
+        "wave_step_count": (i64, [P]),
+        "wave_read_field": (C.c_int, [P, i32, P]),
+        "wave_write_field": (C.c_int, [P, i32, P]),
+        "wave_read_traces": (C.c_int, [P, P, C.POINTER(i32)]),
+        "wave_energy": (C.c_int, [P, C.POINTER(f64)]),
+        "wave_set_kernel": (C.c_int, [P, i32, i32, i32, i32]),
+        "wave_set_timing": (C.c_int, [P, i32]),
+        "wave_read_timing": (C.c_int, [P, C.POINTER(f64), C.POINTER(i64)]),
+        "wave_sweep_bytes": (f64, [P]),
+        "wave_stream_copy": (C.c_int, [P, P, sz, P]),
+        "wave_strerror": (C.c_char_p, [C.c_int]),
+        "wave_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+# ---- the C functions under their own names ---------------------------------
+def wave_bytes_required(d: wave_desc) -> int:
+    return int(_lib.wave_bytes_required(C.byref(d)))
+
+
+def wave_coefficients(d: wave_desc):
+    out = np.zeros(13, np.float32)
+    return int(_lib.wave_coefficients(C.byref(d), _p(out))), out
+
+
+def wave_stability(d: wave_desc, vmax: float) -> float:
+    return float(_lib.wave_stability(C.byref(d), float(vmax)))
+
+
+def wave_eta_default(d: wave_desc, vmax: float):
+    out = np.zeros((d.nz, d.ny, d.nx), np.float32)
+    return int(_lib.wave_eta_default(C.byref(d), float(vmax), _p(out))), out
+
+
+def wave_alloc(d: wave_desc, vel: np.ndarray, eta: Optional[np.ndarray], arena_ptr: int,
+               arena_bytes: int, stream_ptr: int):
+    ctx = C.c_void_p()
+    rc = _lib.wave_alloc(C.byref(d), _p(vel), _p(eta), C.c_void_p(arena_ptr), arena_bytes,
+                         C.c_void_p(stream_ptr), C.byref(ctx))
+    return int(rc), ctx
+
+
+def wave_free(ctx) -> int:
+    return int(_lib.wave_free(ctx))
+
+
+def wave_inject(ctx, i: int, j: int, k: int, samples: np.ndarray) -> int:
+    s = np.ascontiguousarray(samples, dtype=np.float32)
+    return int(_lib.wave_inject(ctx, i, j, k, _p(s), s.size))
+
+
+def wave_record(ctx, ijk: np.ndarray) -> int:
+    a = np.ascontiguousarray(np.asarray(ijk, dtype=np.int32).reshape(-1, 3))
+    return int(_lib.wave_record(ctx, _p(a), a.shape[0]))
+
+
+def wave_step(ctx, n: int) -> int:
+    return int(_lib.wave_step(ctx, int(n)))
+
+
+def wave_sync(ctx) -> int:
+    return int(_lib.wave_sync(ctx))
+
+
+def wave_step_count(ctx) -> int:
+    return int(_lib.wave_step_count(ctx))
+
+
+def wave_read_field(ctx, which: int, out: np.ndarray) -> int:
+    assert out.dtype == np.float32 and out.flags.c_contiguous
+    return int(_lib.wave_read_field(ctx, which, _p(out)))
+
+
+def wave_write_field(ctx, which: int, data: np.ndarray) -> int:
+    a = np.ascontiguousarray(data, dtype=np.float32)
+    return int(_lib.wave_write_field(ctx, which, _p(a)))
+
+
+def wave_read_traces(ctx, out: Optional[np.ndarray]):
+    n = C.c_int32()
+    rc = _lib.wave_read_traces(ctx, _p(out), C.byref(n))
+    return int(rc), int(n.value)
+
+
+def wave_energy(ctx):
+    e = C.c_double()
+    rc = _lib.wave_energy(ctx, C.byref(e))
+    return int(rc), float(e.value)
+
+
+def wave_set_kernel(ctx, variant: int, rows_per_wave: int = 1, waves_per_group: int = 16,
+                    zchunk: int = 0) -> int:
+    return int(_lib.wave_set_kernel(ctx, variant, rows_per_wave, waves_per_group, zchunk))
+
+
+def wave_set_timing(ctx, on: bool) -> int:
+    return int(_lib.wave_set_timing(ctx, 1 if on else 0))
+
+
+def wave_read_timing(ctx):
+    ms, n = C.c_double(), C.c_int64()
+    rc = _lib.wave_read_timing(ctx, C.byref(ms), C.byref(n))
+    return int(rc), float(ms.value), int(n.value)
+
+
+def wave_sweep_bytes(ctx) -> float:
+    return float(_lib.wave_sweep_bytes(ctx))
+
+
+def wave_stream_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream_ptr: int) -> int:
+    return int(_lib.wave_stream_copy(C.c_void_p(dst_ptr), C.c_void_p(src_ptr), nbytes,
+                                     C.c_void_p(stream_ptr)))
+
+
+def wave_strerror(status: int) -> str:
+    return _lib.wave_strerror(int(status)).decode()
+
+
+def wave_last_error() -> str:
+    return _lib.wave_last_error().decode()
+
+
+def make_desc(nx, ny, nz, w, dx, dy, dz, dt, storage="f32", damping=True, refl=1e-3,
+              max_src=4, max_rec=0, max_steps=0) -> wave_desc:
+    d = wave_desc()
+    d.nx, d.ny, d.nz, d.w = int(nx), int(ny), int(nz), int(w)
+    d.dx, d.dy, d.dz, d.dt = float(dx), float(dy), float(dz), float(dt)
+    d.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    d.flags = 0 if damping else WAVE_DAMPING_OFF
+    d.refl = float(refl)
+    d.max_src, d.max_rec, d.max_steps = int(max_src), int(max_rec), int(max_steps)
+    d.reserved = 0
+    return d
+
+
+def _check(rc: int, what: str):
+    if rc != WAVE_OK:
+        raise WaveError(rc, what)
+
+
+class Shot:
+    """One simulation context on a GPU: owns its torch arena and the ctx.
+
+    Arguments mirror `wave_desc`; `vel` is float32 [nz][ny][nx] (m/s) and
+    `eta` an explicit damping array or None for the default profile."""
+
+    def __init__(self, nx, ny, nz, w, dx, dy, dz, dt, vel, *, eta=None, storage="f32",
+                 damping=True, refl=1e-3, max_src=4, max_rec=0, max_steps=0,
+                 device="cuda:0", stream=None):
+        self.device = torch.device(device)
+        self.desc = make_desc(nx, ny, nz, w, dx, dy, dz, dt, storage, damping, refl,
+                              max_src, max_rec, max_steps)
+        nbytes = wave_bytes_required(self.desc)
+        if nbytes == 0:
+            raise WaveError(WAVE_EINVAL, "wave_bytes_required")
+        self.nbytes = nbytes
+        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        vel = np.ascontiguousarray(vel, dtype=np.float32)
+        assert vel.shape == (nz, ny, nx)
+        eta_a = None if eta is None else np.ascontiguousarray(eta, dtype=np.float32)
+        rc, self.ctx = wave_alloc(self.desc, vel, eta_a, self.arena.data_ptr(), nbytes,
+                                  self.stream.cuda_stream)
+        _check(rc, "wave_alloc")
+        self.shape = (nz, ny, nx)
+        self.nrec = 0
+
+    def inject(self, i, j, k, samples):
+        _check(wave_inject(self.ctx, i, j, k, samples), "wave_inject")
+
+    def record(self, ijk):
+        a = np.asarray(ijk, dtype=np.int32).reshape(-1, 3)
+        _check(wave_record(self.ctx, a), "wave_record")
+        self.nrec = a.shape[0]
+
+    def step(self, n):
+        _check(wave_step(self.ctx, n), "wave_step")
+
+    def sync(self):
+        _check(wave_sync(self.ctx), "wave_sync")
+
+    def read(self, which=WAVE_FIELD_U) -> np.ndarray:
+        out = np.empty(self.shape, np.float32)
+        _check(wave_read_field(self.ctx, which, out), "wave_read_field")
+        return out
+
+    def write(self, which, data):
+        _check(wave_write_field(self.ctx, which, data), "wave_write_field")
+
+    def traces(self) -> np.ndarray:
+        rc, n = wave_read_traces(self.ctx, None)
+        _check(rc, "wave_read_traces")
+        out = np.zeros((n, self.nrec), np.float64)
+        if n and self.nrec:
+            rc, _ = wave_read_traces(self.ctx, out)
+            _check(rc, "wave_read_traces")
+        return out
+
+    def energy(self) -> float:
+        rc, e = wave_energy(self.ctx)
+        _check(rc, "wave_energy")
+        return e
+
+    def set_kernel(self, variant, rows_per_wave=1, waves_per_group=16, zchunk=0):
+        _check(wave_set_kernel(self.ctx, variant, rows_per_wave, waves_per_group, zchunk),
+               "wave_set_kernel")
+
+    def set_timing(self, on):
+        _check(wave_set_timing(self.ctx, on), "wave_set_timing")
+
+    def read_timing(self):
+        rc, ms, n = wave_read_timing(self.ctx)
+        _check(rc, "wave_read_timing")
+        return ms, n
+
+    def sweep_bytes(self) -> float:
+        return wave_sweep_bytes(self.ctx)
+
+    @property
+    def step_count(self) -> int:
+        return wave_step_count(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            wave_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def shot_from_synth(s, storage="f32", damping=True, device="cuda:0", max_steps=None, eta=None):
+    """A `Shot` for a synth.Shot (sources injected, receivers set)."""
+    steps = s.steps if max_steps is None else max_steps
+    nrec = 0 if s.rec is None else len(s.rec)
+    sh = Shot(s.nx, s.ny, s.nz, s.w, s.dx, s.dy, s.dz, s.dt, s.vel, eta=eta, storage=storage,
+              damping=damping, max_src=max(1, len(s.src)), max_rec=nrec,
+              max_steps=max(steps, s.wavelet.shape[1] if s.wavelet is not None else 0),
+              device=device)
+    for q, (i, j, k) in enumerate(s.src):
+        sh.inject(i, j, k, s.wavelet[q])
+    if nrec:
+        sh.record(s.rec)
+    return sh

@@ -1,0 +1,226 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+The kernels evaluate every point with the same float32 operations in the same
+order as the oracle's float32 mode, so the comparison with it is exact
+(value equality of every field element and trace sample).  Against the
+float64 oracle the bar is 1e-5 relative L2 after N steps (float32 storage).
+16-bit storage is exact against the oracle's 16-bit mode and its distance
+from float64 is reported and bounded.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def W():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU (run with -m 'not gpu' on CPU)")
+    from paper_2009_04619_amd import wave
+    return wave
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_run(W, shot, steps, storage="f32", damping=True, kernel=None, state=None, eta=None):
+    sh = W.shot_from_synth(shot, storage=storage, damping=damping, max_steps=max(steps, 1),
+                           eta=eta)
+    if kernel is not None:
+        sh.set_kernel(*kernel)
+    if state is not None:
+        sh.write(W.WAVE_FIELD_U, state["u"])
+        sh.write(W.WAVE_FIELD_UPREV, state["u_prev"])
+        if damping and "phi" in state:
+            sh.write(W.WAVE_FIELD_PHI, state["phi"])
+    sh.step(steps)
+    out = dict(u=sh.read(W.WAVE_FIELD_U), u_prev=sh.read(W.WAVE_FIELD_UPREV),
+               phi=sh.read(W.WAVE_FIELD_PHI), traces=sh.traces())
+    sh.close()
+    return out
+
+
+def assert_same(a, b, what):
+    for key in ("u", "u_prev", "phi", "traces"):
+        x, y = a[key], b[key]
+        assert x.shape == y.shape, (what, key)
+        if not np.array_equal(x, y):
+            bad = np.argwhere(x != y)
+            i = tuple(bad[0])
+            raise AssertionError(f"{what}: {key} differs at {len(bad)} points, first {i}: "
+                                 f"{x[i]!r} vs {y[i]!r}")
+
+
+def rel_l2(a, b):
+    n = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / n) if n > 0 else float(np.linalg.norm(a))
+
+
+# --------------------------------------------------------------------------
+def test_c1_plain_fp32_vs_oracle(W):
+    """64^3, 16-cell layer, 2000 m/s, Ricker at the centre, 100 steps."""
+    shot = synth.config_c1(steps=100)
+    say("case c1 64^3 w16 100 steps")
+    g = gpu_run(W, shot, 100)
+    o32 = oracle.run_shot(shot, precision="f32")
+    o32["traces"] = o32["traces"]
+    assert_same(g, o32, "c1 vs fp32 oracle")
+    o64 = oracle.run_shot(shot, precision="f64")
+    eu, et = rel_l2(g["u"], o64["u"]), rel_l2(g["traces"], o64["traces"])
+    say(f"c1 rel L2 vs fp64: field {eu:.3e} traces {et:.3e}")
+    assert eu <= 1e-5 and et <= 1e-5
+    assert np.abs(g["phi"]).max() > 0          # the layer update ran
+    assert np.abs(g["traces"]).max() > 0
+
+
+RAGGED = [
+    (70, 45, 37, 5, 2),     # partial x tile, partial y tiles
+    (65, 17, 130, 3, 1),    # 1 lane in the last x tile; long z
+    (130, 33, 11, 4, 3),
+    (9, 200, 21, 2, 1),     # narrow x
+    (1, 1, 1, 0, 1),        # a single point
+    (64, 16, 8, 0, 1),      # no layer
+    (40, 40, 40, 20, 1),    # all layer (2w = n)
+]
+
+KERNELS = [(W_, ry, nw, zc) for (W_, ry, nw, zc) in [
+    (0, 1, 16, 0), (1, 1, 16, 0), (1, 1, 8, 0), (1, 2, 8, 0), (1, 2, 16, 0), (1, 4, 4, 0),
+    (1, 1, 16, 5), (1, 2, 8, 7), (1, 1, 8, 1)]]
+
+
+@pytest.mark.parametrize("case", RAGGED, ids=lambda c: "x".join(map(str, c[:3])) + f"_w{c[3]}")
+def test_ragged_grids_every_kernel_bitwise(W, case):
+    nx, ny, nz, w, nsrc = case
+    steps = 25
+    shot = synth.config_small_layered(nx, ny, nz, w, steps, seed=nx * 7 + ny, nsrc=nsrc)
+    say(f"case ragged {case}")
+    ref = oracle.run_shot(shot, precision="f32")
+    for k in KERNELS:
+        g = gpu_run(W, shot, steps, kernel=k)
+        assert_same(g, ref, f"{case} kernel {k}")
+
+
+# Bound vs float64 from the storage rounding unit u (2^-8 bf16, 2^-11 f16):
+# one rounding per stored value and step, accumulating like a random walk over
+# N steps with a modest amplification, 2 sqrt(N) u.
+@pytest.mark.parametrize("storage,unit", [("bf16", 2.0 ** -8), ("f16", 2.0 ** -11)])
+def test_16bit_storage_exact_vs_oracle_and_bounded_vs_fp64(W, storage, unit):
+    bound = 2.0 * np.sqrt(150.0) * unit
+    shot = synth.config_small_layered(96, 80, 72, 12, 150, seed=21)
+    say(f"case storage {storage}")
+    g = gpu_run(W, shot, 150, storage=storage)
+    o = oracle.run_shot(shot, precision="f32", storage=storage)
+    assert_same(g, o, storage)
+    for k in [(0, 1, 16, 0), (1, 2, 8, 9)]:
+        assert_same(gpu_run(W, shot, 150, storage=storage, kernel=k), o, f"{storage} {k}")
+    o64 = oracle.run_shot(shot, precision="f64")
+    eu, et = rel_l2(g["u"], o64["u"]), rel_l2(g["traces"], o64["traces"])
+    say(f"{storage} rel L2 vs fp64 after 150 steps: field {eu:.3e} traces {et:.3e} "
+        f"(bound {bound:.3e})")
+    assert eu < bound and et < bound
+
+
+def test_energy_conserved_with_damping_off(W):
+    nx, ny, nz = 80, 72, 64
+    shot = synth.config_small_layered(nx, ny, nz, 0, 1, seed=31)
+    shot.src, shot.wavelet = [], np.zeros((0, 1), np.float32)
+    k_, j_, i_ = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    bump = np.exp(-(((i_ - 40) / 4.0) ** 2 + ((j_ - 30) / 3.0) ** 2
+                    + ((k_ - 33) / 5.0) ** 2)).astype(np.float32)
+    say("case energy damping off")
+    sh = W.shot_from_synth(shot, damping=False, max_steps=1)
+    sh.write(W.WAVE_FIELD_U, bump)
+    sh.write(W.WAVE_FIELD_UPREV, bump)
+    e = [sh.energy()]
+    # the device energy equals the oracle's float64 energy of the same fields
+    vp64, _ = oracle.vp(shot.vel, shot.dt)
+    for _ in range(5):
+        sh.step(60)
+        e.append(sh.energy())
+    u, up = sh.read(W.WAVE_FIELD_U), sh.read(W.WAVE_FIELD_UPREV)
+    eo = oracle.energy(vp64, u, up, shot.dx, shot.dy, shot.dz)
+    assert abs(e[-1] - eo) <= 1e-12 * abs(eo)
+    e = np.array(e)
+    drift = np.abs(e - e[0]).max() / e[0]
+    say(f"float32 fields, float64 energy: max relative drift over 300 steps {drift:.3e}")
+    assert e[0] > 0 and drift < 1e-5
+    sh.close()
+
+
+def test_c2_full_size_few_steps_bitwise(W):
+    """512^3, 20-cell layer, layered model: the benchmark's launch
+    configuration, 3 steps against the float32 oracle on every point."""
+    shot = synth.config_c2(steps=3)
+    say("case c2 512^3 3 steps")
+    g = gpu_run(W, shot, 3)
+    o = oracle.run_shot(shot, precision="f32")
+    assert_same(g, o, "c2 512^3")
+
+
+def test_long_run_medium_grid_vs_oracles(W):
+    shot = synth.config_small_layered(128, 112, 96, 20, 500, seed=41)
+    c = (64, 56, 25)
+    shot.src = [c]
+    shot.wavelet = synth.ricker(500, shot.dt)[None, :]
+    shot.rec = synth.receiver_line(128, 56, 25)
+    say("case long run 128x112x96 500 steps")
+    g = gpu_run(W, shot, 500)
+    o = oracle.run_shot(shot, precision="f32")
+    assert_same(g, o, "long run")
+    o64 = oracle.run_shot(shot, precision="f64")
+    eu, et = rel_l2(g["u"], o64["u"]), rel_l2(g["traces"], o64["traces"])
+    say(f"500 steps rel L2 vs fp64: field {eu:.3e} traces {et:.3e}")
+    assert eu <= 1e-5 and et <= 1e-5
+
+
+def test_deterministic_and_restartable(W):
+    shot = synth.config_small_layered(72, 66, 60, 8, 60, seed=51)
+    say("case determinism/restart")
+    a = gpu_run(W, shot, 60)
+    b = gpu_run(W, shot, 60)
+    assert_same(a, b, "run twice")
+    # 25 steps, snapshot, new context from the snapshot, 35 more steps
+    first = gpu_run(W, shot, 25)
+    rest = synth.config_small_layered(72, 66, 60, 8, 60, seed=51)
+    rest.wavelet = np.ascontiguousarray(rest.wavelet[:, 25:])
+    c = gpu_run(W, rest, 35, state=first)
+    for key in ("u", "u_prev", "phi"):
+        assert np.array_equal(c[key], a[key]), key
+    assert np.array_equal(np.concatenate([first["traces"], c["traces"]]), a["traces"])
+
+
+def test_error_paths(W):
+    shot = synth.config_small_layered(32, 32, 32, 4, 10, seed=61)
+    sh = W.shot_from_synth(shot, max_steps=10)
+    assert W.wave_inject(sh.ctx, 32, 0, 0, np.zeros(3, np.float32)) == W.WAVE_EINVAL
+    assert W.wave_inject(sh.ctx, 0, 0, 0, np.zeros(11, np.float32)) == W.WAVE_EINVAL
+    assert W.wave_step(sh.ctx, 11) == W.WAVE_EINVAL        # trace buffer of 10 steps
+    assert W.wave_step(sh.ctx, -1) == W.WAVE_EINVAL
+    assert W.wave_write_field(sh.ctx, W.WAVE_FIELD_VP, np.zeros((32, 32, 32), np.float32)) \
+        == W.WAVE_EINVAL
+    assert W.wave_set_kernel(sh.ctx, W.WAVE_KERNEL_STREAM, 3, 3, 0) == W.WAVE_EINVAL
+    assert W.wave_step(sh.ctx, 10) == W.WAVE_OK
+    assert sh.step_count == 10
+    sh.close()
+
+
+def test_stream_copy_copies(W):
+    import torch
+    src = torch.arange(1 << 20, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    assert W.wave_stream_copy(dst.data_ptr(), src.data_ptr(), src.numel() * 4, s.cuda_stream) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)

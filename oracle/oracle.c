@@ -42,11 +42,19 @@
  * ora_run_f32 evaluates the same recurrence in float with a fixed
  * per-point operation order (explicit fmaf where a fused multiply-add is
  * meant, nothing else fused; compile with -ffp-contract=off):
- *   lap = c_xyz * u
- *   for axis x, y, z; for m = 1..4: lap = fmaf(c_am, u(+m) + u(-m), lap)
- *   inner: u' = fmaf(vp, lap, fmaf(2, u, -u_prev))
- *   layer: a = fmaf(-eta, eta, fmaf(2, eta, 2))
- *          u' = fmaf(vp, lap + phi, fmaf(a, u, -u_prev)) / fmaf(2, eta, 1)
+ *   lap = 0
+ *   for axis x, y, z; for m = 1..4:
+ *       lap = fmaf(c_am, (u(+m) - u) + (u(-m) - u), lap)
+ *   (Eq. 3 with its centre weight folded into the pairs, see lap32)
+ *   inner: u' = u + fmaf(vp, lap, u - u_prev)
+ *   layer: t  = fmaf(-(eta * eta), u, u - u_prev)
+ *          u' = u + fmaf(vp, lap + phi, t) / fmaf(2, eta, 1)
+ *   (the same updates as above, rearranged around the increment u - u_prev:
+ *   [(2 + 2 eta - eta^2) u - u_prev + X] / (1 + 2 eta)
+ *   = u + [(u - u_prev) - eta^2 u + X] / (1 + 2 eta).  The increment of a
+ *   smooth field is computed exactly and every small term is rounded
+ *   relative to its own size, so only the final add rounds at the size of u;
+ *   with eta = 0 the layer form is the inner form bit for bit)
  *          g  = ((eta(+x) - eta(-x)) * q_x) * (u(+x) - u(-x))
  *          g  = fmaf((eta(+y) - eta(-y)) * q_y, u(+y) - u(-y), g)
  *          g  = fmaf((eta(+z) - eta(-z)) * q_z, u(+z) - u(-z), g)
@@ -221,15 +229,23 @@ static double lap64(const double *u, grid_t g, const double *c, int i, int j, in
     return s;
 }
 
+/* Eq. 3 in float, written with the centre weight folded into the pairs:
+ * c_xyz = -2 sum_a sum_m c_am holds exactly for the weights, so
+ *   lap = sum_a sum_m c_am [(u(+m) - u) + (u(-m) - u)].
+ * Rounding the 13 weights to float separately would break that identity and
+ * add a spurious term proportional to u itself (a frequency shift whose phase
+ * error grows with time); in this form a constant field has lap = 0 exactly
+ * and the differences of a smooth field are exact. */
 static float lap32(const float *u, grid_t g, const float *c, int i, int j, int k)
 {
-    float s = c[0] * U32(u, g, i, j, k);
+    const float uc = U32(u, g, i, j, k);
+    float s = 0.0f;
     for (int m = 1; m <= R; ++m)
-        s = fmaf(c[m], U32(u, g, i + m, j, k) + U32(u, g, i - m, j, k), s);
+        s = fmaf(c[m], (U32(u, g, i + m, j, k) - uc) + (U32(u, g, i - m, j, k) - uc), s);
     for (int m = 1; m <= R; ++m)
-        s = fmaf(c[4 + m], U32(u, g, i, j + m, k) + U32(u, g, i, j - m, k), s);
+        s = fmaf(c[4 + m], (U32(u, g, i, j + m, k) - uc) + (U32(u, g, i, j - m, k) - uc), s);
     for (int m = 1; m <= R; ++m)
-        s = fmaf(c[8 + m], U32(u, g, i, j, k + m) + U32(u, g, i, j, k - m), s);
+        s = fmaf(c[8 + m], (U32(u, g, i, j, k + m) - uc) + (U32(u, g, i, j, k - m) - uc), s);
     return s;
 }
 
@@ -343,13 +359,13 @@ int ora_run_f32(int nx, int ny, int nz, int w, double dx, double dy, double dz,
                     float L = lap32(u_cur, g, c, i, j, k);
                     float un;
                     if (eta == NULL || ora_is_inner(nx, ny, nz, w, i, j, k)) {
-                        un = fmaf(vp[p], L, fmaf(2.0f, u_cur[p], -u_prev[p]));
+                        un = u_cur[p] + fmaf(vp[p], L, u_cur[p] - u_prev[p]);
                         phi_next[p] = phi[p];
                     } else {
                         float e = eta[p];
-                        float a = fmaf(-e, e, fmaf(2.0f, e, 2.0f));
-                        float num = fmaf(vp[p], L + phi[p], fmaf(a, u_cur[p], -u_prev[p]));
-                        un = num / fmaf(2.0f, e, 1.0f);
+                        float t = fmaf(-(e * e), u_cur[p], u_cur[p] - u_prev[p]);
+                        float num = fmaf(vp[p], L + phi[p], t);
+                        un = u_cur[p] + num / fmaf(2.0f, e, 1.0f);
                         float gs = ((U32(eta, g, i + 1, j, k) - U32(eta, g, i - 1, j, k)) * q[0])
                                  * (U32(u_cur, g, i + 1, j, k) - U32(u_cur, g, i - 1, j, k));
                         gs = fmaf((U32(eta, g, i, j + 1, k) - U32(eta, g, i, j - 1, k)) * q[1],

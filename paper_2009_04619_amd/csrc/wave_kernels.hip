@@ -4,11 +4,18 @@
 // Per-point arithmetic (identical in every sweep variant, so results do not
 // depend on tiling): float32, explicit fused multiply-adds only where written
 // (the library is built with -ffp-contract=off), correctly rounded division:
-//   lap = c_xyz * u
-//   lap = fma(c_am, u(+m) + u(-m), lap)      axis x, then y, then z; m = 1..4
-//   inner: u' = fma(vp, lap, fma(2, u, -u_prev))
-//   layer: a  = fma(-eta, eta, fma(2, eta, 2))
-//          u' = fma(vp, lap + phi, fma(a, u, -u_prev)) / fma(2, eta, 1)
+//   lap = 0
+//   lap = fma(c_am, (u(+m) - u) + (u(-m) - u), lap)   axis x, y, z; m = 1..4
+// (Eq. 3 with the centre weight folded into the pairs: c_xyz equals
+// -2 sum c_am exactly, and in this form separately rounded float weights
+// cannot add a spurious term proportional to u, which would shift the
+// frequency and make the phase error grow with time)
+//   inner: u' = u + fma(vp, lap, u - u_prev)
+//   layer: t  = fma(-(eta * eta), u, u - u_prev)
+//          u' = u + fma(vp, lap + phi, t) / fma(2, eta, 1)
+// (Eq. 2 and the layer update rearranged around the increment u - u_prev,
+// which a smooth field gives exactly; every small term is then rounded
+// relative to its own size and only the final add rounds at the size of u)
 //          g  = ((eta(+x) - eta(-x)) * q_x) * (u(+x) - u(-x))
 //          g  = fma((eta(+y) - eta(-y)) * q_y, u(+y) - u(-y), g)
 //          g  = fma((eta(+z) - eta(-z)) * q_z, u(+z) - u(-z), g)
@@ -77,14 +84,14 @@ struct StF16 {
 
 // ---- per-point update ---------------------------------------------------------
 __device__ __forceinline__ float upd_inner(float c, float pu, float vp, float lap) {
-  return __builtin_fmaf(vp, lap, __builtin_fmaf(2.0f, c, -pu));
+  return c + __builtin_fmaf(vp, lap, c - pu);
 }
 
 __device__ __forceinline__ float upd_layer(float c, float pu, float vp, float lap, float e,
                                            float ph) {
-  const float a = __builtin_fmaf(-e, e, __builtin_fmaf(2.0f, e, 2.0f));
-  const float num = __builtin_fmaf(vp, lap + ph, __builtin_fmaf(a, c, -pu));
-  return num / __builtin_fmaf(2.0f, e, 1.0f);
+  const float t = __builtin_fmaf(-(e * e), c, c - pu);
+  const float num = __builtin_fmaf(vp, lap + ph, t);
+  return c + num / __builtin_fmaf(2.0f, e, 1.0f);
 }
 
 __device__ __forceinline__ float upd_phi(float ph, float e, float dex, float dux, float dey,
@@ -114,15 +121,16 @@ __global__ __launch_bounds__(256) void k_sweep_direct(SweepArgs a) {
   const int64_t P = a.pitch, Q = a.plane;
   const int64_t p = (int64_t)z * Q + (int64_t)y * P + x;
   const float c = S::ld(u, p);
-  float lap = a.c[0] * c;
-#pragma unroll
-  for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(a.c[m], S::ld(u, p + m) + S::ld(u, p - m), lap);
+  float lap = 0.0f;
 #pragma unroll
   for (int m = 1; m <= kR; ++m)
-    lap = __builtin_fmaf(a.c[4 + m], S::ld(u, p + m * P) + S::ld(u, p - m * P), lap);
+    lap = __builtin_fmaf(a.c[m], (S::ld(u, p + m) - c) + (S::ld(u, p - m) - c), lap);
 #pragma unroll
   for (int m = 1; m <= kR; ++m)
-    lap = __builtin_fmaf(a.c[8 + m], S::ld(u, p + m * Q) + S::ld(u, p - m * Q), lap);
+    lap = __builtin_fmaf(a.c[4 + m], (S::ld(u, p + m * P) - c) + (S::ld(u, p - m * P) - c), lap);
+#pragma unroll
+  for (int m = 1; m <= kR; ++m)
+    lap = __builtin_fmaf(a.c[8 + m], (S::ld(u, p + m * Q) - c) + (S::ld(u, p - m * Q) - c), lap);
   const float pu = S::ld(un, p);
   const float vp = a.vp[p];
   float r;
@@ -278,7 +286,6 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_stream(SweepArgs a, int tiles
   }
 
   const bool damp = a.damping != 0;
-  const float c0 = a.c[0];
   const bool xl = x < a.w || x >= a.nx - a.w;
   const uint32_t P4 = (uint32_t)P * 4u;
 
@@ -321,15 +328,17 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_stream(SweepArgs a, int tiles
       const bool yin = y < a.ny;
       const float* row = s + (kR + wv * RY + r) * LW + kR + lane;
       const float c = q[(Sl + kR) % 10][r];
-      float lap = c0 * c;
-#pragma unroll
-      for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(a.c[m], row[m] + row[-m], lap);
+      float lap = 0.0f;
 #pragma unroll
       for (int m = 1; m <= kR; ++m)
-        lap = __builtin_fmaf(a.c[4 + m], row[m * LW] + row[-m * LW], lap);
+        lap = __builtin_fmaf(a.c[m], (row[m] - c) + (row[-m] - c), lap);
 #pragma unroll
       for (int m = 1; m <= kR; ++m)
-        lap = __builtin_fmaf(a.c[8 + m], q[(Sl + kR + m) % 10][r] + q[(Sl + kR - m) % 10][r], lap);
+        lap = __builtin_fmaf(a.c[4 + m], (row[m * LW] - c) + (row[-m * LW] - c), lap);
+#pragma unroll
+      for (int m = 1; m <= kR; ++m)
+        lap = __builtin_fmaf(a.c[8 + m],
+                             (q[(Sl + kR + m) % 10][r] - c) + (q[(Sl + kR - m) % 10][r] - c), lap);
       const float pu = pv[B][r];
       const float vp = vv[B][r];
       const bool lay = damp && xin && yin && (zl || y < a.w || y >= a.ny - a.w || xl);

@@ -135,7 +135,7 @@ def test_16bit_storage_exact_vs_oracle_and_bounded_vs_fp64(W, storage, unit):
 def test_energy_conserved_with_damping_off(W):
     nx, ny, nz = 80, 72, 64
     shot = synth.config_small_layered(nx, ny, nz, 0, 1, seed=31)
-    shot.src, shot.wavelet = [], np.zeros((0, 1), np.float32)
+    shot.src, shot.wavelet, shot.rec = [], np.zeros((0, 1), np.float32), None
     k_, j_, i_ = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     bump = np.exp(-(((i_ - 40) / 4.0) ** 2 + ((j_ - 30) / 3.0) ** 2
                     + ((k_ - 33) / 5.0) ** 2)).astype(np.float32)
@@ -145,13 +145,15 @@ def test_energy_conserved_with_damping_off(W):
     sh.write(W.WAVE_FIELD_UPREV, bump)
     e = [sh.energy()]
     # the device energy equals the oracle's float64 energy of the same fields
-    vp64, _ = oracle.vp(shot.vel, shot.dt)
+    # with the float32 vp the scheme runs with (sum order differs: 1e-11)
+    _, vp32 = oracle.vp(shot.vel, shot.dt)
+    vp64 = vp32.astype(np.float64)
     for _ in range(5):
         sh.step(60)
         e.append(sh.energy())
     u, up = sh.read(W.WAVE_FIELD_U), sh.read(W.WAVE_FIELD_UPREV)
     eo = oracle.energy(vp64, u, up, shot.dx, shot.dy, shot.dz)
-    assert abs(e[-1] - eo) <= 1e-12 * abs(eo)
+    assert abs(e[-1] - eo) <= 1e-11 * abs(eo)
     e = np.array(e)
     drift = np.abs(e - e[0]).max() / e[0]
     say(f"float32 fields, float64 energy: max relative drift over 300 steps {drift:.3e}")
@@ -170,19 +172,40 @@ def test_c2_full_size_few_steps_bitwise(W):
 
 
 def test_long_run_medium_grid_vs_oracles(W):
+    """500 steps in 100-step segments: exact against the float32 oracle, and
+    within 1e-5 relative L2 of the float64 oracle at every checkpoint."""
     shot = synth.config_small_layered(128, 112, 96, 20, 500, seed=41)
     c = (64, 56, 25)
     shot.src = [c]
     shot.wavelet = synth.ricker(500, shot.dt)[None, :]
     shot.rec = synth.receiver_line(128, 56, 25)
     say("case long run 128x112x96 500 steps")
-    g = gpu_run(W, shot, 500)
-    o = oracle.run_shot(shot, precision="f32")
-    assert_same(g, o, "long run")
+    sh = W.shot_from_synth(shot, max_steps=500)
+    st64 = None
+    peak = 0.0
+    rows = []
+    for seg in range(5):
+        sh.step(100)
+        g = sh.read(W.WAVE_FIELD_U)
+        o = oracle.run_shot(shot, steps=100, precision="f64", state=st64, n0=100 * seg)
+        st64 = dict(u=o["u"], u_prev=o["u_prev"], phi=o["phi"])
+        nrm = float(np.linalg.norm(o["u"]))
+        peak = max(peak, nrm)
+        err = float(np.linalg.norm(g - o["u"]))
+        rows.append((100 * (seg + 1), nrm, err))
+        say(f"  step {100 * (seg + 1)}: |u| {nrm:.3e} rel L2 {err / nrm:.3e} "
+            f"err/peak {err / peak:.3e}")
+    traces = sh.traces()
+    gu = sh.read(W.WAVE_FIELD_U)
+    sh.close()
+    o32 = oracle.run_shot(shot, precision="f32")
+    assert np.array_equal(gu, o32["u"]) and np.array_equal(traces, o32["traces"])
     o64 = oracle.run_shot(shot, precision="f64")
-    eu, et = rel_l2(g["u"], o64["u"]), rel_l2(g["traces"], o64["traces"])
-    say(f"500 steps rel L2 vs fp64: field {eu:.3e} traces {et:.3e}")
-    assert eu <= 1e-5 and et <= 1e-5
+    et = rel_l2(traces, o64["traces"])
+    say(f"500 steps traces rel L2 vs fp64 {et:.3e}")
+    assert et <= 1e-5
+    for step, nrm, err in rows:
+        assert err <= 1e-5 * nrm, step
 
 
 def test_deterministic_and_restartable(W):

@@ -197,7 +197,7 @@ int wave_energy(wave_ctx *ctx, double *out);
  * waves_per_group (NW) give a 64 x (RY*NW) xy tile; zchunk is the number of
  * z planes one workgroup streams (0 = automatic).  Only compiled
  * combinations are accepted (EINVAL otherwise): (RY, NW) in
- * {(1,16), (1,8), (2,8), (2,16), (4,4)}; the default is (1,16).  Results do not depend on the
+ * {(1,16), (1,8), (2,8), (2,4)}; the default is (1,16).  Results do not depend on the
  * choice: every variant evaluates each point with the same operations in
  * the same order. */
 int wave_set_kernel(wave_ctx *ctx, int32_t variant, int32_t rows_per_wave,
@@ -218,6 +218,51 @@ double wave_sweep_bytes(const wave_ctx *ctx);
  * aligned) with a plain streaming kernel on `hip_stream`: the reference
  * point for measured memory bandwidth.  Does not wait. */
 int wave_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+/* ---- many shots per launch (batching) ------------------------------------------ */
+
+/* A batch advances several contexts together: every time step is one sweep
+ * launch covering all members (their tiles side by side in one grid) plus
+ * one launch for all members' sources and receivers.  Each member takes the
+ * same steps, with the same arithmetic, as under wave_step, so its results
+ * are identical to a run on its own.  Members must share the batch's storage
+ * type and its stream.  While a context is a member, wave_step on it returns
+ * WAVE_EINVAL; state access (read/write field, traces, energy) stays valid
+ * between runs. */
+typedef struct wave_batch wave_batch;
+
+/* Device bytes of the batch tables for up to max_shots members. */
+size_t wave_batch_bytes_required(int32_t max_shots);
+
+/* Create a batch.  storage is the members' wave_storage; the arena (256-byte
+ * aligned, >= wave_batch_bytes_required) holds the member tables and stays
+ * the caller's; hip_stream is the members' stream.  The batch keeps a
+ * stream of its own for its launches (ordered after and before the caller's
+ * stream with events) so that step blocks can be captured as graphs. */
+int wave_batch_create(int32_t storage, int32_t max_shots, void *dev_arena, size_t arena_bytes,
+                      void *hip_stream, wave_batch **out);
+
+/* Add ctx with `nsteps` steps still to take (EINVAL: wrong storage or
+ * stream, already a member, batch full, trace buffer too small). */
+int wave_batch_add(wave_batch *b, wave_ctx *ctx, int32_t nsteps);
+
+/* Remove ctx (it keeps its state and may step on its own again). */
+int wave_batch_remove(wave_batch *b, wave_ctx *ctx);
+
+/* Enqueue up to n steps for every member (a member stops when its own
+ * remaining count reaches 0) and return without waiting. */
+int wave_batch_run(wave_batch *b, int32_t n);
+
+/* Steps ctx still has to take in this batch. */
+int wave_batch_remaining(const wave_batch *b, const wave_ctx *ctx, int32_t *remaining);
+
+/* Tile shape of the batch sweep (same combinations as wave_set_kernel) and
+ * the number of steps captured into one graph (0 = plain launches). */
+int wave_batch_set_kernel(wave_batch *b, int32_t rows_per_wave, int32_t waves_per_group);
+int wave_batch_set_graph(wave_batch *b, int32_t steps_per_graph);
+
+/* Wait for the batch's work, release it (members stay valid contexts). */
+int wave_batch_free(wave_batch *b);
 
 /* ---- diagnostics ----------------------------------------------------------- */
 

@@ -72,6 +72,27 @@ struct InjectArgs {
   int32_t trace_row;
 };
 
+// One member of a batch (device table entry).  The sweep arguments' cur/nxt
+// pointers are chosen per step from u[] and the member's parity.
+struct BatchShot {
+  SweepArgs sa;
+  void* u[2];            // origins of the two u buffers
+  int32_t tiles_x, tiles_y, zchunk, pad0;
+  int64_t block_begin;   // first workgroup of this member in a batch launch
+  int32_t target;        // steps to take in the current run
+  int32_t pad1;
+  InjectArgs inj;        // sources/receivers (u, step, trace_row set per step)
+};
+
+// Per-member step state in device memory, advanced by the batch
+// source/receiver kernel after each sweep.
+struct BatchState {
+  int32_t cur;           // index of u^n in BatchShot::u
+  int32_t step;          // time level n
+  int32_t done;          // steps taken in the current run
+  int32_t trace_row;     // next trace row
+};
+
 struct EnergyArgs {
   const void* cur;      // u^n
   const void* prev;     // u^{n-1}
@@ -94,5 +115,11 @@ int auto_zchunk(int nx, int ny, int nz, int ry, int nw);
 hipError_t launch_inject_record(const InjectArgs& a, int storage, hipStream_t s);
 hipError_t launch_energy(const EnergyArgs& a, int storage, hipStream_t s);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+int stream_chunk_count(int nz, int w, int zchunk, bool damping);
+int stream_tiles_y(int ny, int ry, int nw);
+hipError_t launch_sweep_batch(const BatchShot* shots, BatchState* state, int nshots,
+                              int64_t total_blocks, int storage, int ry, int nw, hipStream_t s);
+hipError_t launch_inject_batch(const BatchShot* shots, BatchState* state, int nshots,
+                               int storage, hipStream_t s);
 
 }  // namespace wave

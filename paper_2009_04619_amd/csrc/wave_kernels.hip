@@ -157,16 +157,25 @@ __global__ __launch_bounds__(256) void k_sweep_direct(SweepArgs a) {
 //  * the centre plane of the tile plus its 4-wide x and y halos is staged in
 //    LDS (double-buffered: one barrier per plane), from which the x and y
 //    neighbours are read;
-//  * u_prev, vp and the halo of plane z+1 are prefetched while plane z is
-//    computed.
+//  * every operand of plane z+1 is prefetched while plane z is computed.
 // The loop is unrolled by 10 so every queue/buffer index is a compile-time
-// constant (no register moves, no modulo).  Blocks are remapped so that
-// consecutive tiles (which share halos) run on the same XCD and its L2.
-// Buffer resource over memory starting at p (gfx9 family: stride 0, no range
-// limit, dword 3 = 0x00020000).  Built from a wave-uniform pointer it lives in
-// scalar registers; accesses then take an unsigned 32-bit byte offset per lane.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_at(const void* p) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)0xffffffff,
+// constant (no modulo).  Blocks are remapped so that consecutive tiles
+// (which share halos) run on the same XCD and its L2.
+//
+// Damping layer: z chunks are cut at the layer faces (z caps are chunks of
+// their own), so whether a lane is a layer point is fixed for a workgroup.
+// Workgroups that touch no layer point run a loop without eta/phi.  The
+// others issue the eta/phi loads and the phi store unconditionally; a lane
+// outside the layer gets an offset beyond the buffer's range, which reads 0
+// and writes nothing, so it fetches no bytes, and eta = phi = 0 turns the
+// layer update into the inner one bit for bit.  Memory operations are thus
+// identical on every path, which keeps the prefetch overlapping the compute.
+
+// Buffer resource over memory starting at p (gfx9 family: stride 0, dword 3 =
+// 0x00020000).  Built from a wave-uniform pointer it lives in scalar
+// registers; accesses then take an unsigned 32-bit byte offset per lane.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_at(const void* p, uint32_t nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes,
                                            0x00020000);
 }
 __device__ __forceinline__ float bld_f32(__amdgpu_buffer_rsrc_t r, uint32_t boff) {
@@ -176,9 +185,50 @@ __device__ __forceinline__ void bst_f32(__amdgpu_buffer_rsrc_t r, uint32_t boff,
   __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)boff, 0, 0);
 }
 
-template <class S, int RY, int NW>
-__global__ __launch_bounds__(64 * NW) void k_sweep_stream(SweepArgs a, int tiles_x, int tiles_y,
-                                                          int zchunk) {
+// Offset that is out of range for every eta/phi resource (their range is one
+// plane, < 2 GiB); nearby offsets (+-4, +-pitch) stay out of range too.
+constexpr uint32_t kOOB = 0xC0000000u;
+
+struct ChunkInfo {
+  int zb, ze;
+  bool cap;  // every point of the chunk is in a z cap of the layer
+};
+
+// z chunks: without a layer, [c*zc, (c+1)*zc); with one, [0, w), then the
+// interior [w, nz-w) in pieces of zc, then [nz-w, nz).
+__host__ __device__ inline int chunk_count(int nz, int w, int zc, bool damp) {
+  if (!damp || w == 0) return (nz + zc - 1) / zc;
+  if (2 * w >= nz) return 1;
+  return 2 + (nz - 2 * w + zc - 1) / zc;
+}
+__device__ inline ChunkInfo chunk_of(int ch, int nz, int w, int zc, bool damp) {
+  ChunkInfo c;
+  if (!damp || w == 0) {
+    c.zb = ch * zc;
+    c.ze = min(c.zb + zc, nz);
+    c.cap = false;
+  } else if (2 * w >= nz) {
+    c.zb = 0;
+    c.ze = nz;
+    c.cap = true;
+  } else {
+    const int nin = (nz - 2 * w + zc - 1) / zc;
+    if (ch == 0) {
+      c.zb = 0; c.ze = w; c.cap = true;
+    } else if (ch == nin + 1) {
+      c.zb = nz - w; c.ze = nz; c.cap = true;
+    } else {
+      c.zb = w + (ch - 1) * zc;
+      c.ze = min(c.zb + zc, nz - w);
+      c.cap = false;
+    }
+  }
+  return c;
+}
+
+template <class S, int RY, int NW, bool LAYER>
+__device__ __forceinline__ void stream_tile(const SweepArgs& a, float (*sm)[(RY * NW + 2 * kR) * (kTX + 2 * kR) + 64],
+                                            int x0, int y0, int zb, int ze, bool cap) {
   using T = typename S::T;
   constexpr int TY = RY * NW;
   constexpr int LW = kTX + 2 * kR;   // LDS row length
@@ -187,23 +237,7 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_stream(SweepArgs a, int tiles
   constexpr int NYH = 2 * kR * kTX;  // y-halo elements per plane
   constexpr int NHALO = NYH + 2 * kR * TY;
   constexpr int HPT = (NHALO + NT - 1) / NT;
-  constexpr int LSZ = LR * LW + 64;  // + a dump row for idle halo lanes
   constexpr uint32_t ES = sizeof(T);
-  __shared__ float sm[2][LSZ];
-
-  // XCD-aware tile order: dispatch sends block b to XCD b % 8; give each XCD
-  // a contiguous range of logical tiles.
-  const int nb = gridDim.x, bid = blockIdx.x;
-  const int per = nb >> 3, rem = nb & 7, xcd = bid & 7, slot = bid >> 3;
-  const int logical = (xcd < rem) ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
-  const int tx = logical % tiles_x;
-  const int t2 = logical / tiles_x;
-  const int ty = t2 % tiles_y;
-  const int ch = t2 / tiles_y;
-  const int x0 = tx * kTX, y0 = ty * TY;
-  const int zb = ch * zchunk;
-  const int ze = min(zb + zchunk, a.nz);
-  if (zb >= ze) return;
 
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -211,6 +245,7 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_stream(SweepArgs a, int tiles
   const bool xin = x < a.nx;
   const int P = a.pitch;
   const int64_t Q = a.plane;
+  const uint32_t planeb = (uint32_t)(Q * 4);
   // Addresses: a uniform per-plane base at (x = 0, y = -4, z) plus an unsigned
   // 32-bit in-plane byte offset ((y + 4) * pitch + x) * size per lane.  Every
   // accessed cell has y >= -4, and x < 0 only on rows y >= 0, so the offset
@@ -261,21 +296,46 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_stream(SweepArgs a, int tiles
     ho[k] = (uint32_t)((gy + kR) * P + gx);
   }
 
+  // layer bookkeeping (LAYER only): per row, whether any lane is a layer
+  // point (uniform), and the byte offset of eta/phi, out of range for lanes
+  // that are not layer points (kOOB +- 4 and +- pitch stay out of range)
+  const bool xl = x < a.w || x >= a.nx - a.w;
+  const uint32_t p4 = (uint32_t)P * 4u;
+  bool rowl[RY];
+  uint32_t eo[RY];
+  if (LAYER) {
+    const bool tile_x = x0 < a.w || min(x0 + kTX, a.nx) > a.nx - a.w;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int y = y0 + wv * RY + r;
+      const bool yl = y < a.w || y >= a.ny - a.w;
+      rowl[r] = cap || yl || tile_x;
+      const bool lay = xin && y < a.ny && (cap || yl || xl);
+      eo[r] = lay ? ro[r] * 4u : kOOB;
+    }
+  }
+
   float q[10][RY];
   float pv[2][RY], vv[2][RY];
   float hh[2][HPT];
+  // LAYER: eta of the own column in a 10-slot ring like the u queue (at slot
+  // Sl, ring[(Sl + j) % 10] holds eta(z - 1 + j), j = 0..2, and slot
+  // (Sl + 3) % 10 receives the prefetch of eta(z + 2)); eta x/y neighbours and
+  // phi double-buffered by plane parity
+  float er[10][RY];
+  float ex0[2][RY], ex1[2][RY], ey0[2][RY], ey1[2][RY], ph[2][RY];
 
   // prologue: planes zb-4 .. zb+4 into queue slots 0..8; plane zb operands
 #pragma unroll
   for (int j = 0; j < 2 * kR + 1; ++j) {
-    const auto ru = rsrc_at(u + (int64_t)(zb - kR + j) * Q);
+    const auto ru = rsrc_at(u + (int64_t)(zb - kR + j) * Q, 0xffffffffu);
 #pragma unroll
     for (int r = 0; r < RY; ++r) q[j][r] = S::bld(ru, ro[r] * ES);
   }
   {
-    const auto ru = rsrc_at(u + (int64_t)zb * Q);
-    const auto rp = rsrc_at(un + (int64_t)zb * Q);
-    const auto rv = rsrc_at(vpa + (int64_t)zb * Q);
+    const auto ru = rsrc_at(u + (int64_t)zb * Q, 0xffffffffu);
+    const auto rp = rsrc_at(un + (int64_t)zb * Q, 0xffffffffu);
+    const auto rv = rsrc_at(vpa + (int64_t)zb * Q, 0xffffffffu);
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       pv[0][r] = S::bld(rp, ro[r] * ES);
@@ -283,11 +343,23 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_stream(SweepArgs a, int tiles
     }
 #pragma unroll
     for (int k = 0; k < HPT; ++k) hh[0][k] = S::bld(ru, ho[k] * ES);
+    if (LAYER) {
+      const float* e = a.eta - b4 + (int64_t)zb * Q;
+      const auto rem = rsrc_at(e - Q, planeb), re0 = rsrc_at(e, planeb), rep = rsrc_at(e + Q, planeb);
+      const auto rph = rsrc_at(a.phi - b4 + (int64_t)zb * Q, planeb);
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        er[0][r] = bld_f32(rem, eo[r]);
+        er[1][r] = bld_f32(re0, eo[r]);
+        er[2][r] = bld_f32(rep, eo[r]);
+        ex0[0][r] = bld_f32(re0, eo[r] - 4u);
+        ex1[0][r] = bld_f32(re0, eo[r] + 4u);
+        ey0[0][r] = bld_f32(re0, eo[r] - p4);
+        ey1[0][r] = bld_f32(re0, eo[r] + p4);
+        ph[0][r] = bld_f32(rph, eo[r]);
+      }
+    }
   }
-
-  const bool damp = a.damping != 0;
-  const bool xl = x < a.w || x >= a.nx - a.w;
-  const uint32_t P4 = (uint32_t)P * 4u;
 
   auto body = [&](auto SC, const int z) {
     constexpr int Sl = decltype(SC)::value;
@@ -299,10 +371,10 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_stream(SweepArgs a, int tiles
     {
       const int z1 = z + 1;                   // <= nz: a ghost plane at most
       const int z5 = min(z + 1 + kR, a.nz + kR - 1);
-      const auto ru1 = rsrc_at(u + (int64_t)z1 * Q);
-      const auto ru5 = rsrc_at(u + (int64_t)z5 * Q);
-      const auto rp1 = rsrc_at(un + (int64_t)z1 * Q);
-      const auto rv1 = rsrc_at(vpa + (int64_t)z1 * Q);
+      const auto ru1 = rsrc_at(u + (int64_t)z1 * Q, 0xffffffffu);
+      const auto ru5 = rsrc_at(u + (int64_t)z5 * Q, 0xffffffffu);
+      const auto rp1 = rsrc_at(un + (int64_t)z1 * Q, 0xffffffffu);
+      const auto rv1 = rsrc_at(vpa + (int64_t)z1 * Q, 0xffffffffu);
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
         q[(Sl + 9) % 10][r] = S::bld(ru5, ro[r] * ES);
@@ -311,6 +383,21 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_stream(SweepArgs a, int tiles
       }
 #pragma unroll
       for (int k = 0; k < HPT; ++k) hh[NB][k] = S::bld(ru1, ho[k] * ES);
+      if (LAYER) {
+        // eta planes z+1 and z+2 (z+2 <= nz: a ghost plane at most)
+        const float* e1 = a.eta - b4 + (int64_t)z1 * Q;
+        const auto re1 = rsrc_at(e1, planeb), re2 = rsrc_at(e1 + Q, planeb);
+        const auto rph1 = rsrc_at(a.phi - b4 + (int64_t)z1 * Q, planeb);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+          er[(Sl + 3) % 10][r] = bld_f32(re2, eo[r]);
+          ex0[NB][r] = bld_f32(re1, eo[r] - 4u);
+          ex1[NB][r] = bld_f32(re1, eo[r] + 4u);
+          ey0[NB][r] = bld_f32(re1, eo[r] - p4);
+          ey1[NB][r] = bld_f32(re1, eo[r] + p4);
+          ph[NB][r] = bld_f32(rph1, eo[r]);
+        }
+      }
     }
     // stage the centre plane and its halo
     float* s = sm[B];
@@ -320,8 +407,8 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_stream(SweepArgs a, int tiles
     for (int k = 0; k < HPT; ++k) s[hl[k]] = hh[B][k];
     __syncthreads();
 
-    const bool zl = z < a.w || z >= a.nz - a.w;
-    const auto rn = rsrc_at(un + (int64_t)z * Q);
+    const auto rn = rsrc_at(un + (int64_t)z * Q, 0xffffffffu);
+    const auto rph = rsrc_at(a.phi - b4 + (int64_t)z * Q, planeb);
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       const int y = y0 + wv * RY + r;
@@ -341,24 +428,23 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_stream(SweepArgs a, int tiles
                              (q[(Sl + kR + m) % 10][r] - c) + (q[(Sl + kR - m) % 10][r] - c), lap);
       const float pu = pv[B][r];
       const float vp = vv[B][r];
-      const bool lay = damp && xin && yin && (zl || y < a.w || y >= a.ny - a.w || xl);
       float res;
-      if (lay) {
-        const float* ez = a.eta - b4 + (int64_t)z * Q;
-        const auto re = rsrc_at(ez);
-        const auto rem1 = rsrc_at(ez - Q);
-        const auto rep1 = rsrc_at(ez + Q);
-        const auto rph = rsrc_at(a.phi - b4 + (int64_t)z * Q);
-        const uint32_t o = ro[r] * 4u;
-        const float e = bld_f32(re, o);
-        const float ph = bld_f32(rph, o);
-        res = upd_layer(c, pu, vp, lap, e, ph);
-        bst_f32(rph, o,
-                upd_phi(ph, e, bld_f32(re, o + 4u) - bld_f32(re, o - 4u), row[1] - row[-1],
-                        bld_f32(re, o + P4) - bld_f32(re, o - P4), row[LW] - row[-LW],
-                        bld_f32(rep1, o) - bld_f32(rem1, o),
+      if (LAYER) {
+        // phi' is stored for every lane; lanes outside the layer have an
+        // out-of-range offset, so their store is dropped
+        float nph = 0.0f;
+        if (rowl[r]) {
+          const float e = er[(Sl + 1) % 10][r];
+          res = upd_layer(c, pu, vp, lap, e, ph[B][r]);
+          nph = upd_phi(ph[B][r], e, ex1[B][r] - ex0[B][r], row[1] - row[-1],
+                        ey1[B][r] - ey0[B][r], row[LW] - row[-LW],
+                        er[(Sl + 2) % 10][r] - er[Sl % 10][r],
                         q[(Sl + kR + 1) % 10][r] - q[(Sl + kR - 1) % 10][r], a.q[0], a.q[1],
-                        a.q[2]));
+                        a.q[2]);
+        } else {
+          res = upd_inner(c, pu, vp, lap);
+        }
+        bst_f32(rph, eo[r], nph);
       } else {
         res = upd_inner(c, pu, vp, lap);
       }
@@ -389,6 +475,118 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_stream(SweepArgs a, int tiles
     body(integral_constant<int, 8>{}, z + 8);
     if (z + 9 >= ze) break;
     body(integral_constant<int, 9>{}, z + 9);
+  }
+}
+
+// Occupancy target in wavefronts per SIMD for one-row tiles.
+#ifndef WAVE_STREAM_WAVES_PER_SIMD
+#define WAVE_STREAM_WAVES_PER_SIMD 6
+#endif
+template <class S, int RY, int NW>
+__global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) void k_sweep_stream(
+    SweepArgs a, int tiles_x, int tiles_y, int zchunk) {
+  constexpr int TY = RY * NW;
+  constexpr int LSZ = (TY + 2 * kR) * (kTX + 2 * kR) + 64;  // + a dump row
+  __shared__ float sm[2][LSZ];
+
+  // XCD-aware tile order: dispatch sends block b to XCD b % 8; give each XCD
+  // a contiguous range of logical tiles.
+  const int nb = gridDim.x, bid = blockIdx.x;
+  const int per = nb >> 3, rem = nb & 7, xcd = bid & 7, slot = bid >> 3;
+  const int logical = (xcd < rem) ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+  const int tx = logical % tiles_x;
+  const int t2 = logical / tiles_x;
+  const int ty = t2 % tiles_y;
+  const int ch = t2 / tiles_y;
+  const int x0 = tx * kTX, y0 = ty * TY;
+  const bool damp = a.damping != 0;
+  const ChunkInfo c = chunk_of(ch, a.nz, a.w, zchunk, damp);
+  if (c.zb >= c.ze) return;
+  const bool layer =
+      damp && (c.cap || x0 < a.w || min(x0 + kTX, a.nx) > a.nx - a.w || y0 < a.w ||
+               min(y0 + TY, a.ny) > a.ny - a.w);
+  if (layer)
+    stream_tile<S, RY, NW, true>(a, sm, x0, y0, c.zb, c.ze, c.cap);
+  else
+    stream_tile<S, RY, NW, false>(a, sm, x0, y0, c.zb, c.ze, false);
+}
+
+// ---- many shots per launch ---------------------------------------------------
+// One workgroup grid covers every member of a batch: the workgroup index (after
+// the same XCD-aware remap) is located in the members' block ranges, the
+// member's parity picks u^n and u^{n-1}, and the tile is swept exactly as in
+// a single-shot launch.  Members that have taken their steps for this run exit
+// at once, so a captured sequence of launches stays valid as members finish.
+template <class S, int RY, int NW>
+__global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) void k_sweep_batch(
+    const BatchShot* __restrict__ shots, const BatchState* __restrict__ state, int nshots) {
+  constexpr int TY = RY * NW;
+  constexpr int LSZ = (TY + 2 * kR) * (kTX + 2 * kR) + 64;
+  __shared__ float sm[2][LSZ];
+  const int nb = gridDim.x, bid = blockIdx.x;
+  const int per = nb >> 3, rem = nb & 7, xcd = bid & 7, slot = bid >> 3;
+  const int64_t logical = (xcd < rem) ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+  // member of this workgroup: last member whose first block is <= logical
+  int lo = 0, hi = nshots - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (shots[mid].block_begin <= logical) lo = mid; else hi = mid - 1;
+  }
+  const BatchShot& b = shots[lo];
+  const BatchState st = state[lo];
+  if (st.done >= b.target) return;
+  SweepArgs a = b.sa;
+  a.cur = b.u[st.cur];
+  a.nxt = b.u[st.cur ^ 1];
+  const int64_t local = logical - b.block_begin;
+  const int tx = (int)(local % b.tiles_x);
+  const int64_t t2 = local / b.tiles_x;
+  const int ty = (int)(t2 % b.tiles_y);
+  const int ch = (int)(t2 / b.tiles_y);
+  const int x0 = tx * kTX, y0 = ty * TY;
+  const bool damp = a.damping != 0;
+  const ChunkInfo c = chunk_of(ch, a.nz, a.w, b.zchunk, damp);
+  if (c.zb >= c.ze) return;
+  const bool layer =
+      damp && (c.cap || x0 < a.w || min(x0 + kTX, a.nx) > a.nx - a.w || y0 < a.w ||
+               min(y0 + TY, a.ny) > a.ny - a.w);
+  if (layer)
+    stream_tile<S, RY, NW, true>(a, sm, x0, y0, c.zb, c.ze, c.cap);
+  else
+    stream_tile<S, RY, NW, false>(a, sm, x0, y0, c.zb, c.ze, false);
+}
+
+// One workgroup per member: source add, receiver sample, then the member's
+// time level advances (rotation = parity flip).
+template <class S>
+__global__ __launch_bounds__(256) void k_inject_batch(const BatchShot* __restrict__ shots,
+                                                      BatchState* __restrict__ state) {
+  using T = typename S::T;
+  const BatchShot& b = shots[blockIdx.x];
+  const BatchState st = state[blockIdx.x];
+  if (st.done >= b.target) return;
+  const InjectArgs& a = b.inj;
+  T* u = static_cast<T*>(b.u[st.cur ^ 1]);
+  if (threadIdx.x == 0) {
+    for (int s = 0; s < a.nsrc; ++s) {
+      const int64_t p = a.src_off[s];
+      const float wv = (st.step < a.max_steps) ? a.wavelet[(int64_t)s * a.max_steps + st.step] : 0.0f;
+      S::st(u, p, __builtin_fmaf(a.vp[p], wv, S::ld(u, p)));
+    }
+  }
+  __syncthreads();
+  if (a.nrec > 0) {
+    double* row = a.traces + (int64_t)st.trace_row * a.nrec;
+    for (int r = threadIdx.x; r < a.nrec; r += blockDim.x) row[r] = (double)S::ld(u, a.rec_off[r]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    BatchState ns = st;
+    ns.cur ^= 1;
+    ns.step += 1;
+    ns.done += 1;
+    if (a.nrec > 0) ns.trace_row += 1;
+    state[blockIdx.x] = ns;
   }
 }
 
@@ -477,10 +675,22 @@ __global__ __launch_bounds__(1024) void k_energy_final(double* partial, int64_t 
 }
 
 // ---- plain copy (bandwidth reference) -------------------------------------------
+// Each thread moves four 16-byte words, all four loads issued before the
+// stores, so every wavefront keeps 4 KB in flight.
 __global__ __launch_bounds__(256) void k_stream_copy(const float4* __restrict__ s,
                                                      float4* __restrict__ d, int64_t n) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) d[i] = s[i];
+  const int64_t base = (int64_t)blockIdx.x * (256 * 4) + threadIdx.x;
+  float4 v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t i = base + k * 256;
+    if (i < n) v[k] = s[i];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t i = base + k * 256;
+    if (i < n) d[i] = v[k];
+  }
 }
 
 template <class S>
@@ -496,7 +706,7 @@ hipError_t sweep_stream_t(const SweepArgs& a, int zchunk, hipStream_t st) {
   constexpr int TY = RY * NW;
   const int tiles_x = (a.nx + kTX - 1) / kTX;
   const int tiles_y = (a.ny + TY - 1) / TY;
-  const int chunks = (a.nz + zchunk - 1) / zchunk;
+  const int chunks = chunk_count(a.nz, a.w, zchunk, a.damping != 0);
   const int64_t blocks = (int64_t)tiles_x * tiles_y * chunks;
   if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_sweep_stream<S, RY, NW>), dim3((unsigned)blocks), dim3(64 * NW), 0, st, a,
@@ -509,8 +719,7 @@ hipError_t sweep_stream_s(const SweepArgs& a, int ry, int nw, int zchunk, hipStr
   if (ry == 1 && nw == 16) return sweep_stream_t<S, 1, 16>(a, zchunk, st);
   if (ry == 1 && nw == 8) return sweep_stream_t<S, 1, 8>(a, zchunk, st);
   if (ry == 2 && nw == 8) return sweep_stream_t<S, 2, 8>(a, zchunk, st);
-  if (ry == 2 && nw == 16) return sweep_stream_t<S, 2, 16>(a, zchunk, st);
-  if (ry == 4 && nw == 4) return sweep_stream_t<S, 4, 4>(a, zchunk, st);
+  if (ry == 2 && nw == 4) return sweep_stream_t<S, 2, 4>(a, zchunk, st);
   return hipErrorInvalidValue;
 }
 
@@ -518,7 +727,7 @@ hipError_t sweep_stream_s(const SweepArgs& a, int ry, int nw, int zchunk, hipStr
 
 bool stream_config_supported(int ry, int nw) {
   return (ry == 1 && nw == 16) || (ry == 1 && nw == 8) || (ry == 2 && nw == 8) ||
-         (ry == 2 && nw == 16) || (ry == 4 && nw == 4);
+         (ry == 2 && nw == 4);
 }
 
 int auto_zchunk(int nx, int ny, int nz, int ry, int nw) {
@@ -581,11 +790,59 @@ hipError_t launch_energy(const EnergyArgs& a, int storage, hipStream_t s) {
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
   const int64_t n = (int64_t)(bytes / 16);
   if (n == 0) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 256 * 16) blocks = 256 * 16;
+  const int64_t blocks = (n + 1023) / 1024;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, s,
                      static_cast<const float4*>(src), static_cast<float4*>(dst), n);
   return hipGetLastError();
 }
 
+int stream_chunk_count(int nz, int w, int zchunk, bool damping) {
+  return chunk_count(nz, w, zchunk, damping);
+}
+
+int stream_tiles_y(int ny, int ry, int nw) { return (ny + ry * nw - 1) / (ry * nw); }
+
+template <class S>
+hipError_t sweep_batch_s(const BatchShot* shots, BatchState* state, int nshots, int64_t blocks,
+                         int ry, int nw, hipStream_t st) {
+  if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 g((unsigned)blocks);
+#define WAVE_BATCH_CASE(RY_, NW_)                                                             \
+  if (ry == RY_ && nw == NW_) {                                                               \
+    hipLaunchKernelGGL((k_sweep_batch<S, RY_, NW_>), g, dim3(64 * NW_), 0, st, shots, state, \
+                       nshots);                                                               \
+    return hipGetLastError();                                                                 \
+  }
+  WAVE_BATCH_CASE(1, 16)
+  WAVE_BATCH_CASE(1, 8)
+  WAVE_BATCH_CASE(2, 8)
+  WAVE_BATCH_CASE(2, 4)
+#undef WAVE_BATCH_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep_batch(const BatchShot* shots, BatchState* state, int nshots,
+                              int64_t total_blocks, int storage, int ry, int nw, hipStream_t s) {
+  switch (storage) {
+    case 0: return sweep_batch_s<StF32>(shots, state, nshots, total_blocks, ry, nw, s);
+    case 1: return sweep_batch_s<StBF16>(shots, state, nshots, total_blocks, ry, nw, s);
+    case 2: return sweep_batch_s<StF16>(shots, state, nshots, total_blocks, ry, nw, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_inject_batch(const BatchShot* shots, BatchState* state, int nshots, int storage,
+                               hipStream_t s) {
+  if (nshots <= 0) return hipSuccess;
+  switch (storage) {
+    case 0: hipLaunchKernelGGL(k_inject_batch<StF32>, dim3(nshots), dim3(256), 0, s, shots, state); break;
+    case 1: hipLaunchKernelGGL(k_inject_batch<StBF16>, dim3(nshots), dim3(256), 0, s, shots, state); break;
+    case 2: hipLaunchKernelGGL(k_inject_batch<StF16>, dim3(nshots), dim3(256), 0, s, shots, state); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace wave
+

@@ -151,6 +151,7 @@ float host_from_bf16(uint16_t b) {
 }  // namespace
 
 struct wave_ctx {
+  wave_batch* batch;      // non-null while a batch member
   wave_desc d;
   Layout L;
   ArenaPlan plan;
@@ -267,12 +268,134 @@ int download_u(wave_ctx* c, int idx, float* host) {
   return WAVE_OK;
 }
 
+// Sweep arguments of a context (cur/nxt are set per step).
+wave::SweepArgs sweep_args(const wave_ctx* c) {
+  const Layout& L = c->L;
+  wave::SweepArgs sa;
+  sa.cur = nullptr;
+  sa.nxt = nullptr;
+  sa.vp = c->f_origin(c->plan.vp);
+  sa.eta = c->f_origin(c->plan.eta);
+  sa.phi = c->f_origin(c->plan.phi);
+  sa.nx = L.nx;
+  sa.ny = L.ny;
+  sa.nz = L.nz;
+  sa.w = c->d.w;
+  sa.pitch = L.pitch;
+  sa.plane = L.plane;
+  memcpy(sa.c, c->c, sizeof(sa.c));
+  memcpy(sa.q, c->q, sizeof(sa.q));
+  sa.damping = c->damp ? 1 : 0;
+  return sa;
+}
+
+// Source/receiver arguments of a context (u, step, trace_row set per step).
+wave::InjectArgs inject_args(const wave_ctx* c) {
+  wave::InjectArgs ia;
+  ia.u = nullptr;
+  ia.vp = c->f_origin(c->plan.vp);
+  ia.nsrc = c->nsrc;
+  ia.src_off = reinterpret_cast<const int64_t*>(c->at(c->plan.src_off));
+  ia.wavelet = reinterpret_cast<const float*>(c->at(c->plan.wavelet));
+  ia.max_steps = std::max(c->d.max_steps, 1);
+  ia.step = 0;
+  ia.nrec = c->nrec;
+  ia.rec_off = reinterpret_cast<const int64_t*>(c->at(c->plan.rec_off));
+  ia.traces = c->nrec > 0 ? reinterpret_cast<double*>(c->at(c->plan.traces)) : nullptr;
+  ia.trace_row = 0;
+  return ia;
+}
+
 int64_t offset_of(const wave_ctx* c, int i, int j, int k) {
   return (int64_t)k * c->L.plane + (int64_t)j * c->L.pitch + i;
 }
 
 bool in_grid(const wave_ctx* c, int i, int j, int k) {
   return i >= 0 && i < c->d.nx && j >= 0 && j < c->d.ny && k >= 0 && k < c->d.nz;
+}
+
+}  // namespace
+
+struct wave_batch {
+  int32_t storage;
+  int32_t max_shots;
+  hipStream_t user_stream;   // the members' stream
+  hipStream_t stream;        // the batch's own stream (graphs can be captured on it)
+  hipEvent_t ev_in, ev_out;
+  char* arena;
+  size_t arena_bytes;
+  wave::BatchShot* d_shots;
+  wave::BatchState* d_state;
+  std::vector<wave_ctx*> members;
+  std::vector<int32_t> remaining;
+  std::vector<wave::BatchShot> h_shots;
+  std::vector<wave::BatchState> h_state;
+  int ry, nw;
+  int64_t total_blocks;
+  bool layout_dirty;          // membership or tile shape changed
+  int graph_steps;            // steps per captured graph (0 = plain launches)
+  hipGraphExec_t gexec;
+  bool graph_valid;
+  bool broken;
+};
+
+namespace {
+
+size_t batch_table_bytes(int32_t max_shots, size_t* state_off) {
+  const size_t a = align_up((size_t)std::max(max_shots, 1) * sizeof(wave::BatchShot), 256);
+  if (state_off) *state_off = a;
+  return a + align_up((size_t)std::max(max_shots, 1) * sizeof(wave::BatchState), 256);
+}
+
+int batch_fail(wave_batch* b, hipError_t e, const char* what) {
+  if (b) b->broken = true;
+  return fail(WAVE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define BCHK(b, expr, what)                                        \
+  do {                                                             \
+    hipError_t _e = (expr);                                        \
+    if (_e != hipSuccess) return batch_fail((b), _e, (what));      \
+  } while (0)
+
+#define CHECK_BATCH(b)                                                                      \
+  do {                                                                                      \
+    if (!(b)) return fail(WAVE_EINVAL, "batch is NULL");                                    \
+    if ((b)->broken) return fail(WAVE_ESTATE, "batch broken by an earlier device error");  \
+  } while (0)
+
+// Rebuild the member tables (static part); targets are filled per run.
+void batch_layout(wave_batch* b) {
+  b->h_shots.resize(b->members.size());
+  int64_t begin = 0;
+  const int ty = b->ry * b->nw;
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    wave_ctx* c = b->members[i];
+    wave::BatchShot& e = b->h_shots[i];
+    memset(&e, 0, sizeof(e));
+    e.sa = sweep_args(c);
+    e.u[0] = c->u_origin(0);
+    e.u[1] = c->u_origin(1);
+    e.tiles_x = (c->L.nx + wave::kTX - 1) / wave::kTX;
+    e.tiles_y = (c->L.ny + ty - 1) / ty;
+    e.zchunk = c->zchunk > 0 ? c->zchunk : wave::auto_zchunk(c->L.nx, c->L.ny, c->L.nz, b->ry, b->nw);
+    const int chunks = wave::stream_chunk_count(c->L.nz, c->d.w, e.zchunk, c->damp);
+    e.block_begin = begin;
+    begin += (int64_t)e.tiles_x * e.tiles_y * chunks;
+    e.target = 0;
+    e.inj = inject_args(c);
+  }
+  b->total_blocks = begin;
+  b->layout_dirty = false;
+  b->graph_valid = false;
+}
+
+hipError_t batch_launch_step(wave_batch* b) {
+  const int n = (int)b->members.size();
+  hipError_t e = wave::launch_sweep_batch(b->d_shots, b->d_state, n, b->total_blocks, b->storage,
+                                          b->ry, b->nw, b->stream);
+  if (e != hipSuccess) return e;
+  return wave::launch_inject_batch(b->d_shots, b->d_state, n, b->storage, b->stream);
 }
 
 }  // namespace
@@ -354,6 +477,7 @@ int wave_alloc(const wave_desc* d, const float* vel, const float* eta, void* dev
     return fail(WAVE_EUNSTABLE, "stability number " + std::to_string(stab) + " > 1 (reduce dt)");
 
   wave_ctx* c = new wave_ctx();
+  c->batch = nullptr;
   c->d = *d;
   c->L = wave::make_layout(d->nx, d->ny, d->nz);
   c->plan = plan;
@@ -419,6 +543,7 @@ int wave_alloc(const wave_desc* d, const float* vel, const float* eta, void* dev
 
 int wave_free(wave_ctx* c) {
   if (!c) return WAVE_OK;
+  if (c->batch) (void)wave_batch_remove(c->batch, c);
   if (!c->broken) (void)hipStreamSynchronize(c->stream);
   for (auto& ev : c->events) {
     (void)hipEventDestroy(ev.first);
@@ -471,34 +596,16 @@ int wave_record(wave_ctx* c, const int32_t* ijk, int32_t nrec) {
 
 int wave_step(wave_ctx* c, int32_t n) {
   CHECK_CTX(c);
+  if (c->batch) return fail(WAVE_EINVAL, "context is a batch member (step it with wave_batch_run)");
   if (n < 0) return fail(WAVE_EINVAL, "n < 0");
   if (c->nrec > 0 && (int64_t)c->trace_count + n > c->d.max_steps)
     return fail(WAVE_EINVAL, "trace buffer would overflow max_steps");
   if (c->step + n > 0x7fffffff) return fail(WAVE_EINVAL, "step counter overflow");
   const Layout& L = c->L;
-  wave::SweepArgs sa;
-  sa.vp = c->f_origin(c->plan.vp);
-  sa.eta = c->f_origin(c->plan.eta);
-  sa.phi = c->f_origin(c->plan.phi);
-  sa.nx = L.nx;
-  sa.ny = L.ny;
-  sa.nz = L.nz;
-  sa.w = c->d.w;
-  sa.pitch = L.pitch;
-  sa.plane = L.plane;
-  memcpy(sa.c, c->c, sizeof(sa.c));
-  memcpy(sa.q, c->q, sizeof(sa.q));
-  sa.damping = c->damp ? 1 : 0;
+  wave::SweepArgs sa = sweep_args(c);
   const int zc = c->zchunk > 0 ? c->zchunk : wave::auto_zchunk(L.nx, L.ny, L.nz, c->ry, c->nw);
 
-  wave::InjectArgs ia;
-  ia.vp = sa.vp;
-  ia.nsrc = c->nsrc;
-  ia.src_off = reinterpret_cast<const int64_t*>(c->at(c->plan.src_off));
-  ia.wavelet = reinterpret_cast<const float*>(c->at(c->plan.wavelet));
-  ia.max_steps = std::max(c->d.max_steps, 1);
-  ia.nrec = c->nrec;
-  ia.rec_off = reinterpret_cast<const int64_t*>(c->at(c->plan.rec_off));
+  wave::InjectArgs ia = inject_args(c);
 
   for (int t = 0; t < n; ++t) {
     sa.cur = c->u_origin(c->cur);
@@ -689,6 +796,197 @@ int wave_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream)
     return fail(WAVE_EINVAL, "copy needs 16-byte aligned pointers and a multiple of 16 bytes");
   hipError_t e = wave::launch_stream_copy(dst, src, bytes, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return dev_fail(nullptr, e, "copy launch");
+  return WAVE_OK;
+}
+
+size_t wave_batch_bytes_required(int32_t max_shots) {
+  if (max_shots < 1 || max_shots > 65536) {
+    g_last_error = "max_shots outside [1, 65536]";
+    return 0;
+  }
+  return batch_table_bytes(max_shots, nullptr);
+}
+
+int wave_batch_create(int32_t storage, int32_t max_shots, void* dev_arena, size_t arena_bytes,
+                      void* hip_stream, wave_batch** out) {
+  if (!out) return fail(WAVE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (storage != WAVE_F32 && storage != WAVE_BF16 && storage != WAVE_F16)
+    return fail(WAVE_EINVAL, "unknown storage type");
+  if (max_shots < 1 || max_shots > 65536) return fail(WAVE_EINVAL, "max_shots outside [1, 65536]");
+  if (!dev_arena || ((uintptr_t)dev_arena & 255)) return fail(WAVE_EINVAL, "arena NULL or not 256-byte aligned");
+  size_t soff = 0;
+  const size_t need = batch_table_bytes(max_shots, &soff);
+  if (arena_bytes < need) return fail(WAVE_ENOMEM, "batch arena too small");
+  wave_batch* b = new wave_batch();
+  b->storage = storage;
+  b->max_shots = max_shots;
+  b->user_stream = static_cast<hipStream_t>(hip_stream);
+  b->arena = static_cast<char*>(dev_arena);
+  b->arena_bytes = arena_bytes;
+  b->d_shots = reinterpret_cast<wave::BatchShot*>(b->arena);
+  b->d_state = reinterpret_cast<wave::BatchState*>(b->arena + soff);
+  b->ry = 1;
+  b->nw = 16;
+  b->total_blocks = 0;
+  b->layout_dirty = true;
+  b->graph_steps = 0;
+  b->gexec = nullptr;
+  b->graph_valid = false;
+  b->broken = false;
+  hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    delete b;
+    return fail(WAVE_EDEVICE, std::string("batch stream/events: ") + hipGetErrorString(e));
+  }
+  *out = b;
+  return WAVE_OK;
+}
+
+int wave_batch_add(wave_batch* b, wave_ctx* c, int32_t nsteps) {
+  CHECK_BATCH(b);
+  CHECK_CTX(c);
+  if (c->batch) return fail(WAVE_EINVAL, "context already in a batch");
+  if (c->d.storage != b->storage) return fail(WAVE_EINVAL, "storage type differs from the batch's");
+  if (c->stream != b->user_stream) return fail(WAVE_EINVAL, "context stream differs from the batch's");
+  if ((int)b->members.size() >= b->max_shots) return fail(WAVE_EINVAL, "batch full");
+  if (nsteps < 0) return fail(WAVE_EINVAL, "nsteps < 0");
+  if (c->nrec > 0 && (int64_t)c->trace_count + nsteps > c->d.max_steps)
+    return fail(WAVE_EINVAL, "trace buffer would overflow max_steps");
+  if (c->step + nsteps > 0x7fffffff) return fail(WAVE_EINVAL, "step counter overflow");
+  b->members.push_back(c);
+  b->remaining.push_back(nsteps);
+  c->batch = b;
+  b->layout_dirty = true;
+  return WAVE_OK;
+}
+
+int wave_batch_remove(wave_batch* b, wave_ctx* c) {
+  CHECK_BATCH(b);
+  if (!c || c->batch != b) return fail(WAVE_EINVAL, "context is not a member");
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    if (b->members[i] == c) {
+      b->members.erase(b->members.begin() + i);
+      b->remaining.erase(b->remaining.begin() + i);
+      break;
+    }
+  }
+  c->batch = nullptr;
+  b->layout_dirty = true;
+  return WAVE_OK;
+}
+
+int wave_batch_remaining(const wave_batch* b, const wave_ctx* c, int32_t* remaining) {
+  if (!b || !c || !remaining) return fail(WAVE_EINVAL, "NULL argument");
+  for (size_t i = 0; i < b->members.size(); ++i)
+    if (b->members[i] == c) {
+      *remaining = b->remaining[i];
+      return WAVE_OK;
+    }
+  return fail(WAVE_EINVAL, "context is not a member");
+}
+
+int wave_batch_set_kernel(wave_batch* b, int32_t ry, int32_t nw) {
+  CHECK_BATCH(b);
+  if (!wave::stream_config_supported(ry, nw)) return fail(WAVE_EINVAL, "tile (rows_per_wave, waves) not compiled");
+  b->ry = ry;
+  b->nw = nw;
+  b->layout_dirty = true;
+  return WAVE_OK;
+}
+
+int wave_batch_set_graph(wave_batch* b, int32_t steps_per_graph) {
+  CHECK_BATCH(b);
+  if (steps_per_graph < 0 || steps_per_graph > 4096) return fail(WAVE_EINVAL, "steps_per_graph outside [0, 4096]");
+  b->graph_steps = steps_per_graph;
+  b->graph_valid = false;
+  return WAVE_OK;
+}
+
+int wave_batch_run(wave_batch* b, int32_t n) {
+  CHECK_BATCH(b);
+  if (n < 0) return fail(WAVE_EINVAL, "n < 0");
+  for (wave_ctx* c : b->members)
+    if (c->broken) return fail(WAVE_ESTATE, "a member context is broken");
+  const size_t nm = b->members.size();
+  if (nm == 0 || n == 0) return WAVE_OK;
+  if (b->layout_dirty) batch_layout(b);
+  // per-run targets and start state
+  int32_t steps = 0;
+  b->h_state.resize(nm);
+  for (size_t i = 0; i < nm; ++i) {
+    wave_ctx* c = b->members[i];
+    const int32_t t = std::min(b->remaining[i], n);
+    b->h_shots[i].target = t;
+    b->h_state[i].cur = c->cur;
+    b->h_state[i].step = (int32_t)c->step;
+    b->h_state[i].done = 0;
+    b->h_state[i].trace_row = c->trace_count;
+    steps = std::max(steps, t);
+  }
+  if (steps == 0) return WAVE_OK;
+  // order after the caller's stream, upload tables, launch
+  BCHK(b, hipEventRecord(b->ev_in, b->user_stream), "hipEventRecord");
+  BCHK(b, hipStreamWaitEvent(b->stream, b->ev_in, 0), "hipStreamWaitEvent");
+  BCHK(b, hipMemcpyAsync(b->d_shots, b->h_shots.data(), nm * sizeof(wave::BatchShot), hipMemcpyHostToDevice, b->stream),
+       "hipMemcpyAsync");
+  BCHK(b, hipMemcpyAsync(b->d_state, b->h_state.data(), nm * sizeof(wave::BatchState), hipMemcpyHostToDevice, b->stream),
+       "hipMemcpyAsync");
+  // the host copies are pageable: wait so the vectors may change afterwards
+  BCHK(b, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  int32_t left = steps;
+  if (b->graph_steps > 0 && steps >= b->graph_steps) {
+    if (!b->graph_valid) {
+      if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+      }
+      hipGraph_t g = nullptr;
+      BCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+      hipError_t e = hipSuccess;
+      for (int t = 0; t < b->graph_steps && e == hipSuccess; ++t) e = batch_launch_step(b);
+      hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+      if (e != hipSuccess) return batch_fail(b, e, "batch launch during capture");
+      if (e2 != hipSuccess) return batch_fail(b, e2, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return batch_fail(b, e, "hipGraphInstantiate");
+      b->graph_valid = true;
+    }
+    while (left >= b->graph_steps) {
+      BCHK(b, hipGraphLaunch(b->gexec, b->stream), "hipGraphLaunch");
+      left -= b->graph_steps;
+    }
+  }
+  for (; left > 0; --left) {
+    hipError_t e = batch_launch_step(b);
+    if (e != hipSuccess) return batch_fail(b, e, "batch launch");
+  }
+  BCHK(b, hipEventRecord(b->ev_out, b->stream), "hipEventRecord");
+  BCHK(b, hipStreamWaitEvent(b->user_stream, b->ev_out, 0), "hipStreamWaitEvent");
+  // host mirrors of each member's state after its `target` steps
+  for (size_t i = 0; i < nm; ++i) {
+    wave_ctx* c = b->members[i];
+    const int32_t t = b->h_shots[i].target;
+    if (t & 1) c->cur = 1 - c->cur;
+    c->step += t;
+    if (c->nrec > 0) c->trace_count += t;
+    b->remaining[i] -= t;
+  }
+  return WAVE_OK;
+}
+
+int wave_batch_free(wave_batch* b) {
+  if (!b) return WAVE_OK;
+  if (!b->broken) (void)hipStreamSynchronize(b->stream);
+  for (wave_ctx* c : b->members) c->batch = nullptr;
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  (void)hipEventDestroy(b->ev_in);
+  (void)hipEventDestroy(b->ev_out);
+  (void)hipStreamDestroy(b->stream);
+  delete b;
   return WAVE_OK;
 }
 

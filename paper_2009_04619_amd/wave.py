@@ -36,6 +36,9 @@ EXPORTED = [
     "wave_step_count", "wave_read_field", "wave_write_field", "wave_read_traces",
     "wave_energy", "wave_set_kernel", "wave_set_timing", "wave_read_timing",
     "wave_sweep_bytes", "wave_stream_copy", "wave_strerror", "wave_last_error",
+    "wave_batch_bytes_required", "wave_batch_create", "wave_batch_add", "wave_batch_remove",
+    "wave_batch_run", "wave_batch_remaining", "wave_batch_set_kernel", "wave_batch_set_graph",
+    "wave_batch_free",
 ]
 
 
@@ -84,6 +87,15 @@ def _load():
         "wave_read_timing": (C.c_int, [P, C.POINTER(f64), C.POINTER(i64)]),
         "wave_sweep_bytes": (f64, [P]),
         "wave_stream_copy": (C.c_int, [P, P, sz, P]),
+        "wave_batch_bytes_required": (sz, [i32]),
+        "wave_batch_create": (C.c_int, [i32, i32, P, sz, P, C.POINTER(P)]),
+        "wave_batch_add": (C.c_int, [P, P, i32]),
+        "wave_batch_remove": (C.c_int, [P, P]),
+        "wave_batch_run": (C.c_int, [P, i32]),
+        "wave_batch_remaining": (C.c_int, [P, P, C.POINTER(i32)]),
+        "wave_batch_set_kernel": (C.c_int, [P, i32, i32]),
+        "wave_batch_set_graph": (C.c_int, [P, i32]),
+        "wave_batch_free": (C.c_int, [P]),
         "wave_strerror": (C.c_char_p, [C.c_int]),
         "wave_last_error": (C.c_char_p, []),
     }
@@ -198,6 +210,48 @@ def wave_sweep_bytes(ctx) -> float:
 def wave_stream_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream_ptr: int) -> int:
     return int(_lib.wave_stream_copy(C.c_void_p(dst_ptr), C.c_void_p(src_ptr), nbytes,
                                      C.c_void_p(stream_ptr)))
+
+
+def wave_batch_bytes_required(max_shots: int) -> int:
+    return int(_lib.wave_batch_bytes_required(int(max_shots)))
+
+
+def wave_batch_create(storage: int, max_shots: int, arena_ptr: int, arena_bytes: int,
+                      stream_ptr: int):
+    b = C.c_void_p()
+    rc = _lib.wave_batch_create(int(storage), int(max_shots), C.c_void_p(arena_ptr), arena_bytes,
+                                C.c_void_p(stream_ptr), C.byref(b))
+    return int(rc), b
+
+
+def wave_batch_add(b, ctx, nsteps: int) -> int:
+    return int(_lib.wave_batch_add(b, ctx, int(nsteps)))
+
+
+def wave_batch_remove(b, ctx) -> int:
+    return int(_lib.wave_batch_remove(b, ctx))
+
+
+def wave_batch_run(b, n: int) -> int:
+    return int(_lib.wave_batch_run(b, int(n)))
+
+
+def wave_batch_remaining(b, ctx):
+    r = C.c_int32()
+    rc = _lib.wave_batch_remaining(b, ctx, C.byref(r))
+    return int(rc), int(r.value)
+
+
+def wave_batch_set_kernel(b, rows_per_wave: int, waves_per_group: int) -> int:
+    return int(_lib.wave_batch_set_kernel(b, int(rows_per_wave), int(waves_per_group)))
+
+
+def wave_batch_set_graph(b, steps_per_graph: int) -> int:
+    return int(_lib.wave_batch_set_graph(b, int(steps_per_graph)))
+
+
+def wave_batch_free(b) -> int:
+    return int(_lib.wave_batch_free(b))
 
 
 def wave_strerror(status: int) -> str:
@@ -333,3 +387,56 @@ def shot_from_synth(s, storage="f32", damping=True, device="cuda:0", max_steps=N
     if nrec:
         sh.record(s.rec)
     return sh
+
+
+class Batch:
+    """Several `Shot`s advanced together (one sweep launch per step for all).
+
+    All members share the batch's storage type and the torch stream."""
+
+    def __init__(self, storage="f32", max_shots=64, device="cuda:0", stream=None):
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        n = wave_batch_bytes_required(max_shots)
+        if n == 0:
+            raise WaveError(WAVE_EINVAL, "wave_batch_bytes_required")
+        self.arena = torch.empty(n, dtype=torch.uint8, device=self.device)
+        st = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        rc, self.b = wave_batch_create(st, max_shots, self.arena.data_ptr(), n,
+                                       self.stream.cuda_stream)
+        _check(rc, "wave_batch_create")
+        self.members = []
+
+    def add(self, shot: "Shot", nsteps: int):
+        _check(wave_batch_add(self.b, shot.ctx, nsteps), "wave_batch_add")
+        self.members.append(shot)
+
+    def remove(self, shot: "Shot"):
+        _check(wave_batch_remove(self.b, shot.ctx), "wave_batch_remove")
+        self.members.remove(shot)
+
+    def run(self, n: int):
+        _check(wave_batch_run(self.b, n), "wave_batch_run")
+
+    def remaining(self, shot: "Shot") -> int:
+        rc, r = wave_batch_remaining(self.b, shot.ctx)
+        _check(rc, "wave_batch_remaining")
+        return r
+
+    def set_kernel(self, rows_per_wave=1, waves_per_group=16):
+        _check(wave_batch_set_kernel(self.b, rows_per_wave, waves_per_group), "wave_batch_set_kernel")
+
+    def set_graph(self, steps_per_graph: int):
+        _check(wave_batch_set_graph(self.b, steps_per_graph), "wave_batch_set_graph")
+
+    def close(self):
+        if getattr(self, "b", None):
+            wave_batch_free(self.b)
+            self.b = None
+            self.members = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,160 @@
+"""GPU batching: several shots advanced by one sweep launch per step.
+
+Every member must end bit for bit where it ends when stepped on its own
+(same per-point arithmetic, same order), whether the steps run as plain
+launches or as replays of a captured graph, and across membership changes.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def W():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU (run with -m 'not gpu' on CPU)")
+    from paper_2009_04619_amd import wave
+    return wave
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+SHAPES = [  # nx, ny, nz, w, steps, storage
+    (70, 45, 37, 5, 23),
+    (128, 48, 64, 8, 30),
+    (33, 90, 41, 4, 7),
+    (64, 64, 64, 16, 30),
+    (150, 20, 18, 3, 12),
+]
+
+
+def shots_for(shapes, seed0=100):
+    out = []
+    for q, (nx, ny, nz, w, steps) in enumerate(shapes):
+        out.append(synth.config_small_layered(nx, ny, nz, w, steps, seed=seed0 + q, nsrc=1 + q % 2))
+    return out
+
+
+def read_all(W, sh):
+    return dict(u=sh.read(W.WAVE_FIELD_U), u_prev=sh.read(W.WAVE_FIELD_UPREV),
+                phi=sh.read(W.WAVE_FIELD_PHI), traces=sh.traces(), n=sh.step_count)
+
+
+def solo(W, s, storage="f32"):
+    sh = W.shot_from_synth(s, storage=storage)
+    sh.step(s.steps)
+    r = read_all(W, sh)
+    sh.close()
+    return r
+
+
+def same(a, b, what):
+    assert a["n"] == b["n"], what
+    for k in ("u", "u_prev", "phi", "traces"):
+        assert a[k].shape == b[k].shape, (what, k)
+        assert np.array_equal(a[k], b[k]), (what, k, int((a[k] != b[k]).sum()))
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("graph", [0, 4])
+def test_batch_members_equal_solo_runs(W, storage, graph):
+    shots = shots_for(SHAPES)
+    say(f"case batch storage={storage} graph={graph}")
+    ref = [solo(W, s, storage) for s in shots]
+    b = W.Batch(storage=storage, max_shots=8)
+    b.set_graph(graph)
+    members = []
+    for s in shots:
+        sh = W.shot_from_synth(s, storage=storage)
+        b.add(sh, s.steps)
+        members.append(sh)
+    for n in (10, 1, 9, 20):          # uneven runs; members stop at their own count
+        b.run(n)
+    for s, sh in zip(shots, members):
+        assert b.remaining(sh) == 0
+    got = [read_all(W, sh) for sh in members]
+    for q, (g, r) in enumerate(zip(got, ref)):
+        same(g, r, f"member {q}")
+    b.close()
+    for sh in members:
+        sh.close()
+    # and one member against the oracle directly
+    o = oracle.run_shot(shots[1], precision="f32", storage=storage)
+    assert np.array_equal(got[1]["u"], o["u"]) and np.array_equal(got[1]["traces"], o["traces"])
+
+
+def test_graph_replays_match_plain_launches_across_runs(W):
+    shots = shots_for(SHAPES[:3], seed0=200)
+    for s in shots:
+        s.steps = 40
+        s.wavelet = np.ascontiguousarray(np.pad(s.wavelet, ((0, 0), (0, 40))))[:, :40]
+    say("case graph replay vs plain")
+    runs = {}
+    for graph in (0, 5):
+        b = W.Batch(max_shots=4)
+        b.set_graph(graph)
+        members = [W.shot_from_synth(s) for s in shots]
+        for s, sh in zip(shots, members):
+            b.add(sh, 40)
+        snaps = []
+        for _ in range(4):             # 4 runs of 10 steps: 2 graph replays each
+            b.run(10)
+            snaps.append([read_all(W, sh) for sh in members])   # host reads in between
+        runs[graph] = snaps
+        b.close()
+        for sh in members:
+            sh.close()
+    for t in range(4):
+        for q in range(3):
+            same(runs[5][t][q], runs[0][t][q], f"run {t} member {q}")
+
+
+def test_membership_changes(W):
+    shots = shots_for(SHAPES[:4], seed0=300)
+    say("case membership changes")
+    ref = [solo(W, s) for s in shots]
+    b = W.Batch(max_shots=4)
+    m = [W.shot_from_synth(s) for s in shots]
+    b.add(m[0], shots[0].steps)
+    b.add(m[1], shots[1].steps)
+    b.run(5)
+    b.add(m[2], shots[2].steps)       # joins while others are midway
+    b.run(3)
+    b.remove(m[1])                    # leaves midway, finishes on its own
+    m[1].step(shots[1].steps - 8)
+    b.add(m[3], shots[3].steps)
+    b.run(100)
+    for q in (0, 2, 3):
+        same(read_all(W, m[q]), ref[q], f"member {q}")
+    same(read_all(W, m[1]), ref[1], "member 1 (left)")
+    b.close()
+    for sh in m:
+        sh.close()
+
+
+def test_batch_error_paths(W):
+    s = shots_for(SHAPES[:1])[0]
+    b = W.Batch(storage="f32", max_shots=1)
+    sh = W.shot_from_synth(s)
+    other = W.shot_from_synth(s, storage="bf16")
+    assert W.wave_batch_add(b.b, other.ctx, 5) == W.WAVE_EINVAL      # storage differs
+    assert W.wave_batch_add(b.b, sh.ctx, s.steps + 1) == W.WAVE_EINVAL  # traces overflow
+    assert W.wave_batch_add(b.b, sh.ctx, 5) == W.WAVE_OK
+    assert W.wave_batch_add(b.b, sh.ctx, 5) == W.WAVE_EINVAL          # already a member
+    assert W.wave_step(sh.ctx, 1) == W.WAVE_EINVAL                    # stepped by the batch
+    assert W.wave_batch_set_kernel(b.b, 3, 3) == W.WAVE_EINVAL
+    assert W.wave_batch_run(b.b, -1) == W.WAVE_EINVAL
+    b.close()
+    assert W.wave_step(sh.ctx, 1) == W.WAVE_OK                        # free again
+    sh.close()
+    other.close()

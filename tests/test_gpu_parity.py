@@ -96,8 +96,8 @@ RAGGED = [
 ]
 
 KERNELS = [(W_, ry, nw, zc) for (W_, ry, nw, zc) in [
-    (0, 1, 16, 0), (1, 1, 16, 0), (1, 1, 8, 0), (1, 2, 8, 0), (1, 2, 16, 0), (1, 4, 4, 0),
-    (1, 1, 16, 5), (1, 2, 8, 7), (1, 1, 8, 1)]]
+    (0, 1, 16, 0), (1, 1, 16, 0), (1, 1, 8, 0), (1, 2, 8, 0), (1, 2, 4, 0),
+    (1, 1, 16, 5), (1, 2, 8, 7), (1, 1, 8, 1), (1, 2, 4, 3)]]
 
 
 @pytest.mark.parametrize("case", RAGGED, ids=lambda c: "x".join(map(str, c[:3])) + f"_w{c[3]}")

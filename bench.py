@@ -71,6 +71,106 @@ def copy_bandwidth(W, torch, nbytes=2 << 30, reps=10):
     return 2.0 * nbytes / (ms / 1e3) / 1e9
 
 
+def plain_rate(W, torch, n, w, storage, steps):
+    """One shot, plain launches, given storage: Gpoints/s and the sweep
+    kernel's algorithmic GB/s."""
+    import synth
+    shot = synth.config_c2(steps=steps + 20, n=n, w=w)
+    sh = W.shot_from_synth(shot, storage=storage, max_steps=steps + 20 + 50)
+    sh.step(20)
+    sh.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(sh.stream)
+    sh.step(steps)
+    e1.record(sh.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    sh.set_timing(True)
+    sh.step(50)
+    kms, k = sh.read_timing()
+    gbs = sh.sweep_bytes() / (kms / k / 1e3) / 1e9
+    sh.close()
+    log(f"[bench] {storage} {n}^3: {shot.points * steps / ms / 1e6:.1f} Gpt/s, sweep {gbs:.0f} GB/s")
+    return {"value": round(shot.points * steps / ms / 1e6, 3), "unit": "Gpoints/s",
+            "storage": storage, "steps": steps, "sweep_gbps_algorithmic": round(gbs, 1),
+            "frac": round(gbs / PEAK_HBM_GBS, 4)}
+
+
+def batched_rate(W, torch, count):
+    """`count` seeded shots (each axis uniform in {128, 144, .., 384}, 200-1000
+    steps, 20-cell layer) advanced together with captured step blocks and a
+    tuned tile, against the same shots run one at a time."""
+    import synth
+    shapes = synth.batch_shapes(count=count)
+    log(f"[bench] batched: building {count} shots")
+    shots = [synth.shot_from_shape(nx, ny, nz, st, seed, pert=0.0)
+             for (nx, ny, nz, st, seed) in shapes]
+    work = sum(s.points * s.steps for s in shots)
+    out = {"shots": count, "points_x_steps": work}
+    for storage in ("f32", "bf16"):
+        members = [W.shot_from_synth(s, storage=storage) for s in shots]
+        b = W.Batch(storage=storage, max_shots=count)
+        for s, m in zip(shots, members):
+            b.add(m, s.steps)
+        b.set_graph(10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cfg = b.tune(2)
+        b.run(max(s.steps for s in shots))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        b.close()
+        for m in members:
+            m.close()
+        out[f"batched_{storage}"] = {"value": round(work / dt / 1e9, 3), "unit": "Gpoints/s",
+                                     "seconds": round(dt, 3), "tile": list(cfg)}
+        log(f"[bench] batched {storage}: {work / dt / 1e9:.1f} Gpt/s ({dt:.2f} s)")
+    # the same shots one at a time, plain float32 launches
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in shots:
+        m = W.shot_from_synth(s)
+        m.step(s.steps)
+        m.sync()
+        m.close()
+    dt_alloc = time.perf_counter() - t0
+    # allocation and set-up are outside the batched timing: time them alone
+    t1 = time.perf_counter()
+    for s in shots:
+        W.shot_from_synth(s).close()
+    dt_setup = time.perf_counter() - t1
+    solo = max(dt_alloc - dt_setup, 1e-9)
+    out["one_at_a_time_f32"] = {"value": round(work / solo / 1e9, 3), "unit": "Gpoints/s",
+                                "seconds": round(solo, 3)}
+    log(f"[bench] one at a time f32: {work / solo / 1e9:.1f} Gpt/s ({solo:.2f} s)")
+    return out
+
+
+def serve_run(W, torch, count):
+    """Seeded Poisson stream (20 requests/s) of shots 96-512 per axis,
+    200-2000 steps, storage uniform over f32/bf16/f16, 240 GB budget."""
+    import synth
+    from paper_2009_04619_amd.serve import GpuExecutor, Request, Server, summarize
+    reqs = []
+    log(f"[bench] serve: building {count} requests")
+    for q, r in enumerate(synth.serve_requests(count=count)):
+        shot = synth.shot_from_shape(r["nx"], r["ny"], r["nz"], r["steps"], r["seed"], pert=0.0)
+        reqs.append(Request(rid=q, arrival=r["t"], shot=shot,
+                            storage=["f32", "bf16", "f16"][r["storage"]]))
+    offered = sum(r.points * r.shot.steps for r in reqs) / max(reqs[-1].arrival, 1e-9)
+    ex = GpuExecutor(graph_steps=10)
+    srv = Server(ex, budget_bytes=240 * 10 ** 9, block_steps=50)
+    t0 = time.perf_counter()
+    done = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    ex.close()
+    out = summarize(done, wall)
+    out["offered_gpoints_per_s"] = round(offered / 1e9, 3)
+    out["arrival_rate_per_s"] = 20.0
+    log(f"[bench] serve: {out}")
+    return out
+
+
 def cpu_baseline(shot, budget_s: float):
     """The float64 oracle as it stands on the host cores, on a bounded number
     of steps of the same grid (calibrated to about `budget_s` seconds)."""
@@ -112,6 +212,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the bf16, batched and serving measurements")
+    ap.add_argument("--batch-shots", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=64)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -166,6 +270,12 @@ def main():
     sh.close()
     del sh
 
+    extras = None
+    if not args.no_extras:
+        extras = {"bf16_plain": plain_rate(W, torch, args.n, args.w, "bf16", 200),
+                  "batched": batched_rate(W, torch, args.batch_shots),
+                  "serve": serve_run(W, torch, args.serve_requests)}
+
     copy_gbs = None if args.no_copy else copy_bandwidth(W, torch)
     if copy_gbs:
         log(f"[bench] stream copy {copy_gbs:.0f} GB/s")
@@ -198,6 +308,7 @@ def main():
                      "kernel": "k_sweep_stream", "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_kernel_ms": round(avg_ms, 5)},
         "copy_gbps": None if copy_gbs is None else round(copy_gbs, 1),
+        "extras": extras,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

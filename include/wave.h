@@ -203,6 +203,15 @@ int wave_energy(wave_ctx *ctx, double *out);
 int wave_set_kernel(wave_ctx *ctx, int32_t variant, int32_t rows_per_wave,
                     int32_t waves_per_group, int32_t zchunk);
 
+/* Autotuner: advance the simulation by `trial_steps` real steps under each
+ * compiled tile shape and a few z-chunk lengths (every candidate computes
+ * identical results, so the trials are ordinary steps of the run), time each
+ * with HIP events, and keep the fastest.  Takes candidates x trial_steps
+ * steps in total; *chosen receives {rows_per_wave, waves_per_group, zchunk}
+ * (may be NULL).  Synchronises.  EINVAL if the steps would overflow the
+ * trace buffer. */
+int wave_tune(wave_ctx *ctx, int32_t trial_steps, int32_t chosen[3]);
+
 /* When on, wave_step brackets every sweep-kernel launch with HIP events on
  * the context stream; wave_read_timing returns the summed kernel time (ms)
  * and the launch count since timing was switched on, and synchronises. */
@@ -260,6 +269,10 @@ int wave_batch_remaining(const wave_batch *b, const wave_ctx *ctx, int32_t *rema
  * the number of steps captured into one graph (0 = plain launches). */
 int wave_batch_set_kernel(wave_batch *b, int32_t rows_per_wave, int32_t waves_per_group);
 int wave_batch_set_graph(wave_batch *b, int32_t steps_per_graph);
+
+/* Autotuner for a batch: runs trial_steps steps under each compiled tile
+ * shape and keeps the fastest; *chosen = {rows_per_wave, waves_per_group}. */
+int wave_batch_tune(wave_batch *b, int32_t trial_steps, int32_t chosen[2]);
 
 /* Wait for the batch's work, release it (members stay valid contexts). */
 int wave_batch_free(wave_batch *b);

@@ -226,100 +226,51 @@ __device__ inline ChunkInfo chunk_of(int ch, int nz, int w, int zc, bool damp) {
   return c;
 }
 
+// Per-thread slot of a tile: which point it owns and where that point lives.
+template <int RY>
+struct Slots {
+  uint32_t ro[RY];   // in-plane element offset ((y + 4) * pitch + x)
+  int ls[RY];        // LDS index of the point in the staged plane
+  bool valid[RY];    // inside the grid (else the clamped ghost row/column)
+  bool lay[RY];      // a damping-layer point
+};
+
+// The streaming loop over planes [zb, ze) for one wavefront's slots.
+// LAYER: the wavefront owns at least one layer point; it then evaluates the
+// layer update for all its points (eta and phi read as 0 and phi' dropped
+// for the others, which gives the inner update exactly).
 template <class S, int RY, int NW, bool LAYER>
-__device__ __forceinline__ void stream_tile(const SweepArgs& a, float (*sm)[(RY * NW + 2 * kR) * (kTX + 2 * kR) + 64],
-                                            int x0, int y0, int zb, int ze, bool cap) {
+__device__ __forceinline__ void stream_loop(const SweepArgs& a,
+                                            float (*sm)[(RY * NW + 2 * kR) * (kTX + 2 * kR) + 64],
+                                            const Slots<RY>& sl, const int* hl, const uint32_t* ho,
+                                            int zb, int ze) {
   using T = typename S::T;
   constexpr int TY = RY * NW;
-  constexpr int LW = kTX + 2 * kR;   // LDS row length
-  constexpr int LR = TY + 2 * kR;    // LDS rows
+  constexpr int LW = kTX + 2 * kR;
   constexpr int NT = 64 * NW;
-  constexpr int NYH = 2 * kR * kTX;  // y-halo elements per plane
-  constexpr int NHALO = NYH + 2 * kR * TY;
+  constexpr int NHALO = 2 * kR * kTX + 2 * kR * TY;
   constexpr int HPT = (NHALO + NT - 1) / NT;
   constexpr uint32_t ES = sizeof(T);
-
-  const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int x = x0 + lane;
-  const bool xin = x < a.nx;
-  const int P = a.pitch;
   const int64_t Q = a.plane;
+  const int P = a.pitch;
   const uint32_t planeb = (uint32_t)(Q * 4);
-  // Addresses: a uniform per-plane base at (x = 0, y = -4, z) plus an unsigned
-  // 32-bit in-plane byte offset ((y + 4) * pitch + x) * size per lane.  Every
-  // accessed cell has y >= -4, and x < 0 only on rows y >= 0, so the offset
-  // is never negative.  Rows past the grid are clamped to the last ghost row
-  // y = ny + 3 (all zero), which keeps every load in bounds and branch-free;
-  // such rows store zero there.
+  const uint32_t p4 = (uint32_t)P * 4u;
   const int64_t b4 = 4 * (int64_t)P;
   const T* u = static_cast<const T*>(a.cur) - b4;
   T* un = static_cast<T*>(a.nxt) - b4;
   const float* vpa = a.vp - b4;
-  const int ylast = a.ny + kR - 1;
 
-  uint32_t ro[RY];   // in-plane element offset of (x, y_r)
-#pragma unroll
-  for (int r = 0; r < RY; ++r) {
-    const int y = min(y0 + wv * RY + r, ylast);
-    ro[r] = (uint32_t)((y + kR) * P + x);
-  }
-
-  // halo bookkeeping: LDS index and in-plane element offset
-  int hl[HPT];
-  uint32_t ho[HPT];
-#pragma unroll
-  for (int k = 0; k < HPT; ++k) {
-    const int h = threadIdx.x + k * NT;
-    int rl, cl, gy, gx;
-    if (h < NYH) {
-      const int hr = h / kTX, hc = h % kTX;
-      rl = (hr < kR) ? hr : TY + hr;
-      gy = (hr < kR) ? y0 - kR + hr : y0 + TY + (hr - kR);
-      cl = kR + hc;
-      gx = x0 + hc;
-    } else if (h < NHALO) {
-      const int kk = h - NYH;
-      const int row = kk / (2 * kR), cc = kk % (2 * kR);
-      rl = kR + row;
-      gy = y0 + row;
-      cl = (cc < kR) ? cc : kTX + cc;
-      gx = (cc < kR) ? x0 - kR + cc : x0 + kTX + (cc - kR);
-    } else {
-      rl = LR;  // dump row
-      cl = lane;
-      gy = ylast;
-      gx = x0 + lane;
-    }
-    gy = min(gy, ylast);
-    hl[k] = rl * LW + cl;
-    ho[k] = (uint32_t)((gy + kR) * P + gx);
-  }
-
-  // layer bookkeeping (LAYER only): per row, whether any lane is a layer
-  // point (uniform), and the byte offset of eta/phi, out of range for lanes
-  // that are not layer points (kOOB +- 4 and +- pitch stay out of range)
-  const bool xl = x < a.w || x >= a.nx - a.w;
-  const uint32_t p4 = (uint32_t)P * 4u;
-  bool rowl[RY];
-  uint32_t eo[RY];
+  uint32_t eo[RY];   // eta/phi byte offset; out of range for non-layer points
   if (LAYER) {
-    const bool tile_x = x0 < a.w || min(x0 + kTX, a.nx) > a.nx - a.w;
 #pragma unroll
-    for (int r = 0; r < RY; ++r) {
-      const int y = y0 + wv * RY + r;
-      const bool yl = y < a.w || y >= a.ny - a.w;
-      rowl[r] = cap || yl || tile_x;
-      const bool lay = xin && y < a.ny && (cap || yl || xl);
-      eo[r] = lay ? ro[r] * 4u : kOOB;
-    }
+    for (int r = 0; r < RY; ++r) eo[r] = sl.lay[r] ? sl.ro[r] * 4u : kOOB;
   }
 
   float q[10][RY];
   float pv[2][RY], vv[2][RY];
   float hh[2][HPT];
   // LAYER: eta of the own column in a 10-slot ring like the u queue (at slot
-  // Sl, ring[(Sl + j) % 10] holds eta(z - 1 + j), j = 0..2, and slot
+  // Sl, er[(Sl + j) % 10] holds eta(z - 1 + j), j = 0..2, and slot
   // (Sl + 3) % 10 receives the prefetch of eta(z + 2)); eta x/y neighbours and
   // phi double-buffered by plane parity
   float er[10][RY];
@@ -330,7 +281,7 @@ __device__ __forceinline__ void stream_tile(const SweepArgs& a, float (*sm)[(RY 
   for (int j = 0; j < 2 * kR + 1; ++j) {
     const auto ru = rsrc_at(u + (int64_t)(zb - kR + j) * Q, 0xffffffffu);
 #pragma unroll
-    for (int r = 0; r < RY; ++r) q[j][r] = S::bld(ru, ro[r] * ES);
+    for (int r = 0; r < RY; ++r) q[j][r] = S::bld(ru, sl.ro[r] * ES);
   }
   {
     const auto ru = rsrc_at(u + (int64_t)zb * Q, 0xffffffffu);
@@ -338,8 +289,8 @@ __device__ __forceinline__ void stream_tile(const SweepArgs& a, float (*sm)[(RY 
     const auto rv = rsrc_at(vpa + (int64_t)zb * Q, 0xffffffffu);
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      pv[0][r] = S::bld(rp, ro[r] * ES);
-      vv[0][r] = bld_f32(rv, ro[r] * 4u);
+      pv[0][r] = S::bld(rp, sl.ro[r] * ES);
+      vv[0][r] = bld_f32(rv, sl.ro[r] * 4u);
     }
 #pragma unroll
     for (int k = 0; k < HPT; ++k) hh[0][k] = S::bld(ru, ho[k] * ES);
@@ -377,9 +328,9 @@ __device__ __forceinline__ void stream_tile(const SweepArgs& a, float (*sm)[(RY 
       const auto rv1 = rsrc_at(vpa + (int64_t)z1 * Q, 0xffffffffu);
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
-        q[(Sl + 9) % 10][r] = S::bld(ru5, ro[r] * ES);
-        pv[NB][r] = S::bld(rp1, ro[r] * ES);
-        vv[NB][r] = bld_f32(rv1, ro[r] * 4u);
+        q[(Sl + 9) % 10][r] = S::bld(ru5, sl.ro[r] * ES);
+        pv[NB][r] = S::bld(rp1, sl.ro[r] * ES);
+        vv[NB][r] = bld_f32(rv1, sl.ro[r] * 4u);
       }
 #pragma unroll
       for (int k = 0; k < HPT; ++k) hh[NB][k] = S::bld(ru1, ho[k] * ES);
@@ -402,7 +353,7 @@ __device__ __forceinline__ void stream_tile(const SweepArgs& a, float (*sm)[(RY 
     // stage the centre plane and its halo
     float* s = sm[B];
 #pragma unroll
-    for (int r = 0; r < RY; ++r) s[(kR + wv * RY + r) * LW + kR + lane] = q[(Sl + kR) % 10][r];
+    for (int r = 0; r < RY; ++r) s[sl.ls[r]] = q[(Sl + kR) % 10][r];
 #pragma unroll
     for (int k = 0; k < HPT; ++k) s[hl[k]] = hh[B][k];
     __syncthreads();
@@ -411,9 +362,7 @@ __device__ __forceinline__ void stream_tile(const SweepArgs& a, float (*sm)[(RY 
     const auto rph = rsrc_at(a.phi - b4 + (int64_t)z * Q, planeb);
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      const int y = y0 + wv * RY + r;
-      const bool yin = y < a.ny;
-      const float* row = s + (kR + wv * RY + r) * LW + kR + lane;
+      const float* row = s + sl.ls[r];
       const float c = q[(Sl + kR) % 10][r];
       float lap = 0.0f;
 #pragma unroll
@@ -430,27 +379,21 @@ __device__ __forceinline__ void stream_tile(const SweepArgs& a, float (*sm)[(RY 
       const float vp = vv[B][r];
       float res;
       if (LAYER) {
-        // phi' is stored for every lane; lanes outside the layer have an
-        // out-of-range offset, so their store is dropped
-        float nph = 0.0f;
-        if (rowl[r]) {
-          const float e = er[(Sl + 1) % 10][r];
-          res = upd_layer(c, pu, vp, lap, e, ph[B][r]);
-          nph = upd_phi(ph[B][r], e, ex1[B][r] - ex0[B][r], row[1] - row[-1],
-                        ey1[B][r] - ey0[B][r], row[LW] - row[-LW],
-                        er[(Sl + 2) % 10][r] - er[Sl % 10][r],
-                        q[(Sl + kR + 1) % 10][r] - q[(Sl + kR - 1) % 10][r], a.q[0], a.q[1],
-                        a.q[2]);
-        } else {
-          res = upd_inner(c, pu, vp, lap);
-        }
+        const float e = er[(Sl + 1) % 10][r];
+        res = upd_layer(c, pu, vp, lap, e, ph[B][r]);
+        const float nph =
+            upd_phi(ph[B][r], e, ex1[B][r] - ex0[B][r], row[1] - row[-1], ey1[B][r] - ey0[B][r],
+                    row[LW] - row[-LW], er[(Sl + 2) % 10][r] - er[Sl % 10][r],
+                    q[(Sl + kR + 1) % 10][r] - q[(Sl + kR - 1) % 10][r], a.q[0], a.q[1], a.q[2]);
+        // stored for every point; points outside the layer have an out-of-
+        // range offset, so their store is dropped
         bst_f32(rph, eo[r], nph);
       } else {
         res = upd_inner(c, pu, vp, lap);
       }
-      // lanes past the grid (x >= nx, or a row clamped to the ghost row
-      // ny + 3) write zero into zero ghost cells: no branch around the store
-      S::bst(rn, ro[r] * ES, (xin && yin) ? res : 0.0f);
+      // points past the grid (clamped to ghost cells) write zero there: no
+      // branch around the store
+      S::bst(rn, sl.ro[r] * ES, sl.valid[r] ? res : 0.0f);
     }
   };
 
@@ -478,6 +421,114 @@ __device__ __forceinline__ void stream_tile(const SweepArgs& a, float (*sm)[(RY 
   }
 }
 
+// Column c of the tile's x range belongs to: 0 the damping layer, 1 the
+// inner region, 2 past the grid.
+__device__ __forceinline__ int col_class(const SweepArgs& a, int x) {
+  if (x >= a.nx) return 2;
+  return (x < a.w || x >= a.nx - a.w) ? 0 : 1;
+}
+
+// The c-th column of class k in [x0, x0 + 64).
+__device__ inline int nth_col(const SweepArgs& a, int x0, int k, int c) {
+  for (int i = 0; i < kTX; ++i)
+    if (col_class(a, x0 + i) == k && c-- == 0) return i;
+  return kTX - 1;
+}
+
+// Sweep one tile over the planes [zb, ze).  Points map to (wavefront, lane,
+// slot) row by row, one x column per lane.  In a tile that contains x-layer
+// columns, the points are reordered so that the layer points come first
+// (all rows), then the inner points, then the columns past the grid: the
+// layer points then fill whole wavefronts instead of a few lanes of every
+// wavefront, and only the wavefronts that own layer points run the layer
+// loop.  Any mapping works: the z neighbours are per column, the x and y
+// neighbours come from LDS.
+template <class S, int RY, int NW>
+__device__ __forceinline__ void stream_tile(const SweepArgs& a,
+                                            float (*sm)[(RY * NW + 2 * kR) * (kTX + 2 * kR) + 64],
+                                            int x0, int y0, int zb, int ze, bool cap) {
+  constexpr int TY = RY * NW;
+  constexpr int LW = kTX + 2 * kR;   // LDS row length
+  constexpr int LR = TY + 2 * kR;    // LDS rows
+  constexpr int NT = 64 * NW;
+  constexpr int NYH = 2 * kR * kTX;  // y-halo elements per plane
+  constexpr int NHALO = NYH + 2 * kR * TY;
+  constexpr int HPT = (NHALO + NT - 1) / NT;
+
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int P = a.pitch;
+  const int ylast = a.ny + kR - 1;
+  const bool damp = a.damping != 0;
+  const bool tile_x = damp && (x0 < a.w || min(x0 + kTX, a.nx) > a.nx - a.w);
+
+  // column counts per class (layer / inner / past the grid) for the reorder
+  int ncol[3] = {0, 0, 0};
+  if (tile_x)
+    for (int i = 0; i < kTX; ++i) ncol[col_class(a, x0 + i)] += 1;
+
+  Slots<RY> sl;
+  bool any_lay = false;
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    int col = lane, row = wv * RY + r;
+    if (tile_x) {
+      int p = row * kTX + lane;         // point index in the reordered tile
+      int k = 0;
+      while (k < 2 && p >= ncol[k] * TY) {
+        p -= ncol[k] * TY;
+        ++k;
+      }
+      row = p / ncol[k];
+      col = nth_col(a, x0, k, p % ncol[k]);
+    }
+    const int x = x0 + col, y = y0 + row;
+    sl.valid[r] = x < a.nx && y < a.ny;
+    sl.ro[r] = (uint32_t)((min(y, ylast) + kR) * P + x);
+    sl.ls[r] = (kR + row) * LW + kR + col;
+    sl.lay[r] = damp && sl.valid[r] &&
+                (cap || y < a.w || y >= a.ny - a.w || x < a.w || x >= a.nx - a.w);
+    any_lay = any_lay || sl.lay[r];
+  }
+
+  // halo bookkeeping: LDS index and in-plane element offset
+  int hl[HPT];
+  uint32_t ho[HPT];
+#pragma unroll
+  for (int k = 0; k < HPT; ++k) {
+    const int h = threadIdx.x + k * NT;
+    int rl, cl, gy, gx;
+    if (h < NYH) {
+      const int hr = h / kTX, hc = h % kTX;
+      rl = (hr < kR) ? hr : TY + hr;
+      gy = (hr < kR) ? y0 - kR + hr : y0 + TY + (hr - kR);
+      cl = kR + hc;
+      gx = x0 + hc;
+    } else if (h < NHALO) {
+      const int kk = h - NYH;
+      const int row = kk / (2 * kR), cc = kk % (2 * kR);
+      rl = kR + row;
+      gy = y0 + row;
+      cl = (cc < kR) ? cc : kTX + cc;
+      gx = (cc < kR) ? x0 - kR + cc : x0 + kTX + (cc - kR);
+    } else {
+      rl = LR;  // dump row
+      cl = lane;
+      gy = ylast;
+      gx = x0 + lane;
+    }
+    gy = min(gy, ylast);
+    hl[k] = rl * LW + cl;
+    ho[k] = (uint32_t)((gy + kR) * P + gx);
+  }
+
+  // wavefront-uniform choice of the loop
+  if (__any(any_lay))
+    stream_loop<S, RY, NW, true>(a, sm, sl, hl, ho, zb, ze);
+  else
+    stream_loop<S, RY, NW, false>(a, sm, sl, hl, ho, zb, ze);
+}
+
 // Occupancy target in wavefronts per SIMD for one-row tiles.
 #ifndef WAVE_STREAM_WAVES_PER_SIMD
 #define WAVE_STREAM_WAVES_PER_SIMD 6
@@ -502,13 +553,7 @@ __global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) 
   const bool damp = a.damping != 0;
   const ChunkInfo c = chunk_of(ch, a.nz, a.w, zchunk, damp);
   if (c.zb >= c.ze) return;
-  const bool layer =
-      damp && (c.cap || x0 < a.w || min(x0 + kTX, a.nx) > a.nx - a.w || y0 < a.w ||
-               min(y0 + TY, a.ny) > a.ny - a.w);
-  if (layer)
-    stream_tile<S, RY, NW, true>(a, sm, x0, y0, c.zb, c.ze, c.cap);
-  else
-    stream_tile<S, RY, NW, false>(a, sm, x0, y0, c.zb, c.ze, false);
+  stream_tile<S, RY, NW>(a, sm, x0, y0, c.zb, c.ze, damp && c.cap);
 }
 
 // ---- many shots per launch ---------------------------------------------------
@@ -547,13 +592,7 @@ __global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) 
   const bool damp = a.damping != 0;
   const ChunkInfo c = chunk_of(ch, a.nz, a.w, b.zchunk, damp);
   if (c.zb >= c.ze) return;
-  const bool layer =
-      damp && (c.cap || x0 < a.w || min(x0 + kTX, a.nx) > a.nx - a.w || y0 < a.w ||
-               min(y0 + TY, a.ny) > a.ny - a.w);
-  if (layer)
-    stream_tile<S, RY, NW, true>(a, sm, x0, y0, c.zb, c.ze, c.cap);
-  else
-    stream_tile<S, RY, NW, false>(a, sm, x0, y0, c.zb, c.ze, false);
+  stream_tile<S, RY, NW>(a, sm, x0, y0, c.zb, c.ze, damp && c.cap);
 }
 
 // One workgroup per member: source add, receiver sample, then the member's

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <string>
 #include <utility>
 #include <vector>
@@ -754,6 +755,74 @@ int wave_set_kernel(wave_ctx* c, int32_t variant, int32_t ry, int32_t nw, int32_
   return WAVE_OK;
 }
 
+namespace {
+// Tile shapes compiled into the library, in tuning order.
+constexpr int kShapes[][2] = {{1, 16}, {1, 8}, {2, 8}, {2, 4}};
+}  // namespace
+
+int wave_tune(wave_ctx* c, int32_t trial_steps, int32_t chosen[3]) {
+  CHECK_CTX(c);
+  if (c->batch) return fail(WAVE_EINVAL, "context is a batch member (use wave_batch_tune)");
+  if (trial_steps < 1) return fail(WAVE_EINVAL, "trial_steps < 1");
+  const int nshape = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
+  const int nz = c->L.nz;
+  std::vector<std::array<int, 3>> cand;
+  for (int k = 0; k < nshape; ++k) {
+    const int ry = kShapes[k][0], nw = kShapes[k][1];
+    const int za = wave::auto_zchunk(c->L.nx, c->L.ny, nz, ry, nw);
+    for (int zc : {za, std::max(8, za / 2), std::min(nz, 2 * za)}) {
+      std::array<int, 3> e = {ry, nw, zc};
+      if (std::find(cand.begin(), cand.end(), e) == cand.end()) cand.push_back(e);
+    }
+  }
+  if (c->nrec > 0 && (int64_t)c->trace_count + (int64_t)cand.size() * trial_steps > c->d.max_steps)
+    return fail(WAVE_EINVAL, "tuning steps would overflow the trace buffer");
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0), "hipEventCreate");
+  HIPCHK(c, hipEventCreate(&e1), "hipEventCreate");
+  const int variant = c->variant, ry0 = c->ry, nw0 = c->nw, zc0 = c->zchunk;
+  float best = 0.0f;
+  std::array<int, 3> pick = {ry0, nw0, zc0};
+  int rc = WAVE_OK;
+  for (const auto& e : cand) {
+    c->variant = WAVE_KERNEL_STREAM;
+    c->ry = e[0];
+    c->nw = e[1];
+    c->zchunk = e[2];
+    hipError_t he = hipEventRecord(e0, c->stream);
+    if (he == hipSuccess) rc = wave_step(c, trial_steps);
+    if (he == hipSuccess && rc == WAVE_OK) he = hipEventRecord(e1, c->stream);
+    if (he == hipSuccess && rc == WAVE_OK) he = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (he == hipSuccess && rc == WAVE_OK) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess) rc = dev_fail(c, he, "tuning");
+    if (rc != WAVE_OK) break;
+    if (best == 0.0f || ms < best) {
+      best = ms;
+      pick = e;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != WAVE_OK) {
+    c->variant = variant;
+    c->ry = ry0;
+    c->nw = nw0;
+    c->zchunk = zc0;
+    return rc;
+  }
+  c->variant = WAVE_KERNEL_STREAM;
+  c->ry = pick[0];
+  c->nw = pick[1];
+  c->zchunk = pick[2];
+  if (chosen) {
+    chosen[0] = pick[0];
+    chosen[1] = pick[1];
+    chosen[2] = pick[2];
+  }
+  return WAVE_OK;
+}
+
 int wave_set_timing(wave_ctx* c, int32_t on) {
   CHECK_CTX(c);
   c->timing = on != 0;
@@ -974,6 +1043,49 @@ int wave_batch_run(wave_batch* b, int32_t n) {
     c->step += t;
     if (c->nrec > 0) c->trace_count += t;
     b->remaining[i] -= t;
+  }
+  return WAVE_OK;
+}
+
+int wave_batch_tune(wave_batch* b, int32_t trial_steps, int32_t chosen[2]) {
+  CHECK_BATCH(b);
+  if (trial_steps < 1) return fail(WAVE_EINVAL, "trial_steps < 1");
+  const int nshape = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
+  const int ry0 = b->ry, nw0 = b->nw;
+  float best = 0.0f;
+  int pr = ry0, pn = nw0;
+  for (int k = 0; k < nshape; ++k) {
+    b->ry = kShapes[k][0];
+    b->nw = kShapes[k][1];
+    b->layout_dirty = true;
+    hipEvent_t e0, e1;
+    BCHK(b, hipEventCreate(&e0), "hipEventCreate");
+    BCHK(b, hipEventCreate(&e1), "hipEventCreate");
+    BCHK(b, hipEventRecord(e0, b->user_stream), "hipEventRecord");
+    int rc = wave_batch_run(b, trial_steps);
+    if (rc != WAVE_OK) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return rc;
+    }
+    BCHK(b, hipEventRecord(e1, b->user_stream), "hipEventRecord");
+    BCHK(b, hipEventSynchronize(e1), "hipEventSynchronize");
+    float ms = 0.0f;
+    BCHK(b, hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best == 0.0f || ms < best) {
+      best = ms;
+      pr = kShapes[k][0];
+      pn = kShapes[k][1];
+    }
+  }
+  b->ry = pr;
+  b->nw = pn;
+  b->layout_dirty = true;
+  if (chosen) {
+    chosen[0] = pr;
+    chosen[1] = pn;
   }
   return WAVE_OK;
 }

@@ -38,7 +38,7 @@ EXPORTED = [
     "wave_sweep_bytes", "wave_stream_copy", "wave_strerror", "wave_last_error",
     "wave_batch_bytes_required", "wave_batch_create", "wave_batch_add", "wave_batch_remove",
     "wave_batch_run", "wave_batch_remaining", "wave_batch_set_kernel", "wave_batch_set_graph",
-    "wave_batch_free",
+    "wave_batch_free", "wave_tune", "wave_batch_tune",
 ]
 
 
@@ -96,6 +96,8 @@ def _load():
         "wave_batch_set_kernel": (C.c_int, [P, i32, i32]),
         "wave_batch_set_graph": (C.c_int, [P, i32]),
         "wave_batch_free": (C.c_int, [P]),
+        "wave_tune": (C.c_int, [P, i32, P]),
+        "wave_batch_tune": (C.c_int, [P, i32, P]),
         "wave_strerror": (C.c_char_p, [C.c_int]),
         "wave_last_error": (C.c_char_p, []),
     }
@@ -254,6 +256,18 @@ def wave_batch_free(b) -> int:
     return int(_lib.wave_batch_free(b))
 
 
+def wave_tune(ctx, trial_steps: int):
+    out = np.zeros(3, np.int32)
+    rc = _lib.wave_tune(ctx, int(trial_steps), _p(out))
+    return int(rc), tuple(int(v) for v in out)
+
+
+def wave_batch_tune(b, trial_steps: int):
+    out = np.zeros(2, np.int32)
+    rc = _lib.wave_batch_tune(b, int(trial_steps), _p(out))
+    return int(rc), tuple(int(v) for v in out)
+
+
 def wave_strerror(status: int) -> str:
     return _lib.wave_strerror(int(status)).decode()
 
@@ -358,6 +372,12 @@ class Shot:
     def sweep_bytes(self) -> float:
         return wave_sweep_bytes(self.ctx)
 
+    def tune(self, trial_steps: int):
+        """Advance trial_steps steps per candidate tile and keep the fastest."""
+        rc, cfg = wave_tune(self.ctx, trial_steps)
+        _check(rc, "wave_tune")
+        return cfg
+
     @property
     def step_count(self) -> int:
         return wave_step_count(self.ctx)
@@ -425,6 +445,11 @@ class Batch:
 
     def set_kernel(self, rows_per_wave=1, waves_per_group=16):
         _check(wave_batch_set_kernel(self.b, rows_per_wave, waves_per_group), "wave_batch_set_kernel")
+
+    def tune(self, trial_steps: int):
+        rc, cfg = wave_batch_tune(self.b, trial_steps)
+        _check(rc, "wave_batch_tune")
+        return cfg
 
     def set_graph(self, steps_per_graph: int):
         _check(wave_batch_set_graph(self.b, steps_per_graph), "wave_batch_set_graph")

@@ -184,6 +184,18 @@ def config_small_layered(nx: int, ny: int, nz: int, w: int, steps: int, seed: in
                 src=src, wavelet=wav, rec=rec, seed=seed)
 
 
+def shot_from_shape(nx: int, ny: int, nz: int, steps: int, seed: int, w: int = 20,
+                    pert: float = 0.05) -> Shot:
+    """A layered-model shot of the given shape: Ricker source 5 cells below the
+    layer at the xy centre, a receiver line along x at the source depth."""
+    vel = layered_velocity(nx, ny, nz, w, seed, pert=pert)
+    dt = _dt_for(float(vel.max()))
+    k = min(nz - 1, w + 5)
+    return Shot(f"shot_{nx}x{ny}x{nz}", nx, ny, nz, w, H, H, H, dt, vel, steps,
+                src=[(nx // 2, ny // 2, k)], wavelet=ricker(steps, dt)[None, :],
+                rec=receiver_line(nx, ny // 2, k), seed=seed)
+
+
 def batch_shapes(count: int = 64, seed: int = 4000, lo: int = 128, hi: int = 384,
                  step: int = 16, smin: int = 200, smax: int = 1000):
     """Seeded shot shapes for the many-shot workload: each axis uniform over

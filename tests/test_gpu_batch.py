@@ -158,3 +158,32 @@ def test_batch_error_paths(W):
     assert W.wave_step(sh.ctx, 1) == W.WAVE_OK                        # free again
     sh.close()
     other.close()
+
+
+def test_tuned_runs_stay_exact(W):
+    """Tuning trials are ordinary steps: a tuned shot and a tuned batch end
+    exactly where untuned runs end."""
+    shots = shots_for(SHAPES[:3], seed0=400)
+    for s in shots:
+        s.steps = 60
+        s.wavelet = np.ascontiguousarray(np.pad(s.wavelet, ((0, 0), (0, 60))))[:, :60]
+    say("case tuned runs")
+    ref = [solo(W, s) for s in shots]
+    sh = W.shot_from_synth(shots[0])
+    cfg = sh.tune(2)                  # <= 12 candidates x 2 steps
+    assert len(cfg) == 3
+    sh.step(60 - sh.step_count)
+    same(read_all(W, sh), ref[0], "tuned shot")
+    sh.close()
+    b = W.Batch(max_shots=4)
+    m = [W.shot_from_synth(s) for s in shots]
+    for s, x in zip(shots, m):
+        b.add(x, 60)
+    bc = b.tune(3)                    # 4 shapes x 3 steps
+    assert len(bc) == 2
+    b.run(100)
+    for q in range(3):
+        same(read_all(W, m[q]), ref[q], f"tuned batch member {q}")
+    b.close()
+    for x in m:
+        x.close()

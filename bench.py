@@ -75,9 +75,10 @@ def plain_rate(W, torch, n, w, storage, steps):
     """One shot, plain launches, given storage: Gpoints/s and the sweep
     kernel's algorithmic GB/s."""
     import synth
-    shot = synth.config_c2(steps=steps + 20, n=n, w=w)
-    sh = W.shot_from_synth(shot, storage=storage, max_steps=steps + 20 + 50)
-    sh.step(20)
+    shot = synth.config_c2(steps=steps + 20 + 64, n=n, w=w)
+    sh = W.shot_from_synth(shot, storage=storage, max_steps=steps + 20 + 50 + 64)
+    sh.tune(2)
+    sh.step(max(0, 20 - sh.step_count))
     sh.sync()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(sh.stream)
@@ -206,8 +207,8 @@ def main():
     ap.add_argument("--n", type=int, default=512, help="grid extent per axis")
     ap.add_argument("--w", type=int, default=20, help="damping layer width")
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"])
-    ap.add_argument("--kernel", default="1,1,16,0",
-                    help="variant,rows_per_wave,waves_per_group,zchunk")
+    ap.add_argument("--kernel", default="tune",
+                    help="'tune' (autotune during warmup) or variant,rows_per_wave,waves_per_group,zchunk")
     ap.add_argument("--roofline-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
@@ -230,13 +231,22 @@ def main():
 
     log(f"[bench] building workload {args.n}^3 w{args.w}")
     total = args.warmup + args.steps
-    shot = synth.config_c2(steps=total, n=args.n, w=args.w)
-    sh = W.shot_from_synth(shot, storage=args.storage, max_steps=total + args.roofline_steps)
-    k = [int(v) for v in args.kernel.split(",")]
-    sh.set_kernel(*k)
+    shot = synth.config_c2(steps=total + 64, n=args.n, w=args.w)
+    sh = W.shot_from_synth(shot, storage=args.storage,
+                           max_steps=total + 64 + args.roofline_steps)
     stream = sh.stream
     log(f"[bench] warmup {args.warmup} steps")
-    sh.step(args.warmup)
+    if args.kernel == "tune":
+        # the tuner's trials are ordinary steps of this run (every tile shape
+        # computes identical results); they count toward the warmup
+        cfg = sh.tune(max(1, min(4, args.warmup // 12)))
+        kernel = f"stream rows_per_wave={cfg[0]} waves_per_group={cfg[1]} zchunk={cfg[2]} (tuned)"
+        log(f"[bench] tuned: {kernel} after {sh.step_count} steps")
+    else:
+        k = [int(v) for v in args.kernel.split(",")]
+        sh.set_kernel(*k)
+        kernel = args.kernel
+    sh.step(max(0, args.warmup - sh.step_count))
     sh.sync()
 
     torch.cuda.synchronize()
@@ -301,7 +311,7 @@ def main():
         "config": {"workload": f"acoustic 25-pt leapfrog, {args.n}^3 grid incl. {args.w}-cell "
                                f"damping layer, 1 source, {args.n} receivers",
                    "grid": [args.n, args.n, args.n], "layer": args.w,
-                   "storage": args.storage, "kernel": args.kernel},
+                   "storage": args.storage, "kernel": kernel},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": None if traffic is None else round(traffic / 1e9, 4),

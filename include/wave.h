@@ -56,6 +56,8 @@ typedef enum wave_storage { WAVE_F32 = 0, WAVE_BF16 = 1, WAVE_F16 = 2 } wave_sto
 
 /* wave_desc.flags */
 #define WAVE_DAMPING_OFF 1 /* eta := 0: Eq. 2 on every point */
+#define WAVE_ETA_ARRAY 2   /* eta is supplied per point at wave_alloc (else the
+                              default profile, kept as three 1-D tables) */
 
 typedef struct wave_desc {
     int32_t nx, ny, nz;  /* total extents incl. the layer, 1..32768, and
@@ -64,7 +66,7 @@ typedef struct wave_desc {
     double dx, dy, dz;   /* grid spacing (m), > 0                          */
     double dt;           /* time step (s), > 0                             */
     int32_t storage;     /* wave_storage of u                              */
-    int32_t flags;       /* WAVE_DAMPING_OFF or 0                          */
+    int32_t flags;       /* WAVE_DAMPING_OFF | WAVE_ETA_ARRAY, or 0        */
     double refl;         /* target reflection of the default eta profile,
                             0 < refl < 1 (1e-3 is typical)                 */
     int32_t max_src;     /* source table capacity, >= 0                    */
@@ -107,13 +109,19 @@ int wave_eta_default(const wave_desc *d, double vmax, float *out);
  *   vel_host   velocity V (m/s), float [nz][ny][nx], finite and > 0.
  *              vp = (V dt)^2 (the dt^2 V^2 factor of Eq. 2) is computed
  *              from it in double and rounded once to float.
- *   eta_host   damping eta >= 0 per point, float [nz][ny][nx], or NULL for
- *              the default profile (wave_eta_default with vmax = max V).
- *              Ignored with WAVE_DAMPING_OFF.
+ *   eta_host   with WAVE_ETA_ARRAY: damping eta >= 0 per point, float
+ *              [nz][ny][nx] (stored as a device array).  Without the flag:
+ *              NULL, and the default profile (wave_eta_default with vmax =
+ *              max V) is used; being a sum of three per-axis profiles it is
+ *              kept as three 1-D tables and evaluated in the kernels with the
+ *              same float64 operations as on the host (same float result),
+ *              so no eta array is stored or read.  Ignored (must be NULL)
+ *              with WAVE_DAMPING_OFF.
  *   dev_arena  device pointer, 256-byte aligned, arena_bytes long.
  *   hip_stream hipStream_t (NULL = the null stream).
- * Errors: EINVAL (descriptor, pointers, alignment, non-finite input),
- * ENOMEM (arena too small), EUNSTABLE (wave_stability > 1), EDEVICE. */
+ * Errors: EINVAL (descriptor, pointers, alignment, non-finite input, eta
+ * given without WAVE_ETA_ARRAY or missing with it), ENOMEM (arena too
+ * small), EUNSTABLE (wave_stability > 1), EDEVICE. */
 int wave_alloc(const wave_desc *d, const float *vel_host, const float *eta_host,
                void *dev_arena, size_t arena_bytes, void *hip_stream, wave_ctx **out);
 
@@ -219,8 +227,10 @@ int wave_set_timing(wave_ctx *ctx, int32_t on);
 int wave_read_timing(wave_ctx *ctx, double *ms_total, int64_t *launches);
 
 /* Algorithmic HBM bytes one sweep of this context moves: every array read
- * or written once per point (16 bytes per inner point and 28 per layer
- * point in float32 storage; u is 2 bytes per access with 16-bit storage). */
+ * or written once per point.  Float32 storage: 16 bytes per inner point
+ * (u^n, u^{n-1}, vp read, u^{n+1} written); a layer point adds phi read and
+ * written (8) and, with WAVE_ETA_ARRAY, eta read (4).  u is 2 bytes per
+ * access with 16-bit storage. */
 double wave_sweep_bytes(const wave_ctx *ctx);
 
 /* Device-to-device copy of `bytes` (multiple of 16, both pointers 16-byte

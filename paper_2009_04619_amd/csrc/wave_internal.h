@@ -48,7 +48,10 @@ struct SweepArgs {
   const void* cur;      // u^n     (storage type)
   void* nxt;            // u^{n-1} on entry, u^{n+1} on exit (storage type)
   const float* vp;      // (V dt)^2
-  const float* eta;     // damping eta
+  const float* eta;     // damping eta per point (array mode), else null
+  const double* etab;   // default profile tables (table mode), else null:
+                        // tx[-1..nx], ty[-1..ny], tz[-1..nz] back to back
+  double dt;            // eta = fl32(dt * ((tx + ty) + tz)) in table mode
   float* phi;           // phi^n on entry, phi^{n+1} on exit
   int32_t nx, ny, nz, w;
   int32_t pitch;

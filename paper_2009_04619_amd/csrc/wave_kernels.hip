@@ -103,6 +103,17 @@ __device__ __forceinline__ float upd_phi(float ph, float e, float dex, float dux
   return (ph - g) / (1.0f + e);
 }
 
+// Default damping profile in table mode: eta(x, y, z) = fl32(dt * ((tx[x] +
+// ty[y]) + tz[z])) inside the grid, 0 outside (the profile is a sum of three
+// per-axis terms; the double operations match the host's).
+__device__ __forceinline__ float eta_tab(const SweepArgs& a, int x, int y, int z) {
+  if (x < 0 || x >= a.nx || y < 0 || y >= a.ny || z < 0 || z >= a.nz) return 0.0f;
+  const double* tx = a.etab + 1;
+  const double* ty = tx + a.nx + 2;
+  const double* tz = ty + a.ny + 2;
+  return (float)(a.dt * ((tx[x] + ty[y]) + tz[z]));
+}
+
 __device__ __forceinline__ bool in_layer(const SweepArgs& a, int x, int y, int z) {
   return x < a.w || x >= a.nx - a.w || y < a.w || y >= a.ny - a.w || z < a.w ||
          z >= a.nz - a.w;
@@ -135,13 +146,29 @@ __global__ __launch_bounds__(256) void k_sweep_direct(SweepArgs a) {
   const float vp = a.vp[p];
   float r;
   if (a.damping && in_layer(a, x, y, z)) {
-    const float e = a.eta[p];
+    float e, exm, exp_, eym, eyp, ezm, ezp;
+    if (a.etab) {
+      e = eta_tab(a, x, y, z);
+      exm = eta_tab(a, x - 1, y, z);
+      exp_ = eta_tab(a, x + 1, y, z);
+      eym = eta_tab(a, x, y - 1, z);
+      eyp = eta_tab(a, x, y + 1, z);
+      ezm = eta_tab(a, x, y, z - 1);
+      ezp = eta_tab(a, x, y, z + 1);
+    } else {
+      e = a.eta[p];
+      exm = a.eta[p - 1];
+      exp_ = a.eta[p + 1];
+      eym = a.eta[p - P];
+      eyp = a.eta[p + P];
+      ezm = a.eta[p - Q];
+      ezp = a.eta[p + Q];
+    }
     const float ph = a.phi[p];
     r = upd_layer(c, pu, vp, lap, e, ph);
-    a.phi[p] = upd_phi(ph, e, a.eta[p + 1] - a.eta[p - 1], S::ld(u, p + 1) - S::ld(u, p - 1),
-                       a.eta[p + P] - a.eta[p - P], S::ld(u, p + P) - S::ld(u, p - P),
-                       a.eta[p + Q] - a.eta[p - Q], S::ld(u, p + Q) - S::ld(u, p - Q), a.q[0],
-                       a.q[1], a.q[2]);
+    a.phi[p] = upd_phi(ph, e, exp_ - exm, S::ld(u, p + 1) - S::ld(u, p - 1), eyp - eym,
+                       S::ld(u, p + P) - S::ld(u, p - P), ezp - ezm,
+                       S::ld(u, p + Q) - S::ld(u, p - Q), a.q[0], a.q[1], a.q[2]);
   } else {
     r = upd_inner(c, pu, vp, lap);
   }
@@ -229,6 +256,7 @@ __device__ inline ChunkInfo chunk_of(int ch, int nz, int w, int zc, bool damp) {
 // Per-thread slot of a tile: which point it owns and where that point lives.
 template <int RY>
 struct Slots {
+  int x[RY], y[RY];  // grid coordinates of the point
   uint32_t ro[RY];   // in-plane element offset ((y + 4) * pitch + x)
   int ls[RY];        // LDS index of the point in the staged plane
   bool valid[RY];    // inside the grid (else the clamped ghost row/column)
@@ -236,10 +264,12 @@ struct Slots {
 };
 
 // The streaming loop over planes [zb, ze) for one wavefront's slots.
-// LAYER: the wavefront owns at least one layer point; it then evaluates the
-// layer update for all its points (eta and phi read as 0 and phi' dropped
-// for the others, which gives the inner update exactly).
-template <class S, int RY, int NW, bool LAYER>
+// EM = 0: no layer point.  EM = 1, 2: the wavefront owns at least one layer
+// point and evaluates the layer update for all its points (eta and phi read
+// as 0 and phi' dropped for the others, which gives the inner update
+// exactly); eta comes from the per-point array (EM = 1) or from the default
+// profile's tables (EM = 2, no eta traffic).
+template <class S, int RY, int NW, int EM>
 __device__ __forceinline__ void stream_loop(const SweepArgs& a,
                                             float (*sm)[(RY * NW + 2 * kR) * (kTX + 2 * kR) + 64],
                                             const Slots<RY>& sl, const int* hl, const uint32_t* ho,
@@ -260,10 +290,36 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
   T* un = static_cast<T*>(a.nxt) - b4;
   const float* vpa = a.vp - b4;
 
+  constexpr bool LAYER = EM != 0;
+  constexpr bool EARR = EM == 1;
   uint32_t eo[RY];   // eta/phi byte offset; out of range for non-layer points
   if (LAYER) {
 #pragma unroll
     for (int r = 0; r < RY; ++r) eo[r] = sl.lay[r] ? sl.ro[r] * 4u : kOOB;
+  }
+  // EM = 2: partial sums of the profile tables that do not depend on z
+  // (centre, x-1, x+1, y-1, y+1), and whether x+-1, y+-1 are inside the grid
+  double tsc[RY], tsxm[RY], tsxp[RY], tsym[RY], tsyp[RY];
+  bool okxm[RY], okxp[RY], okym[RY], okyp[RY];
+  const double* tzt = nullptr;
+  if (EM == 2) {
+    const double* tx = a.etab + 1;
+    const double* ty = tx + a.nx + 2;
+    tzt = ty + a.ny + 2;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int x = sl.x[r], y = sl.y[r];
+      const double t0 = tx[x], ty0 = ty[y];
+      tsc[r] = t0 + ty0;
+      tsxm[r] = tx[x - 1] + ty0;
+      tsxp[r] = tx[x + 1] + ty0;
+      tsym[r] = t0 + ty[y - 1];
+      tsyp[r] = t0 + ty[y + 1];
+      okxm[r] = x >= 1;
+      okxp[r] = x + 1 < a.nx;
+      okym[r] = y >= 1;
+      okyp[r] = y + 1 < a.ny;
+    }
   }
 
   float q[10][RY];
@@ -295,9 +351,13 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
 #pragma unroll
     for (int k = 0; k < HPT; ++k) hh[0][k] = S::bld(ru, ho[k] * ES);
     if (LAYER) {
+      const auto rph = rsrc_at(a.phi - b4 + (int64_t)zb * Q, planeb);
+#pragma unroll
+      for (int r = 0; r < RY; ++r) ph[0][r] = bld_f32(rph, eo[r]);
+    }
+    if (EARR) {
       const float* e = a.eta - b4 + (int64_t)zb * Q;
       const auto rem = rsrc_at(e - Q, planeb), re0 = rsrc_at(e, planeb), rep = rsrc_at(e + Q, planeb);
-      const auto rph = rsrc_at(a.phi - b4 + (int64_t)zb * Q, planeb);
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
         er[0][r] = bld_f32(rem, eo[r]);
@@ -307,7 +367,6 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
         ex1[0][r] = bld_f32(re0, eo[r] + 4u);
         ey0[0][r] = bld_f32(re0, eo[r] - p4);
         ey1[0][r] = bld_f32(re0, eo[r] + p4);
-        ph[0][r] = bld_f32(rph, eo[r]);
       }
     }
   }
@@ -335,10 +394,14 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
 #pragma unroll
       for (int k = 0; k < HPT; ++k) hh[NB][k] = S::bld(ru1, ho[k] * ES);
       if (LAYER) {
+        const auto rph1 = rsrc_at(a.phi - b4 + (int64_t)z1 * Q, planeb);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) ph[NB][r] = bld_f32(rph1, eo[r]);
+      }
+      if (EARR) {
         // eta planes z+1 and z+2 (z+2 <= nz: a ghost plane at most)
         const float* e1 = a.eta - b4 + (int64_t)z1 * Q;
         const auto re1 = rsrc_at(e1, planeb), re2 = rsrc_at(e1 + Q, planeb);
-        const auto rph1 = rsrc_at(a.phi - b4 + (int64_t)z1 * Q, planeb);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
           er[(Sl + 3) % 10][r] = bld_f32(re2, eo[r]);
@@ -346,7 +409,6 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
           ex1[NB][r] = bld_f32(re1, eo[r] + 4u);
           ey0[NB][r] = bld_f32(re1, eo[r] - p4);
           ey1[NB][r] = bld_f32(re1, eo[r] + p4);
-          ph[NB][r] = bld_f32(rph1, eo[r]);
         }
       }
     }
@@ -379,12 +441,34 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
       const float vp = vv[B][r];
       float res;
       if (LAYER) {
-        const float e = er[(Sl + 1) % 10][r];
+        float e, dex, dey, dez;
+        if (EARR) {
+          e = er[(Sl + 1) % 10][r];
+          dex = ex1[B][r] - ex0[B][r];
+          dey = ey1[B][r] - ey0[B][r];
+          dez = er[(Sl + 2) % 10][r] - er[Sl % 10][r];
+        } else {
+          // table mode: eta of the point and of its six neighbours (0 outside
+          // the grid); non-layer points read eta = 0 like the array mode's
+          // out-of-range loads
+          const bool okzm = z >= 1, okzp = z + 1 < a.nz;
+          const double tz0 = tzt[z], tzm = tzt[z - 1], tzp = tzt[z + 1];
+          const bool ly = sl.lay[r];
+          e = ly ? (float)(a.dt * (tsc[r] + tz0)) : 0.0f;
+          const float exm = (ly && okxm[r]) ? (float)(a.dt * (tsxm[r] + tz0)) : 0.0f;
+          const float exp_ = (ly && okxp[r]) ? (float)(a.dt * (tsxp[r] + tz0)) : 0.0f;
+          const float eym = (ly && okym[r]) ? (float)(a.dt * (tsym[r] + tz0)) : 0.0f;
+          const float eyp = (ly && okyp[r]) ? (float)(a.dt * (tsyp[r] + tz0)) : 0.0f;
+          const float ezm = (ly && okzm) ? (float)(a.dt * (tsc[r] + tzm)) : 0.0f;
+          const float ezp = (ly && okzp) ? (float)(a.dt * (tsc[r] + tzp)) : 0.0f;
+          dex = exp_ - exm;
+          dey = eyp - eym;
+          dez = ezp - ezm;
+        }
         res = upd_layer(c, pu, vp, lap, e, ph[B][r]);
-        const float nph =
-            upd_phi(ph[B][r], e, ex1[B][r] - ex0[B][r], row[1] - row[-1], ey1[B][r] - ey0[B][r],
-                    row[LW] - row[-LW], er[(Sl + 2) % 10][r] - er[Sl % 10][r],
-                    q[(Sl + kR + 1) % 10][r] - q[(Sl + kR - 1) % 10][r], a.q[0], a.q[1], a.q[2]);
+        const float nph = upd_phi(ph[B][r], e, dex, row[1] - row[-1], dey, row[LW] - row[-LW],
+                                  dez, q[(Sl + kR + 1) % 10][r] - q[(Sl + kR - 1) % 10][r],
+                                  a.q[0], a.q[1], a.q[2]);
         // stored for every point; points outside the layer have an out-of-
         // range offset, so their store is dropped
         bst_f32(rph, eo[r], nph);
@@ -421,28 +505,6 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
   }
 }
 
-// Column c of the tile's x range belongs to: 0 the damping layer, 1 the
-// inner region, 2 past the grid.
-__device__ __forceinline__ int col_class(const SweepArgs& a, int x) {
-  if (x >= a.nx) return 2;
-  return (x < a.w || x >= a.nx - a.w) ? 0 : 1;
-}
-
-// The c-th column of class k in [x0, x0 + 64).
-__device__ inline int nth_col(const SweepArgs& a, int x0, int k, int c) {
-  for (int i = 0; i < kTX; ++i)
-    if (col_class(a, x0 + i) == k && c-- == 0) return i;
-  return kTX - 1;
-}
-
-// Sweep one tile over the planes [zb, ze).  Points map to (wavefront, lane,
-// slot) row by row, one x column per lane.  In a tile that contains x-layer
-// columns, the points are reordered so that the layer points come first
-// (all rows), then the inner points, then the columns past the grid: the
-// layer points then fill whole wavefronts instead of a few lanes of every
-// wavefront, and only the wavefronts that own layer points run the layer
-// loop.  Any mapping works: the z neighbours are per column, the x and y
-// neighbours come from LDS.
 template <class S, int RY, int NW>
 __device__ __forceinline__ void stream_tile(const SweepArgs& a,
                                             float (*sm)[(RY * NW + 2 * kR) * (kTX + 2 * kR) + 64],
@@ -460,29 +522,15 @@ __device__ __forceinline__ void stream_tile(const SweepArgs& a,
   const int P = a.pitch;
   const int ylast = a.ny + kR - 1;
   const bool damp = a.damping != 0;
-  const bool tile_x = damp && (x0 < a.w || min(x0 + kTX, a.nx) > a.nx - a.w);
-
-  // column counts per class (layer / inner / past the grid) for the reorder
-  int ncol[3] = {0, 0, 0};
-  if (tile_x)
-    for (int i = 0; i < kTX; ++i) ncol[col_class(a, x0 + i)] += 1;
 
   Slots<RY> sl;
   bool any_lay = false;
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    int col = lane, row = wv * RY + r;
-    if (tile_x) {
-      int p = row * kTX + lane;         // point index in the reordered tile
-      int k = 0;
-      while (k < 2 && p >= ncol[k] * TY) {
-        p -= ncol[k] * TY;
-        ++k;
-      }
-      row = p / ncol[k];
-      col = nth_col(a, x0, k, p % ncol[k]);
-    }
+    const int col = lane, row = wv * RY + r;
     const int x = x0 + col, y = y0 + row;
+    sl.x[r] = min(x, a.nx - 1);
+    sl.y[r] = min(y, a.ny - 1);
     sl.valid[r] = x < a.nx && y < a.ny;
     sl.ro[r] = (uint32_t)((min(y, ylast) + kR) * P + x);
     sl.ls[r] = (kR + row) * LW + kR + col;
@@ -523,15 +571,17 @@ __device__ __forceinline__ void stream_tile(const SweepArgs& a,
   }
 
   // wavefront-uniform choice of the loop
-  if (__any(any_lay))
-    stream_loop<S, RY, NW, true>(a, sm, sl, hl, ho, zb, ze);
+  if (!__any(any_lay))
+    stream_loop<S, RY, NW, 0>(a, sm, sl, hl, ho, zb, ze);
+  else if (a.etab)
+    stream_loop<S, RY, NW, 2>(a, sm, sl, hl, ho, zb, ze);
   else
-    stream_loop<S, RY, NW, false>(a, sm, sl, hl, ho, zb, ze);
+    stream_loop<S, RY, NW, 1>(a, sm, sl, hl, ho, zb, ze);
 }
 
 // Occupancy target in wavefronts per SIMD for one-row tiles.
 #ifndef WAVE_STREAM_WAVES_PER_SIMD
-#define WAVE_STREAM_WAVES_PER_SIMD 6
+#define WAVE_STREAM_WAVES_PER_SIMD 5
 #endif
 template <class S, int RY, int NW>
 __global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) void k_sweep_stream(

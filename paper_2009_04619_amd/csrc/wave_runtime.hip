@@ -53,7 +53,7 @@ bool desc_ok(const wave_desc* d, std::string* why) {
   if (!(d->dt > 0) || !isfinite(d->dt)) return bad("dt must be finite and > 0");
   if (d->storage != WAVE_F32 && d->storage != WAVE_BF16 && d->storage != WAVE_F16)
     return bad("unknown storage type");
-  if (d->flags & ~WAVE_DAMPING_OFF) return bad("unknown flags");
+  if (d->flags & ~(WAVE_DAMPING_OFF | WAVE_ETA_ARRAY)) return bad("unknown flags");
   if (!(d->flags & WAVE_DAMPING_OFF) && d->w > 0 && !(d->refl > 0 && d->refl < 1))
     return bad("refl must be in (0, 1)");
   if (d->max_src < 0 || d->max_rec < 0 || d->max_steps < 0) return bad("negative capacity");
@@ -62,9 +62,10 @@ bool desc_ok(const wave_desc* d, std::string* why) {
 }
 
 bool damping_on(const wave_desc* d) { return !(d->flags & WAVE_DAMPING_OFF) && d->w > 0; }
+bool eta_array(const wave_desc* d) { return damping_on(d) && (d->flags & WAVE_ETA_ARRAY); }
 
 struct ArenaPlan {
-  size_t u[2], vp, eta, phi, src_off, wavelet, rec_off, traces, partial, eres, total;
+  size_t u[2], vp, eta, etab, phi, src_off, wavelet, rec_off, traces, partial, eres, total;
 };
 
 ArenaPlan plan_arena(const wave_desc* d) {
@@ -82,7 +83,8 @@ ArenaPlan plan_arena(const wave_desc* d) {
   a.u[1] = take((size_t)L.elems * es);
   a.vp = take((size_t)L.elems * 4);
   const bool damp = damping_on(d);
-  a.eta = damp ? take((size_t)L.elems * 4) : (size_t)-1;
+  a.eta = eta_array(d) ? take((size_t)L.elems * 4) : (size_t)-1;
+  a.etab = (damp && !eta_array(d)) ? take((size_t)(d->nx + d->ny + d->nz + 6) * 8) : (size_t)-1;
   a.phi = damp ? take((size_t)L.elems * 4) : (size_t)-1;
   a.src_off = take((size_t)std::max(d->max_src, 1) * 8);
   a.wavelet = take((size_t)std::max(d->max_src, 1) * std::max(d->max_steps, 1) * 4);
@@ -134,6 +136,27 @@ void eta_plane(const wave_desc* d, double vmax, int k, float* out) {
   }
 }
 
+// Per-axis terms of the default profile: t[i + 1] = d0 (depth/w)^2 for
+// i = -1..n (0 outside the layer and at i = -1, n).  eta = fl32(dt *
+// ((tx + ty) + tz)), the sum eta_plane forms.
+void eta_tables(const wave_desc* d, double vmax, std::vector<double>& t) {
+  const double h[3] = {d->dx, d->dy, d->dz};
+  const int n[3] = {d->nx, d->ny, d->nz};
+  t.assign((size_t)(d->nx + d->ny + d->nz + 6), 0.0);
+  size_t base = 0;
+  for (int a = 0; a < 3; ++a) {
+    const double d0 = 3.0 * vmax * log(1.0 / d->refl) / (2.0 * ((double)d->w * h[a]));
+    for (int i = 0; i < n[a]; ++i) {
+      const double cells = depth_cells(i, n[a], d->w);
+      if (cells > 0.0) {
+        const double r = cells / (double)d->w;
+        t[base + 1 + i] = d0 * r * r;
+      }
+    }
+    base += (size_t)n[a] + 2;
+  }
+}
+
 uint16_t host_bf16(float f) {
   uint32_t u;
   memcpy(&u, &f, 4);
@@ -166,6 +189,7 @@ struct wave_ctx {
   float c[13];
   float q[3];
   double c64[13];
+  double vmax;
   int nsrc, nrec, trace_count;
   int variant, ry, nw, zchunk;
   bool timing;
@@ -277,6 +301,8 @@ wave::SweepArgs sweep_args(const wave_ctx* c) {
   sa.nxt = nullptr;
   sa.vp = c->f_origin(c->plan.vp);
   sa.eta = c->f_origin(c->plan.eta);
+  sa.etab = c->plan.etab == (size_t)-1 ? nullptr : reinterpret_cast<const double*>(c->at(c->plan.etab));
+  sa.dt = c->d.dt;
   sa.phi = c->f_origin(c->plan.phi);
   sa.nx = L.nx;
   sa.ny = L.ny;
@@ -469,6 +495,9 @@ int wave_alloc(const wave_desc* d, const float* vel, const float* eta, void* dev
     vmax = std::max(vmax, (double)v);
   }
   const bool damp = damping_on(d);
+  if (eta_array(d) && !eta) return fail(WAVE_EINVAL, "WAVE_ETA_ARRAY set but eta is NULL");
+  if (eta && !eta_array(d))
+    return fail(WAVE_EINVAL, "eta given without WAVE_ETA_ARRAY (or with damping off)");
   if (damp && eta) {
     for (size_t p = 0; p < n; ++p)
       if (!(eta[p] >= 0.0f) || !isfinite(eta[p])) return fail(WAVE_EINVAL, "eta must be finite and >= 0");
@@ -489,6 +518,7 @@ int wave_alloc(const wave_desc* d, const float* vel, const float* eta, void* dev
   c->step = 0;
   c->broken = false;
   c->damp = damp;
+  c->vmax = vmax;
   coefficients64(d, c->c64);
   for (int m = 0; m < 13; ++m) c->c[m] = (float)c->c64[m];
   c->q[0] = (float)(1.0 / (4.0 * d->dx * d->dx));
@@ -525,18 +555,17 @@ int wave_alloc(const wave_desc* d, const float* vel, const float* eta, void* dev
     int rc = upload_plane(c, c->at(plan.vp), 4, k, plane.data());
     if (rc) return bail(rc);
   }
-  if (damp) {
+  if (eta_array(d)) {
     for (int k = 0; k < d->nz; ++k) {
-      const float* src;
-      if (eta) {
-        src = eta + (size_t)k * pn;
-      } else {
-        eta_plane(d, vmax, k, plane.data());
-        src = plane.data();
-      }
-      int rc = upload_plane(c, c->at(plan.eta), 4, k, src);
+      int rc = upload_plane(c, c->at(plan.eta), 4, k, eta + (size_t)k * pn);
       if (rc) return bail(rc);
     }
+  } else if (damp) {
+    std::vector<double> t;
+    eta_tables(d, vmax, t);
+    hipError_t he = hipMemcpyAsync(c->at(plan.etab), t.data(), t.size() * 8, hipMemcpyHostToDevice, c->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) return bail(dev_fail(nullptr, he, "eta tables upload"));
   }
   *out = c;
   return WAVE_OK;
@@ -660,9 +689,14 @@ int wave_read_field(wave_ctx* c, int32_t which, float* out) {
   switch (which) {
     case WAVE_FIELD_U: return download_u(c, c->cur, out);
     case WAVE_FIELD_UPREV: return download_u(c, 1 - c->cur, out);
+    case WAVE_FIELD_ETA:
+      if (c->plan.etab != (size_t)-1) {   // default profile held as tables
+        for (int k = 0; k < c->L.nz; ++k) eta_plane(&c->d, c->vmax, k, out + (size_t)k * pn);
+        return WAVE_OK;
+      }
+      [[fallthrough]];
     case WAVE_FIELD_PHI:
-    case WAVE_FIELD_VP:
-    case WAVE_FIELD_ETA: {
+    case WAVE_FIELD_VP: {
       const size_t off = which == WAVE_FIELD_PHI ? c->plan.phi : which == WAVE_FIELD_VP ? c->plan.vp : c->plan.eta;
       if (off == (size_t)-1) {
         memset(out, 0, pn * c->L.nz * sizeof(float));
@@ -857,7 +891,8 @@ double wave_sweep_bytes(const wave_ctx* c) {
   }
   const double layer = total - inner;
   const double es = c->es;
-  return inner * (3.0 * es + 4.0) + layer * (3.0 * es + 16.0);
+  const double eta_b = c->plan.eta == (size_t)-1 ? 0.0 : 4.0;
+  return inner * (3.0 * es + 4.0) + layer * (3.0 * es + 12.0 + eta_b);
 }
 
 int wave_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {

@@ -26,6 +26,7 @@ WAVE_OK, WAVE_EINVAL, WAVE_ENOMEM, WAVE_EUNSTABLE = 0, -1, -2, -3
 WAVE_EDEVICE, WAVE_ESTATE, WAVE_EBUDGET = -4, -5, -6
 WAVE_F32, WAVE_BF16, WAVE_F16 = 0, 1, 2
 WAVE_DAMPING_OFF = 1
+WAVE_ETA_ARRAY = 2
 WAVE_FIELD_U, WAVE_FIELD_UPREV, WAVE_FIELD_PHI, WAVE_FIELD_VP, WAVE_FIELD_ETA = 0, 1, 2, 3, 4
 WAVE_KERNEL_DIRECT, WAVE_KERNEL_STREAM = 0, 1
 STORAGE = {"f32": WAVE_F32, "bf16": WAVE_BF16, "f16": WAVE_F16}
@@ -277,12 +278,12 @@ def wave_last_error() -> str:
 
 
 def make_desc(nx, ny, nz, w, dx, dy, dz, dt, storage="f32", damping=True, refl=1e-3,
-              max_src=4, max_rec=0, max_steps=0) -> wave_desc:
+              max_src=4, max_rec=0, max_steps=0, eta_array=False) -> wave_desc:
     d = wave_desc()
     d.nx, d.ny, d.nz, d.w = int(nx), int(ny), int(nz), int(w)
     d.dx, d.dy, d.dz, d.dt = float(dx), float(dy), float(dz), float(dt)
     d.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
-    d.flags = 0 if damping else WAVE_DAMPING_OFF
+    d.flags = (0 if damping else WAVE_DAMPING_OFF) | (WAVE_ETA_ARRAY if (eta_array and damping) else 0)
     d.refl = float(refl)
     d.max_src, d.max_rec, d.max_steps = int(max_src), int(max_rec), int(max_steps)
     d.reserved = 0
@@ -305,7 +306,8 @@ class Shot:
                  device="cuda:0", stream=None):
         self.device = torch.device(device)
         self.desc = make_desc(nx, ny, nz, w, dx, dy, dz, dt, storage, damping, refl,
-                              max_src, max_rec, max_steps)
+                              max_src, max_rec, max_steps,
+                              eta_array=eta is not None and damping)
         nbytes = wave_bytes_required(self.desc)
         if nbytes == 0:
             raise WaveError(WAVE_EINVAL, "wave_bytes_required")
@@ -314,7 +316,7 @@ class Shot:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         vel = np.ascontiguousarray(vel, dtype=np.float32)
         assert vel.shape == (nz, ny, nx)
-        eta_a = None if eta is None else np.ascontiguousarray(eta, dtype=np.float32)
+        eta_a = None if (eta is None or not damping) else np.ascontiguousarray(eta, dtype=np.float32)
         rc, self.ctx = wave_alloc(self.desc, vel, eta_a, self.arena.data_ptr(), nbytes,
                                   self.stream.cuda_stream)
         _check(rc, "wave_alloc")

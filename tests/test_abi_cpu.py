@@ -69,10 +69,13 @@ def test_stability_matches_oracle(W):
 def test_bytes_required_and_validation(W):
     d = _desc(W)
     n = W.wave_bytes_required(d)
-    # five padded float arrays at least
+    # u^n, u^{n-1}, vp, phi padded float arrays (default profile: no eta array)
     pitch = ((40 + 8 + 63) // 64) * 64
-    assert n >= 5 * (44 + 8) * (36 + 8) * pitch * 4
+    arr = (44 + 8) * (36 + 8) * pitch * 4
+    assert n >= 4 * arr
     assert n % 256 == 0
+    ne = W.wave_bytes_required(_desc(W, eta_array=True))
+    assert ne >= 5 * arr and ne > n   # the eta array replaces the small profile tables
     assert W.wave_bytes_required(_desc(W, storage="bf16")) < n
     assert W.wave_bytes_required(_desc(W, damping=False)) < n
     for bad in (dict(nx=0), dict(w=-1), dict(w=19), dict(dx=0.0), dict(dt=-1.0),
@@ -102,8 +105,14 @@ def test_alloc_rejects_bad_arguments_before_touching_a_device(W):
     assert rc == W.WAVE_EUNSTABLE
     assert "stability" in W.wave_last_error()
     neg = np.full((44, 36, 40), -1.0, np.float32)
-    rc, _ = W.wave_alloc(d, vel, neg, 256 * 1000, need, 0)
-    assert rc == W.WAVE_EINVAL
+    de = _desc(W, dt=1e-3, eta_array=True)
+    rc, _ = W.wave_alloc(de, vel, neg, 256 * 1000, W.wave_bytes_required(de), 0)
+    assert rc == W.WAVE_EINVAL                          # negative eta
+    ok_eta = np.zeros((44, 36, 40), np.float32)
+    rc, _ = W.wave_alloc(d, vel, ok_eta, 256 * 1000, need, 0)
+    assert rc == W.WAVE_EINVAL                          # eta without the flag
+    rc, _ = W.wave_alloc(de, vel, None, 256 * 1000, W.wave_bytes_required(de), 0)
+    assert rc == W.WAVE_EINVAL                          # flag without eta
 
 
 def test_null_context_is_rejected(W):

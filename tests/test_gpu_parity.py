@@ -112,6 +112,26 @@ def test_ragged_grids_every_kernel_bitwise(W, case):
         assert_same(g, ref, f"{case} kernel {k}")
 
 
+def test_eta_array_mode_and_table_mode(W):
+    """An explicit per-point eta (array mode) against the oracle with the same
+    eta; and the default profile held as tables equals the same profile
+    passed as an array."""
+    nx, ny, nz, w = 70, 45, 37, 5
+    shot = synth.config_small_layered(nx, ny, nz, w, 25, seed=77, nsrc=2)
+    e64, e32 = oracle.eta_default(nx, ny, nz, w, shot.dx, shot.dy, shot.dz, shot.dt,
+                                  float(shot.vel.max()))
+    rng = np.random.default_rng(5)
+    eta = (e32 * (1.0 + 0.5 * rng.random(e32.shape))).astype(np.float32)
+    say("case eta array mode")
+    ref = oracle.run_shot(shot, precision="f32", eta=eta)
+    for k in [(0, 1, 16, 0), (1, 1, 16, 0), (1, 1, 8, 5), (1, 2, 8, 0), (1, 2, 4, 3)]:
+        assert_same(gpu_run(W, shot, 25, kernel=k, eta=eta), ref, f"array mode {k}")
+    tab = gpu_run(W, shot, 25)
+    arr = gpu_run(W, shot, 25, eta=e32)
+    assert_same(tab, arr, "table mode vs array mode")
+    assert_same(tab, oracle.run_shot(shot, precision="f32"), "table mode vs oracle")
+
+
 # Bound vs float64 from the storage rounding unit u (2^-8 bf16, 2^-11 f16):
 # one rounding per stored value and step, accumulating like a random walk over
 # N steps with a modest amplification, 2 sqrt(N) u.

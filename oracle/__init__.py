@@ -69,14 +69,16 @@ def _load():
         lib.ora_vp.restype = None
         lib.ora_eta_default.argtypes = [i32, i32, i32, i32, f64, f64, f64, f64, f64, f64, P, P]
         lib.ora_eta_default.restype = None
+        lib.ora_eta_axis_tables.argtypes = [i32, i32, i32, i32, f64, f64, f64, f64, f64, P, P, P]
+        lib.ora_eta_axis_tables.restype = None
         lib.ora_round_bf16.argtypes = [C.c_float]
         lib.ora_round_bf16.restype = C.c_float
         lib.ora_round_f16.argtypes = [C.c_float]
         lib.ora_round_f16.restype = C.c_float
-        lib.ora_run_f64.argtypes = [i32, i32, i32, i32, f64, f64, f64, P, P,
+        lib.ora_run_f64.argtypes = [i32, i32, i32, i32, f64, f64, f64, P, P, P, f64,
                                     i32, P, P, i32, i32, P, P, i32, i32, P, P, P]
         lib.ora_run_f64.restype = i32
-        lib.ora_run_f32.argtypes = [i32, i32, i32, i32, f64, f64, f64, P, P, i32,
+        lib.ora_run_f32.argtypes = [i32, i32, i32, i32, f64, f64, f64, P, P, P, f64, i32,
                                     i32, P, P, i32, i32, P, P, i32, i32, P, P, P]
         lib.ora_run_f32.restype = i32
         lib.ora_energy.argtypes = [i32, i32, i32, f64, f64, f64, P, P, P]
@@ -129,6 +131,15 @@ def eta_default(nx, ny, nz, w, dx, dy, dz, dt, vmax, refl=1e-3):
     return e64, e32
 
 
+def eta_axis_tables(nx, ny, nz, w, dx, dy, dz, vmax, refl=1e-3):
+    """Axis terms (t_x, t_y, t_z) of the default profile, float64 arrays of
+    n_a + 2 entries for i = -1..n_a; eta = dt ((t_x + t_y) + t_z)."""
+    t = [np.empty(n + 2, np.float64) for n in (nx, ny, nz)]
+    _load().ora_eta_axis_tables(nx, ny, nz, w, dx, dy, dz, vmax, refl,
+                                _ptr(t[0]), _ptr(t[1]), _ptr(t[2]))
+    return tuple(t)
+
+
 def round_bf16(x: float) -> float:
     return float(_load().ora_round_bf16(float(x)))
 
@@ -161,7 +172,10 @@ def run(nx, ny, nz, w, dx, dy, dz, dt, vel, steps, *,
     vel      float32 [nz][ny][nx] velocity (m/s); vp = (V dt)^2 is derived here.
     src      sequence of (i, j, k); wavelet float32 [nsrc][nsamp] (w[n]).
     rec      int32 [nrec][3] receiver (i, j, k) or None.
-    eta      "default" (profile from vmax), an explicit array, or None.
+    eta      "default" (the profile from vmax, its gradient from the axis
+             terms), "default-array" (the same profile as a plain array:
+             gradient from differences of the array, zero beyond the faces),
+             an explicit array (array semantics), or None.
     damping  False runs Eq. 2 on every point (no layer formula).
     state    dict(u=u^n, u_prev=u^{n-1}, phi=phi^n) or None (zeros).
     Returns dict(u, u_prev, phi, traces[steps][nrec] float64, vp, eta).
@@ -171,10 +185,14 @@ def run(nx, ny, nz, w, dx, dy, dz, dt, vel, steps, *,
     vel = np.ascontiguousarray(vel, dtype=np.float32)
     assert vel.shape == shape
     vp64, vp32 = vp(vel, dt)
+    etab = None
     if not damping:
         e64 = e32 = None
-    elif isinstance(eta, str) and eta == "default":
+    elif isinstance(eta, str) and eta in ("default", "default-array"):
         e64, e32 = eta_default(nx, ny, nz, w, dx, dy, dz, dt, float(vel.max()), refl)
+        if eta == "default":
+            etab = np.ascontiguousarray(np.concatenate(
+                eta_axis_tables(nx, ny, nz, w, dx, dy, dz, float(vel.max()), refl)))
     elif eta is None:
         e64 = e32 = None
     else:
@@ -205,7 +223,7 @@ def run(nx, ny, nz, w, dx, dy, dz, dt, vel, steps, *,
         up = np.array(state["u_prev"], dtype=dt_np, order="C", copy=True)
         ph = np.array(state.get("phi", np.zeros(shape)), dtype=dt_np, order="C", copy=True)
     if precision == "f64":
-        rc = lib.ora_run_f64(nx, ny, nz, w, dx, dy, dz, _ptr(vp64), _ptr(e64),
+        rc = lib.ora_run_f64(nx, ny, nz, w, dx, dy, dz, _ptr(vp64), _ptr(e64), _ptr(etab), dt,
                              nsrc, _ptr(src_a), _ptr(wav), nsamp, nrec, _ptr(rec_a),
                              _ptr(traces), n0, steps, _ptr(u), _ptr(up), _ptr(ph))
         vpo, eo = vp64, e64
@@ -213,7 +231,8 @@ def run(nx, ny, nz, w, dx, dy, dz, dt, vel, steps, *,
         if storage != "f32" and state is not None:
             r = np.vectorize(round_bf16 if storage == "bf16" else round_f16, otypes=[np.float32])
             u, up = r(u), r(up)
-        rc = lib.ora_run_f32(nx, ny, nz, w, dx, dy, dz, _ptr(vp32), _ptr(e32), STORAGE[storage],
+        rc = lib.ora_run_f32(nx, ny, nz, w, dx, dy, dz, _ptr(vp32), _ptr(e32), _ptr(etab), dt,
+                             STORAGE[storage],
                              nsrc, _ptr(src_a), _ptr(wav), nsamp, nrec, _ptr(rec_a),
                              _ptr(traces), n0, steps, _ptr(u), _ptr(up), _ptr(ph))
         vpo, eo = vp32, e32

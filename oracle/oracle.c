@@ -42,10 +42,12 @@
  * ora_run_f32 evaluates the same recurrence in float with a fixed
  * per-point operation order (explicit fmaf where a fused multiply-add is
  * meant, nothing else fused; compile with -ffp-contract=off):
- *   lap = 0
+ *   lap = c_xyz * u
  *   for axis x, y, z; for m = 1..4:
- *       lap = fmaf(c_am, (u(+m) - u) + (u(-m) - u), lap)
- *   (Eq. 3 with its centre weight folded into the pairs, see lap32)
+ *       lap = fmaf(c_am, u(+m) + u(-m), lap)
+ *   lap = fmaf(c_e, u, lap)
+ *   (Eq. 3 in its printed order, then a correction for the float weights:
+ *   c_e = fl32(-(c_xyz + 2 sum c_am)) over the float weights, see lap32)
  *   inner: u' = u + fmaf(vp, lap, u - u_prev)
  *   layer: t  = fmaf(-(eta * eta), u, u - u_prev)
  *          u' = u + fmaf(vp, lap + phi, t) / fmaf(2, eta, 1)
@@ -55,10 +57,13 @@
  *   smooth field is computed exactly and every small term is rounded
  *   relative to its own size, so only the final add rounds at the size of u;
  *   with eta = 0 the layer form is the inner form bit for bit)
- *          g  = ((eta(+x) - eta(-x)) * q_x) * (u(+x) - u(-x))
- *          g  = fmaf((eta(+y) - eta(-y)) * q_y, u(+y) - u(-y), g)
- *          g  = fmaf((eta(+z) - eta(-z)) * q_z, u(+z) - u(-z), g)
+ *          g  = (de_x * q_x) * (u(+x) - u(-x))
+ *          g  = fmaf(de_y * q_y, u(+y) - u(-y), g)
+ *          g  = fmaf(de_z * q_z, u(+z) - u(-z), g)
  *          phi' = (phi - g) / (1 + eta),   q_a = fl32(1 / (4 h_a^2))
+ *   with de_a = eta(+a) - eta(-a) from an eta array, or, for the default
+ *   profile given as axis terms (ora_eta_axis_tables),
+ *   de_a = fl32(dt (t_a(i+1) - t_a(i-1))) in double before the rounding
  *   source: u'(s) = fmaf(vp(s), w_s[n], u'(s)), sources in list order
  * With 16-bit storage the float value is rounded to the storage format
  * (round to nearest, ties to even) wherever u is written.
@@ -160,6 +165,34 @@ void ora_eta_default(int nx, int ny, int nz, int w, double dx, double dy, double
             }
 }
 
+/* Per-axis terms of the same profile, t_a(i) = d0_a (depth_a(i) / w)^2, for
+ * i = -1..n_a, stored at index i + 1, so that eta = dt ((t_x + t_y) + t_z)
+ * (the sum above, in the same order).  The depth formula continues one cell
+ * beyond each face of the grid (depth w + 1 there): the profile extended by
+ * its own formula.  In table mode the layer's eta gradient is taken from
+ * these terms: the profile is a sum of one-axis functions, so its central
+ * difference along axis a is dt (t_a(i+1) - t_a(i-1)), free of the other
+ * axes' terms. */
+void ora_eta_axis_tables(int nx, int ny, int nz, int w, double dx, double dy, double dz,
+                         double vmax, double refl, double *tx, double *ty, double *tz)
+{
+    const int n[3] = {nx, ny, nz};
+    const double h[3] = {dx, dy, dz};
+    double *t[3] = {tx, ty, tz};
+    for (int a = 0; a < 3; ++a) {
+        double d0 = (w > 0) ? 3.0 * vmax * log(1.0 / refl) / (2.0 * ((double)w * h[a])) : 0.0;
+        for (int i = -1; i <= n[a]; ++i) {
+            double cells = layer_depth(i, n[a], w);
+            double v = 0.0;
+            if (cells > 0.0) {
+                double r = cells / (double)w;
+                v = d0 * r * r;
+            }
+            t[a][i + 1] = v;
+        }
+    }
+}
+
 /* ---- rounding to 16-bit storage formats, from the IEEE definition ------
  * round-to-nearest-even at the format's precision, done in double where
  * every step below is exact: a float is exact in double, scaling by a power
@@ -229,24 +262,33 @@ static double lap64(const double *u, grid_t g, const double *c, int i, int j, in
     return s;
 }
 
-/* Eq. 3 in float, written with the centre weight folded into the pairs:
- * c_xyz = -2 sum_a sum_m c_am holds exactly for the weights, so
- *   lap = sum_a sum_m c_am [(u(+m) - u) + (u(-m) - u)].
- * Rounding the 13 weights to float separately would break that identity and
- * add a spurious term proportional to u itself (a frequency shift whose phase
- * error grows with time); in this form a constant field has lap = 0 exactly
- * and the differences of a smooth field are exact. */
-static float lap32(const float *u, grid_t g, const float *c, int i, int j, int k)
+/* Eq. 3 in float, in the printed order (centre term, then the x, y and z
+ * pairs for m = 1..4), plus one correction term.  In exact arithmetic
+ * c_xyz = -2 sum_a sum_m c_am, so a constant field has a zero Laplacian;
+ * the 13 weights rounded to float separately miss that identity by a
+ * residual e = c_xyz + 2 sum c_am (of the float weights), which would act as
+ * a spurious term e u, a frequency shift whose phase error grows with time.
+ * The last operation removes it with c_e = fl32(-e) (e is exact in double:
+ * 13 floats of nearby magnitude). */
+static float lap32(const float *u, grid_t g, const float *c, float ce, int i, int j, int k)
 {
     const float uc = U32(u, g, i, j, k);
-    float s = 0.0f;
+    float s = c[0] * uc;
     for (int m = 1; m <= R; ++m)
-        s = fmaf(c[m], (U32(u, g, i + m, j, k) - uc) + (U32(u, g, i - m, j, k) - uc), s);
+        s = fmaf(c[m], U32(u, g, i + m, j, k) + U32(u, g, i - m, j, k), s);
     for (int m = 1; m <= R; ++m)
-        s = fmaf(c[4 + m], (U32(u, g, i, j + m, k) - uc) + (U32(u, g, i, j - m, k) - uc), s);
+        s = fmaf(c[4 + m], U32(u, g, i, j + m, k) + U32(u, g, i, j - m, k), s);
     for (int m = 1; m <= R; ++m)
-        s = fmaf(c[8 + m], (U32(u, g, i, j, k + m) - uc) + (U32(u, g, i, j, k - m) - uc), s);
-    return s;
+        s = fmaf(c[8 + m], U32(u, g, i, j, k + m) + U32(u, g, i, j, k - m), s);
+    return fmaf(ce, uc, s);
+}
+
+/* The correction weight c_e of lap32 for the float weights c[0..12]. */
+static float weight_residual32(const float *c)
+{
+    double e = (double)c[0];
+    for (int m = 1; m < 13; ++m) e += 2.0 * (double)c[m];
+    return (float)(-e);
 }
 
 /*
@@ -259,7 +301,7 @@ static float lap32(const float *u, grid_t g, const float *c, int i, int j, int k
  * or -1 on bad arguments / allocation failure.
  */
 int ora_run_f64(int nx, int ny, int nz, int w, double dx, double dy, double dz,
-                const double *vp, const double *eta,
+                const double *vp, const double *eta, const double *etab, double eta_dt,
                 int nsrc, const int32_t *src_ijk, const float *wavelets, int nsamp,
                 int nrec, const int32_t *rec_ijk, double *traces,
                 int n0, int steps, double *u_cur, double *u_prev, double *phi)
@@ -292,15 +334,25 @@ int ora_run_f64(int nx, int ny, int nz, int w, double dx, double dy, double dz,
                         double e = eta[p];
                         u_next[p] = ((2.0 + 2.0 * e - e * e) * u_cur[p] - u_prev[p]
                                      + vp[p] * (L + phi[p])) / (1.0 + 2.0 * e);
+                        /* central differences of eta: of the array (zero
+                         * beyond the faces), or of the profile's axis terms */
+                        double dex, dey, dez;
+                        if (etab) {
+                            const double *tx = etab, *ty = tx + nx + 2, *tz = ty + ny + 2;
+                            dex = eta_dt * (tx[i + 2] - tx[i]);
+                            dey = eta_dt * (ty[j + 2] - ty[j]);
+                            dez = eta_dt * (tz[k + 2] - tz[k]);
+                        } else {
+                            dex = U64(eta, g, i + 1, j, k) - U64(eta, g, i - 1, j, k);
+                            dey = U64(eta, g, i, j + 1, k) - U64(eta, g, i, j - 1, k);
+                            dez = U64(eta, g, i, j, k + 1) - U64(eta, g, i, j, k - 1);
+                        }
                         double gsum = 0.0;
-                        gsum += (U64(eta, g, i + 1, j, k) - U64(eta, g, i - 1, j, k))
-                              * (U64(u_cur, g, i + 1, j, k) - U64(u_cur, g, i - 1, j, k))
+                        gsum += dex * (U64(u_cur, g, i + 1, j, k) - U64(u_cur, g, i - 1, j, k))
                               / (4.0 * h2[0]);
-                        gsum += (U64(eta, g, i, j + 1, k) - U64(eta, g, i, j - 1, k))
-                              * (U64(u_cur, g, i, j + 1, k) - U64(u_cur, g, i, j - 1, k))
+                        gsum += dey * (U64(u_cur, g, i, j + 1, k) - U64(u_cur, g, i, j - 1, k))
                               / (4.0 * h2[1]);
-                        gsum += (U64(eta, g, i, j, k + 1) - U64(eta, g, i, j, k - 1))
-                              * (U64(u_cur, g, i, j, k + 1) - U64(u_cur, g, i, j, k - 1))
+                        gsum += dez * (U64(u_cur, g, i, j, k + 1) - U64(u_cur, g, i, j, k - 1))
                               / (4.0 * h2[2]);
                         phi_next[p] = (phi[p] - gsum) / (1.0 + e);
                     }
@@ -330,7 +382,8 @@ int ora_run_f64(int nx, int ny, int nz, int w, double dx, double dy, double dz,
  * storage: 0 = float, 1 = bfloat16, 2 = binary16 for u (values are kept in
  * float arrays but every written u is rounded to the storage format). */
 int ora_run_f32(int nx, int ny, int nz, int w, double dx, double dy, double dz,
-                const float *vp, const float *eta, int storage,
+                const float *vp, const float *eta, const double *etab, double eta_dt,
+                int storage,
                 int nsrc, const int32_t *src_ijk, const float *wavelets, int nsamp,
                 int nrec, const int32_t *rec_ijk, double *traces,
                 int n0, int steps, float *u_cur, float *u_prev, float *phi)
@@ -343,6 +396,7 @@ int ora_run_f32(int nx, int ny, int nz, int w, double dx, double dy, double dz,
     ora_coefficients(dx, dy, dz, c64);
     float c[13];
     for (int m = 0; m < 13; ++m) c[m] = (float)c64[m];
+    const float ce = weight_residual32(c);
     float q[3] = {(float)(1.0 / (4.0 * dx * dx)), (float)(1.0 / (4.0 * dy * dy)),
                   (float)(1.0 / (4.0 * dz * dz))};
     float *u_next = (float *)calloc(n, sizeof(float));
@@ -356,7 +410,7 @@ int ora_run_f32(int nx, int ny, int nz, int w, double dx, double dy, double dz,
             for (int j = 0; j < ny; ++j)
                 for (int i = 0; i < nx; ++i) {
                     size_t p = IDX(nx, ny, i, j, k);
-                    float L = lap32(u_cur, g, c, i, j, k);
+                    float L = lap32(u_cur, g, c, ce, i, j, k);
                     float un;
                     if (eta == NULL || ora_is_inner(nx, ny, nz, w, i, j, k)) {
                         un = u_cur[p] + fmaf(vp[p], L, u_cur[p] - u_prev[p]);
@@ -366,11 +420,22 @@ int ora_run_f32(int nx, int ny, int nz, int w, double dx, double dy, double dz,
                         float t = fmaf(-(e * e), u_cur[p], u_cur[p] - u_prev[p]);
                         float num = fmaf(vp[p], L + phi[p], t);
                         un = u_cur[p] + num / fmaf(2.0f, e, 1.0f);
-                        float gs = ((U32(eta, g, i + 1, j, k) - U32(eta, g, i - 1, j, k)) * q[0])
+                        float dex, dey, dez;
+                        if (etab) {
+                            const double *tx = etab, *ty = tx + nx + 2, *tz = ty + ny + 2;
+                            dex = (float)(eta_dt * (tx[i + 2] - tx[i]));
+                            dey = (float)(eta_dt * (ty[j + 2] - ty[j]));
+                            dez = (float)(eta_dt * (tz[k + 2] - tz[k]));
+                        } else {
+                            dex = U32(eta, g, i + 1, j, k) - U32(eta, g, i - 1, j, k);
+                            dey = U32(eta, g, i, j + 1, k) - U32(eta, g, i, j - 1, k);
+                            dez = U32(eta, g, i, j, k + 1) - U32(eta, g, i, j, k - 1);
+                        }
+                        float gs = (dex * q[0])
                                  * (U32(u_cur, g, i + 1, j, k) - U32(u_cur, g, i - 1, j, k));
-                        gs = fmaf((U32(eta, g, i, j + 1, k) - U32(eta, g, i, j - 1, k)) * q[1],
+                        gs = fmaf(dey * q[1],
                                   U32(u_cur, g, i, j + 1, k) - U32(u_cur, g, i, j - 1, k), gs);
-                        gs = fmaf((U32(eta, g, i, j, k + 1) - U32(eta, g, i, j, k - 1)) * q[2],
+                        gs = fmaf(dez * q[2],
                                   U32(u_cur, g, i, j, k + 1) - U32(u_cur, g, i, j, k - 1), gs);
                         phi_next[p] = (phi[p] - gs) / (1.0f + e);
                     }

@@ -51,12 +51,15 @@ struct SweepArgs {
   const float* eta;     // damping eta per point (array mode), else null
   const double* etab;   // default profile tables (table mode), else null:
                         // tx[-1..nx], ty[-1..ny], tz[-1..nz] back to back
+  const float* etq;     // table mode: dqx[nx], dqy[ny], dqz[nz] back to back,
+                        // dq_a = fl32(fl32(dt (t_a(i+1) - t_a(i-1))) * q_a)
   double dt;            // eta = fl32(dt * ((tx + ty) + tz)) in table mode
   float* phi;           // phi^n on entry, phi^{n+1} on exit
   int32_t nx, ny, nz, w;
   int32_t pitch;
   int64_t plane;
   float c[13];          // Eq. 3 weights (float32)
+  float ce;             // -(c[0] + 2 sum c[1..12]): removes the weights' residual
   float q[3];           // 1 / (4 h_a^2)
   int32_t damping;      // 0: Eq. 2 everywhere
 };
@@ -115,6 +118,10 @@ hipError_t launch_sweep_stream(const SweepArgs& a, int storage, int ry, int nw,
                                int zchunk, hipStream_t s);
 bool stream_config_supported(int ry, int nw);
 int auto_zchunk(int nx, int ny, int nz, int ry, int nw);
+// Largest z chunk the streaming kernels accept for planes of `plane`
+// elements (their float arrays are addressed with 32-bit offsets inside a
+// window of zchunk + 8 planes); below 1 when one plane is too large.
+int stream_zchunk_limit(int64_t plane);
 hipError_t launch_inject_record(const InjectArgs& a, int storage, hipStream_t s);
 hipError_t launch_energy(const EnergyArgs& a, int storage, hipStream_t s);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);

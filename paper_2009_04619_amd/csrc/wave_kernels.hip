@@ -4,24 +4,32 @@
 // Per-point arithmetic (identical in every sweep variant, so results do not
 // depend on tiling): float32, explicit fused multiply-adds only where written
 // (the library is built with -ffp-contract=off), correctly rounded division:
-//   lap = 0
-//   lap = fma(c_am, (u(+m) - u) + (u(-m) - u), lap)   axis x, y, z; m = 1..4
-// (Eq. 3 with the centre weight folded into the pairs: c_xyz equals
-// -2 sum c_am exactly, and in this form separately rounded float weights
-// cannot add a spurious term proportional to u, which would shift the
-// frequency and make the phase error grow with time)
+//   lap = c_xyz * u
+//   lap = fma(c_am, u(+m) + u(-m), lap)   axis x, y, z; m = 1..4
+//   lap = fma(c_e, u, lap)
+// (Eq. 3 in its printed order.  In exact arithmetic c_xyz = -2 sum c_am, so
+// a constant field has zero Laplacian; the float weights miss that identity
+// by a residual, which would act as a spurious term proportional to u -- a
+// frequency shift whose phase error grows with time.  c_e = fl32(-(c_xyz +
+// 2 sum c_am)) over the float weights removes it.)
 //   inner: u' = u + fma(vp, lap, u - u_prev)
 //   layer: t  = fma(-(eta * eta), u, u - u_prev)
 //          u' = u + fma(vp, lap + phi, t) / fma(2, eta, 1)
 // (Eq. 2 and the layer update rearranged around the increment u - u_prev,
 // which a smooth field gives exactly; every small term is then rounded
 // relative to its own size and only the final add rounds at the size of u)
-//          g  = ((eta(+x) - eta(-x)) * q_x) * (u(+x) - u(-x))
-//          g  = fma((eta(+y) - eta(-y)) * q_y, u(+y) - u(-y), g)
-//          g  = fma((eta(+z) - eta(-z)) * q_z, u(+z) - u(-z), g)
+//          g  = (de_x * q_x) * (u(+x) - u(-x))
+//          g  = fma(de_y * q_y, u(+y) - u(-y), g)
+//          g  = fma(de_z * q_z, u(+z) - u(-z), g)
 //          phi' = (phi - g) / (1 + eta)
+// de_a is eta(+a) - eta(-a) of a per-point eta array (zero beyond the
+// faces), or, for the default profile held as per-axis tables,
+// fl32(dt (t_a(i+1) - t_a(i-1))): the central difference of a sum of
+// one-axis functions along a involves only that axis' term (the tables
+// continue the profile one cell past each face).
 // The layer form with eta = phi = 0 gives the inner form bit for bit, which
 // is the reduction of the damped update to Eq. 2.
+#include <algorithm>
 #include <type_traits>
 
 #include "wave_internal.h"
@@ -36,11 +44,12 @@ struct StF32 {
   static __device__ __forceinline__ void st(T* p, int64_t i, float v) { p[i] = v; }
   static __device__ __forceinline__ float cvt(T v) { return v; }
   static __device__ __forceinline__ T enc(float v) { return v; }
-  static __device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t boff) {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)boff, 0, 0));
+  static __device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
   }
-  static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t boff, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)boff, 0, 0);
+  static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
+                                             float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)vo, (int)so, 0);
   }
 };
 
@@ -59,11 +68,12 @@ struct StBF16 {
   static __device__ __forceinline__ void st(T* p, int64_t i, float v) { p[i] = f32_to_bf16_rne(v); }
   static __device__ __forceinline__ float cvt(T v) { return __uint_as_float((uint32_t)v << 16); }
   static __device__ __forceinline__ T enc(float v) { return f32_to_bf16_rne(v); }
-  static __device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t boff) {
-    return cvt((uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)boff, 0, 0));
+  static __device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return cvt((uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0));
   }
-  static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t boff, float v) {
-    __builtin_amdgcn_raw_buffer_store_b16(enc(v), r, (int)boff, 0, 0);
+  static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
+                                             float v) {
+    __builtin_amdgcn_raw_buffer_store_b16(enc(v), r, (int)vo, (int)so, 0);
   }
 };
 
@@ -73,12 +83,14 @@ struct StF16 {
   static __device__ __forceinline__ void st(T* p, int64_t i, float v) { p[i] = (_Float16)v; }
   static __device__ __forceinline__ float cvt(T v) { return (float)v; }
   static __device__ __forceinline__ T enc(float v) { return (_Float16)v; }
-  static __device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t boff) {
-    return cvt(__builtin_bit_cast(_Float16,
-                                  (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)boff, 0, 0)));
+  static __device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return cvt(__builtin_bit_cast(
+        _Float16, (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0)));
   }
-  static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t boff, float v) {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, enc(v)), r, (int)boff, 0, 0);
+  static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
+                                             float v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, enc(v)), r, (int)vo,
+                                          (int)so, 0);
   }
 };
 
@@ -94,20 +106,20 @@ __device__ __forceinline__ float upd_layer(float c, float pu, float vp, float la
   return c + num / __builtin_fmaf(2.0f, e, 1.0f);
 }
 
-__device__ __forceinline__ float upd_phi(float ph, float e, float dex, float dux, float dey,
-                                         float duy, float dez, float duz, float qx, float qy,
-                                         float qz) {
-  float g = (dex * qx) * dux;
-  g = __builtin_fmaf(dey * qy, duy, g);
-  g = __builtin_fmaf(dez * qz, duz, g);
+// phi' from the products dq_a = fl32(de_a * q_a) of the eta differences and
+// 1 / (4 h_a^2), and the u differences du_a.
+__device__ __forceinline__ float upd_phi(float ph, float e, float dqx, float dux, float dqy,
+                                         float duy, float dqz, float duz) {
+  float g = dqx * dux;
+  g = __builtin_fmaf(dqy, duy, g);
+  g = __builtin_fmaf(dqz, duz, g);
   return (ph - g) / (1.0f + e);
 }
 
 // Default damping profile in table mode: eta(x, y, z) = fl32(dt * ((tx[x] +
-// ty[y]) + tz[z])) inside the grid, 0 outside (the profile is a sum of three
-// per-axis terms; the double operations match the host's).
+// ty[y]) + tz[z])) (the profile is a sum of three per-axis terms; the double
+// operations match the host's).  Its differences come from the dq tables.
 __device__ __forceinline__ float eta_tab(const SweepArgs& a, int x, int y, int z) {
-  if (x < 0 || x >= a.nx || y < 0 || y >= a.ny || z < 0 || z >= a.nz) return 0.0f;
   const double* tx = a.etab + 1;
   const double* ty = tx + a.nx + 2;
   const double* tz = ty + a.ny + 2;
@@ -132,43 +144,36 @@ __global__ __launch_bounds__(256) void k_sweep_direct(SweepArgs a) {
   const int64_t P = a.pitch, Q = a.plane;
   const int64_t p = (int64_t)z * Q + (int64_t)y * P + x;
   const float c = S::ld(u, p);
-  float lap = 0.0f;
+  float lap = a.c[0] * c;
+#pragma unroll
+  for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(a.c[m], S::ld(u, p + m) + S::ld(u, p - m), lap);
 #pragma unroll
   for (int m = 1; m <= kR; ++m)
-    lap = __builtin_fmaf(a.c[m], (S::ld(u, p + m) - c) + (S::ld(u, p - m) - c), lap);
+    lap = __builtin_fmaf(a.c[4 + m], S::ld(u, p + m * P) + S::ld(u, p - m * P), lap);
 #pragma unroll
   for (int m = 1; m <= kR; ++m)
-    lap = __builtin_fmaf(a.c[4 + m], (S::ld(u, p + m * P) - c) + (S::ld(u, p - m * P) - c), lap);
-#pragma unroll
-  for (int m = 1; m <= kR; ++m)
-    lap = __builtin_fmaf(a.c[8 + m], (S::ld(u, p + m * Q) - c) + (S::ld(u, p - m * Q) - c), lap);
+    lap = __builtin_fmaf(a.c[8 + m], S::ld(u, p + m * Q) + S::ld(u, p - m * Q), lap);
+  lap = __builtin_fmaf(a.ce, c, lap);
   const float pu = S::ld(un, p);
   const float vp = a.vp[p];
   float r;
   if (a.damping && in_layer(a, x, y, z)) {
-    float e, exm, exp_, eym, eyp, ezm, ezp;
+    float e, dqx, dqy, dqz;
     if (a.etab) {
       e = eta_tab(a, x, y, z);
-      exm = eta_tab(a, x - 1, y, z);
-      exp_ = eta_tab(a, x + 1, y, z);
-      eym = eta_tab(a, x, y - 1, z);
-      eyp = eta_tab(a, x, y + 1, z);
-      ezm = eta_tab(a, x, y, z - 1);
-      ezp = eta_tab(a, x, y, z + 1);
+      dqx = a.etq[x];
+      dqy = a.etq[a.nx + y];
+      dqz = a.etq[a.nx + a.ny + z];
     } else {
       e = a.eta[p];
-      exm = a.eta[p - 1];
-      exp_ = a.eta[p + 1];
-      eym = a.eta[p - P];
-      eyp = a.eta[p + P];
-      ezm = a.eta[p - Q];
-      ezp = a.eta[p + Q];
+      dqx = (a.eta[p + 1] - a.eta[p - 1]) * a.q[0];
+      dqy = (a.eta[p + P] - a.eta[p - P]) * a.q[1];
+      dqz = (a.eta[p + Q] - a.eta[p - Q]) * a.q[2];
     }
     const float ph = a.phi[p];
     r = upd_layer(c, pu, vp, lap, e, ph);
-    a.phi[p] = upd_phi(ph, e, exp_ - exm, S::ld(u, p + 1) - S::ld(u, p - 1), eyp - eym,
-                       S::ld(u, p + P) - S::ld(u, p - P), ezp - ezm,
-                       S::ld(u, p + Q) - S::ld(u, p - Q), a.q[0], a.q[1], a.q[2]);
+    a.phi[p] = upd_phi(ph, e, dqx, S::ld(u, p + 1) - S::ld(u, p - 1), dqy,
+                       S::ld(u, p + P) - S::ld(u, p - P), dqz, S::ld(u, p + Q) - S::ld(u, p - Q));
   } else {
     r = upd_inner(c, pu, vp, lap);
   }
@@ -178,77 +183,100 @@ __global__ __launch_bounds__(256) void k_sweep_direct(SweepArgs a) {
 // ---- variant 1: 2.5-D streaming ------------------------------------------------
 // A workgroup of NW wavefronts owns a 64 x TY xy tile (TY = RY * NW; each
 // wavefront owns RY rows, one x column per lane) and streams it through the
-// planes [zb, ze) of one z chunk.  Per plane:
-//  * the 9 z-values u(z-4..z+4) of every owned column sit in registers (a
-//    10-slot queue, the 10th slot receives the prefetch of u(z+5));
+// planes [zb, ze) of one z chunk.  Per plane z:
+//  * the values u(z-4..z+4) of every owned column sit in registers, in a ring
+//    that also holds the kPD planes of u already requested beyond z+4;
 //  * the centre plane of the tile plus its 4-wide x and y halos is staged in
 //    LDS (double-buffered: one barrier per plane), from which the x and y
 //    neighbours are read;
-//  * every operand of plane z+1 is prefetched while plane z is computed.
-// The loop is unrolled by 10 so every queue/buffer index is a compile-time
-// constant (no modulo).  Blocks are remapped so that consecutive tiles
+//  * the operands of plane z + kPD (u^{n-1}, vp, halo, phi, eta) are
+//    requested while plane z is computed, so about kPD planes of loads are in
+//    flight per wavefront.
+// The loop is unrolled by the ring length so every ring index is a
+// compile-time constant.  Blocks are remapped so that consecutive tiles
 // (which share halos) run on the same XCD and its L2.
 //
-// Damping layer: z chunks are cut at the layer faces (z caps are chunks of
-// their own), so whether a lane is a layer point is fixed for a workgroup.
-// Workgroups that touch no layer point run a loop without eta/phi.  The
-// others issue the eta/phi loads and the phi store unconditionally; a lane
-// outside the layer gets an offset beyond the buffer's range, which reads 0
-// and writes nothing, so it fetches no bytes, and eta = phi = 0 turns the
-// layer update into the inner one bit for bit.  Memory operations are thus
-// identical on every path, which keeps the prefetch overlapping the compute.
+// Addressing: each array is reached through one buffer resource per tile
+// whose base is plane zb-4, row -4 of the chunk's window (planes zb-4 ..
+// ze+3); a lane's offset inside a plane is fixed for the whole loop and the
+// plane enters as a wave-uniform offset, so the loop does no 64-bit address
+// arithmetic.  The window of every float array is below 2 GiB (checked by the
+// launcher), so 32-bit offsets cover it.
+//
+// Damping layer: z chunks are cut at the layer faces (chunks in the z caps
+// hold only cap planes), so whether a lane is a layer point is fixed for a
+// workgroup.  Wavefronts that own no layer point run a loop without eta/phi.
+// The others issue the eta/phi loads and the phi store unconditionally; a
+// lane outside the layer gets an offset beyond the resource's range, which
+// reads 0 and writes nothing, so it fetches no bytes, and eta = phi = 0
+// turns the layer update into the inner one bit for bit.  Memory operations
+// are thus identical on every path, which keeps the prefetch overlapping the
+// compute.
 
 // Buffer resource over memory starting at p (gfx9 family: stride 0, dword 3 =
 // 0x00020000).  Built from a wave-uniform pointer it lives in scalar
-// registers; accesses then take an unsigned 32-bit byte offset per lane.
+// registers; accesses then take an unsigned 32-bit byte offset per lane plus
+// a wave-uniform one.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_at(const void* p, uint32_t nbytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes,
                                            0x00020000);
 }
-__device__ __forceinline__ float bld_f32(__amdgpu_buffer_rsrc_t r, uint32_t boff) {
-  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)boff, 0, 0));
+__device__ __forceinline__ float bld_f32(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
 }
-__device__ __forceinline__ void bst_f32(__amdgpu_buffer_rsrc_t r, uint32_t boff, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)boff, 0, 0);
+__device__ __forceinline__ void bst_f32(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
+                                        float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)vo, (int)so, 0);
 }
 
-// Offset that is out of range for every eta/phi resource (their range is one
-// plane, < 2 GiB); nearby offsets (+-4, +-pitch) stay out of range too.
-constexpr uint32_t kOOB = 0xC0000000u;
+// Lane offset that is out of range for every eta/phi resource (their range
+// is one chunk window, below kWindowMax); nearby offsets (-4, -pitch) stay
+// out of range, and adding a window offset cannot wrap 32 bits.
+constexpr uint32_t kOOB = 0x80000000u;
+
+// Prefetch distance in planes (the u ring then has 9 + kPD slots and the
+// per-plane operand rings kPD + 1; both divide the unroll length).
+#ifndef WAVE_STREAM_PD
+#define WAVE_STREAM_PD 3
+#endif
+constexpr int kPD = WAVE_STREAM_PD;
+static_assert(kPD == 1 || kPD == 3 || kPD == 7, "prefetch distance must make kPD + 1 divide 9 + kPD");
 
 struct ChunkInfo {
   int zb, ze;
   bool cap;  // every point of the chunk is in a z cap of the layer
 };
 
-// z chunks: without a layer, [c*zc, (c+1)*zc); with one, [0, w), then the
-// interior [w, nz-w) in pieces of zc, then [nz-w, nz).
+__host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// z chunks: pieces of at most zc planes.  With a layer, the z caps [0, w)
+// and [nz-w, nz) and the interior [w, nz-w) are cut separately (a grid with
+// 2w >= nz is all cap).
 __host__ __device__ inline int chunk_count(int nz, int w, int zc, bool damp) {
-  if (!damp || w == 0) return (nz + zc - 1) / zc;
-  if (2 * w >= nz) return 1;
-  return 2 + (nz - 2 * w + zc - 1) / zc;
+  if (!damp || w == 0 || 2 * w >= nz) return cdiv(nz, zc);
+  return 2 * cdiv(w, zc) + cdiv(nz - 2 * w, zc);
 }
 __device__ inline ChunkInfo chunk_of(int ch, int nz, int w, int zc, bool damp) {
   ChunkInfo c;
-  if (!damp || w == 0) {
+  if (!damp || w == 0 || 2 * w >= nz) {
     c.zb = ch * zc;
     c.ze = min(c.zb + zc, nz);
-    c.cap = false;
-  } else if (2 * w >= nz) {
-    c.zb = 0;
-    c.ze = nz;
+    c.cap = damp && w > 0;
+    return c;
+  }
+  const int nc = cdiv(w, zc), ni = cdiv(nz - 2 * w, zc);
+  if (ch < nc) {
+    c.zb = ch * zc;
+    c.ze = min(c.zb + zc, w);
     c.cap = true;
+  } else if (ch < nc + ni) {
+    c.zb = w + (ch - nc) * zc;
+    c.ze = min(c.zb + zc, nz - w);
+    c.cap = false;
   } else {
-    const int nin = (nz - 2 * w + zc - 1) / zc;
-    if (ch == 0) {
-      c.zb = 0; c.ze = w; c.cap = true;
-    } else if (ch == nin + 1) {
-      c.zb = nz - w; c.ze = nz; c.cap = true;
-    } else {
-      c.zb = w + (ch - 1) * zc;
-      c.ze = min(c.zb + zc, nz - w);
-      c.cap = false;
-    }
+    c.zb = nz - w + (ch - nc - ni) * zc;
+    c.ze = min(c.zb + zc, nz);
+    c.cap = true;
   }
   return c;
 }
@@ -281,227 +309,232 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
   constexpr int NHALO = 2 * kR * kTX + 2 * kR * TY;
   constexpr int HPT = (NHALO + NT - 1) / NT;
   constexpr uint32_t ES = sizeof(T);
-  const int64_t Q = a.plane;
-  const int P = a.pitch;
-  const uint32_t planeb = (uint32_t)(Q * 4);
-  const uint32_t p4 = (uint32_t)P * 4u;
-  const int64_t b4 = 4 * (int64_t)P;
-  const T* u = static_cast<const T*>(a.cur) - b4;
-  T* un = static_cast<T*>(a.nxt) - b4;
-  const float* vpa = a.vp - b4;
-
+  constexpr int PD = kPD;
+  constexpr int L = 2 * kR + 1 + PD;                    // u ring
+  constexpr int NR = PD + 1;                            // per-plane operand rings
+  constexpr int NE = (L % (PD + 3) == 0) ? PD + 3 : L;  // eta column ring
+  static_assert(L % NR == 0 && L % NE == 0 && L % 2 == 0, "ring lengths must divide the unroll");
   constexpr bool LAYER = EM != 0;
   constexpr bool EARR = EM == 1;
-  uint32_t eo[RY];   // eta/phi byte offset; out of range for non-layer points
+
+  const int64_t Q = a.plane;
+  const int P = a.pitch;
+  const uint32_t pe = (uint32_t)Q * ES;  // bytes per plane, wavefield arrays
+  const uint32_t p4 = (uint32_t)Q * 4u;  // bytes per plane, float arrays
+  const uint32_t rb4 = (uint32_t)P * 4u;
+  // window of the chunk: planes zb-4 .. ze+3, from row -4
+  const int64_t w0 = (int64_t)(zb - kR) * Q - (int64_t)kR * P;
+  const uint32_t wlen = (uint32_t)(ze - zb + 2 * kR) * p4;
+  const int zlast = ze - zb + kR - 1;  // window index of plane ze-1
+  const auto ru = rsrc_at(static_cast<const T*>(a.cur) + w0, 0xffffffffu);
+  const auto rn = rsrc_at(static_cast<T*>(a.nxt) + w0, 0xffffffffu);
+  const auto rv = rsrc_at(a.vp + w0, 0xffffffffu);
+  const auto rph = rsrc_at(LAYER ? (const void*)(a.phi + w0) : nullptr, LAYER ? wlen : 0u);
+  const auto ret = rsrc_at(EARR ? (const void*)(a.eta + w0) : nullptr, EARR ? wlen : 0u);
+
+  uint32_t vo[RY], vo4[RY];  // lane byte offsets in a plane
+  uint32_t hoe[HPT];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    vo[r] = sl.ro[r] * ES;
+    vo4[r] = sl.ro[r] * 4u;
+  }
+#pragma unroll
+  for (int k = 0; k < HPT; ++k) hoe[k] = ho[k] * ES;
+  uint32_t eo[RY];  // eta/phi lane offset; out of range for non-layer points
   if (LAYER) {
 #pragma unroll
-    for (int r = 0; r < RY; ++r) eo[r] = sl.lay[r] ? sl.ro[r] * 4u : kOOB;
+    for (int r = 0; r < RY; ++r) eo[r] = sl.lay[r] ? vo4[r] : kOOB;
   }
-  // EM = 2: partial sums of the profile tables that do not depend on z
-  // (centre, x-1, x+1, y-1, y+1), and whether x+-1, y+-1 are inside the grid
-  double tsc[RY], tsxm[RY], tsxp[RY], tsym[RY], tsyp[RY];
-  bool okxm[RY], okxp[RY], okym[RY], okyp[RY];
+  // EM = 2: the z-independent part of the profile sum, tx + ty, and the x and
+  // y difference products of the point; per plane tz(z) and dq_z(z), which
+  // are the same for every lane, travel in operand rings
+  double tsc[RY];
+  float dqx[RY], dqy[RY];
   const double* tzt = nullptr;
+  const float* dqzt = nullptr;
   if (EM == 2) {
     const double* tx = a.etab + 1;
     const double* ty = tx + a.nx + 2;
     tzt = ty + a.ny + 2;
+    dqzt = a.etq + a.nx + a.ny;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       const int x = sl.x[r], y = sl.y[r];
-      const double t0 = tx[x], ty0 = ty[y];
-      tsc[r] = t0 + ty0;
-      tsxm[r] = tx[x - 1] + ty0;
-      tsxp[r] = tx[x + 1] + ty0;
-      tsym[r] = t0 + ty[y - 1];
-      tsyp[r] = t0 + ty[y + 1];
-      okxm[r] = x >= 1;
-      okxp[r] = x + 1 < a.nx;
-      okym[r] = y >= 1;
-      okyp[r] = y + 1 < a.ny;
+      tsc[r] = tx[x] + ty[y];
+      dqx[r] = a.etq[x];
+      dqy[r] = a.etq[a.nx + y];
     }
   }
 
-  float q[10][RY];
-  float pv[2][RY], vv[2][RY];
-  float hh[2][HPT];
-  // LAYER: eta of the own column in a 10-slot ring like the u queue (at slot
-  // Sl, er[(Sl + j) % 10] holds eta(z - 1 + j), j = 0..2, and slot
-  // (Sl + 3) % 10 receives the prefetch of eta(z + 2)); eta x/y neighbours and
-  // phi double-buffered by plane parity
-  float er[10][RY];
-  float ex0[2][RY], ex1[2][RY], ey0[2][RY], ey1[2][RY], ph[2][RY];
+  float q[L][RY];
+  float pv[NR][RY], vv[NR][RY];
+  float hh[NR][HPT];
+  // LAYER: eta of the own column in a ring (at slot Sl, er[(Sl + j) % NE]
+  // holds eta(z - 1 + j)); phi and the eta x/y neighbours in operand rings
+  float er[NE][RY];
+  float ex0[NR][RY], ex1[NR][RY], ey0[NR][RY], ey1[NR][RY], ph[NR][RY];
+  double tzr[NR];
+  float dzr[NR];
 
-  // prologue: planes zb-4 .. zb+4 into queue slots 0..8; plane zb operands
+  // prologue: u(zb-4 .. zb+3+PD) into ring slots 0 .. L-2, operands of planes
+  // zb .. zb+PD-1 into operand slots 0 .. PD-1, eta(zb-1 .. zb+PD) into eta
+  // slots 0 .. PD+1 (window indices clamped to the window)
 #pragma unroll
-  for (int j = 0; j < 2 * kR + 1; ++j) {
-    const auto ru = rsrc_at(u + (int64_t)(zb - kR + j) * Q, 0xffffffffu);
+  for (int j = 0; j < L - 1; ++j) {
+    const uint32_t so = (uint32_t)min(j, zlast + kR) * pe;
 #pragma unroll
-    for (int r = 0; r < RY; ++r) q[j][r] = S::bld(ru, sl.ro[r] * ES);
+    for (int r = 0; r < RY; ++r) q[j][r] = S::bld(ru, vo[r], so);
   }
-  {
-    const auto ru = rsrc_at(u + (int64_t)zb * Q, 0xffffffffu);
-    const auto rp = rsrc_at(un + (int64_t)zb * Q, 0xffffffffu);
-    const auto rv = rsrc_at(vpa + (int64_t)zb * Q, 0xffffffffu);
+#pragma unroll
+  for (int j = 0; j < PD; ++j) {
+    const uint32_t kp = (uint32_t)min(j + kR, zlast);
+    const uint32_t se = kp * pe, s4 = kp * p4;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      pv[0][r] = S::bld(rp, sl.ro[r] * ES);
-      vv[0][r] = bld_f32(rv, sl.ro[r] * 4u);
+      pv[j][r] = S::bld(rn, vo[r], se);
+      vv[j][r] = bld_f32(rv, vo4[r], s4);
     }
 #pragma unroll
-    for (int k = 0; k < HPT; ++k) hh[0][k] = S::bld(ru, ho[k] * ES);
+    for (int k = 0; k < HPT; ++k) hh[j][k] = S::bld(ru, hoe[k], se);
     if (LAYER) {
-      const auto rph = rsrc_at(a.phi - b4 + (int64_t)zb * Q, planeb);
 #pragma unroll
-      for (int r = 0; r < RY; ++r) ph[0][r] = bld_f32(rph, eo[r]);
+      for (int r = 0; r < RY; ++r) ph[j][r] = bld_f32(rph, eo[r], s4);
+    }
+    if (EM == 2) {
+      const int zt = zb - kR + (int)kp;
+      tzr[j] = tzt[zt];
+      dzr[j] = dqzt[zt];
     }
     if (EARR) {
-      const float* e = a.eta - b4 + (int64_t)zb * Q;
-      const auto rem = rsrc_at(e - Q, planeb), re0 = rsrc_at(e, planeb), rep = rsrc_at(e + Q, planeb);
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
-        er[0][r] = bld_f32(rem, eo[r]);
-        er[1][r] = bld_f32(re0, eo[r]);
-        er[2][r] = bld_f32(rep, eo[r]);
-        ex0[0][r] = bld_f32(re0, eo[r] - 4u);
-        ex1[0][r] = bld_f32(re0, eo[r] + 4u);
-        ey0[0][r] = bld_f32(re0, eo[r] - p4);
-        ey1[0][r] = bld_f32(re0, eo[r] + p4);
+        ex0[j][r] = bld_f32(ret, eo[r] - 4u, s4);
+        ex1[j][r] = bld_f32(ret, eo[r] + 4u, s4);
+        ey0[j][r] = bld_f32(ret, eo[r] - rb4, s4);
+        ey1[j][r] = bld_f32(ret, eo[r] + rb4, s4);
       }
+    }
+  }
+  if (EARR) {
+#pragma unroll
+    for (int j = 0; j < PD + 2; ++j) {
+      const uint32_t s4 = (uint32_t)min(j - 1 + kR, zlast + 1) * p4;
+#pragma unroll
+      for (int r = 0; r < RY; ++r) er[j][r] = bld_f32(ret, eo[r], s4);
     }
   }
 
   auto body = [&](auto SC, const int z) {
     constexpr int Sl = decltype(SC)::value;
-    constexpr int B = Sl & 1;        // buffers of this plane
-    constexpr int NB = B ^ 1;        // buffers of the next plane
-    // prefetch plane z+1 operands and u(z+5), unconditionally so that the
-    // number of loads in flight is the same on every path (the last plane
-    // clamps to ghost planes, which stay inside the allocation)
+    constexpr int B = Sl % NR;          // operand slot of plane z
+    constexpr int BP = (Sl + PD) % NR;  // operand slot of plane z + PD
+    constexpr int LB = Sl & 1;          // LDS buffer
+    const int kz = z - zb + kR;         // window index of plane z
+    // request the operands of plane zp = min(z + PD, ze - 1) and u(zp + 4),
+    // unconditionally so that the number of loads in flight is the same on
+    // every path (past the chunk's end the loads repeat its last planes,
+    // which are in cache, and are never used)
     {
-      const int z1 = z + 1;                   // <= nz: a ghost plane at most
-      const int z5 = min(z + 1 + kR, a.nz + kR - 1);
-      const auto ru1 = rsrc_at(u + (int64_t)z1 * Q, 0xffffffffu);
-      const auto ru5 = rsrc_at(u + (int64_t)z5 * Q, 0xffffffffu);
-      const auto rp1 = rsrc_at(un + (int64_t)z1 * Q, 0xffffffffu);
-      const auto rv1 = rsrc_at(vpa + (int64_t)z1 * Q, 0xffffffffu);
+      const uint32_t kp = (uint32_t)min(kz + PD, zlast);
+      const uint32_t se = kp * pe, s4 = kp * p4;
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
-        q[(Sl + 9) % 10][r] = S::bld(ru5, sl.ro[r] * ES);
-        pv[NB][r] = S::bld(rp1, sl.ro[r] * ES);
-        vv[NB][r] = bld_f32(rv1, sl.ro[r] * 4u);
+        q[(Sl + L - 1) % L][r] = S::bld(ru, vo[r], se + 4u * pe);
+        pv[BP][r] = S::bld(rn, vo[r], se);
+        vv[BP][r] = bld_f32(rv, vo4[r], s4);
       }
 #pragma unroll
-      for (int k = 0; k < HPT; ++k) hh[NB][k] = S::bld(ru1, ho[k] * ES);
+      for (int k = 0; k < HPT; ++k) hh[BP][k] = S::bld(ru, hoe[k], se);
       if (LAYER) {
-        const auto rph1 = rsrc_at(a.phi - b4 + (int64_t)z1 * Q, planeb);
 #pragma unroll
-        for (int r = 0; r < RY; ++r) ph[NB][r] = bld_f32(rph1, eo[r]);
+        for (int r = 0; r < RY; ++r) ph[BP][r] = bld_f32(rph, eo[r], s4);
+      }
+      if (EM == 2) {
+        const int zt = zb - kR + (int)kp;
+        tzr[BP] = tzt[zt];
+        dzr[BP] = dqzt[zt];
       }
       if (EARR) {
-        // eta planes z+1 and z+2 (z+2 <= nz: a ghost plane at most)
-        const float* e1 = a.eta - b4 + (int64_t)z1 * Q;
-        const auto re1 = rsrc_at(e1, planeb), re2 = rsrc_at(e1 + Q, planeb);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-          er[(Sl + 3) % 10][r] = bld_f32(re2, eo[r]);
-          ex0[NB][r] = bld_f32(re1, eo[r] - 4u);
-          ex1[NB][r] = bld_f32(re1, eo[r] + 4u);
-          ey0[NB][r] = bld_f32(re1, eo[r] - p4);
-          ey1[NB][r] = bld_f32(re1, eo[r] + p4);
+          er[(Sl + PD + 2) % NE][r] = bld_f32(ret, eo[r], s4 + p4);
+          ex0[BP][r] = bld_f32(ret, eo[r] - 4u, s4);
+          ex1[BP][r] = bld_f32(ret, eo[r] + 4u, s4);
+          ey0[BP][r] = bld_f32(ret, eo[r] - rb4, s4);
+          ey1[BP][r] = bld_f32(ret, eo[r] + rb4, s4);
         }
       }
     }
     // stage the centre plane and its halo
-    float* s = sm[B];
+    float* s = sm[LB];
 #pragma unroll
-    for (int r = 0; r < RY; ++r) s[sl.ls[r]] = q[(Sl + kR) % 10][r];
+    for (int r = 0; r < RY; ++r) s[sl.ls[r]] = q[(Sl + kR) % L][r];
 #pragma unroll
     for (int k = 0; k < HPT; ++k) s[hl[k]] = hh[B][k];
     __syncthreads();
 
-    const auto rn = rsrc_at(un + (int64_t)z * Q, 0xffffffffu);
-    const auto rph = rsrc_at(a.phi - b4 + (int64_t)z * Q, planeb);
+    const uint32_t sz = (uint32_t)kz * pe, sz4 = (uint32_t)kz * p4;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       const float* row = s + sl.ls[r];
-      const float c = q[(Sl + kR) % 10][r];
-      float lap = 0.0f;
+      const float c = q[(Sl + kR) % L][r];
+      float lap = a.c[0] * c;
+#pragma unroll
+      for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(a.c[m], row[m] + row[-m], lap);
 #pragma unroll
       for (int m = 1; m <= kR; ++m)
-        lap = __builtin_fmaf(a.c[m], (row[m] - c) + (row[-m] - c), lap);
+        lap = __builtin_fmaf(a.c[4 + m], row[m * LW] + row[-m * LW], lap);
 #pragma unroll
       for (int m = 1; m <= kR; ++m)
-        lap = __builtin_fmaf(a.c[4 + m], (row[m * LW] - c) + (row[-m * LW] - c), lap);
-#pragma unroll
-      for (int m = 1; m <= kR; ++m)
-        lap = __builtin_fmaf(a.c[8 + m],
-                             (q[(Sl + kR + m) % 10][r] - c) + (q[(Sl + kR - m) % 10][r] - c), lap);
+        lap = __builtin_fmaf(a.c[8 + m], q[(Sl + kR + m) % L][r] + q[(Sl + kR - m) % L][r], lap);
+      lap = __builtin_fmaf(a.ce, c, lap);
       const float pu = pv[B][r];
       const float vp = vv[B][r];
       float res;
       if (LAYER) {
-        float e, dex, dey, dez;
+        float e, gx, gy, gz;
         if (EARR) {
-          e = er[(Sl + 1) % 10][r];
-          dex = ex1[B][r] - ex0[B][r];
-          dey = ey1[B][r] - ey0[B][r];
-          dez = er[(Sl + 2) % 10][r] - er[Sl % 10][r];
+          e = er[(Sl + 1) % NE][r];
+          gx = (ex1[B][r] - ex0[B][r]) * a.q[0];
+          gy = (ey1[B][r] - ey0[B][r]) * a.q[1];
+          gz = (er[(Sl + 2) % NE][r] - er[Sl % NE][r]) * a.q[2];
         } else {
-          // table mode: eta of the point and of its six neighbours (0 outside
-          // the grid); non-layer points read eta = 0 like the array mode's
-          // out-of-range loads
-          const bool okzm = z >= 1, okzp = z + 1 < a.nz;
-          const double tz0 = tzt[z], tzm = tzt[z - 1], tzp = tzt[z + 1];
-          const bool ly = sl.lay[r];
-          e = ly ? (float)(a.dt * (tsc[r] + tz0)) : 0.0f;
-          const float exm = (ly && okxm[r]) ? (float)(a.dt * (tsxm[r] + tz0)) : 0.0f;
-          const float exp_ = (ly && okxp[r]) ? (float)(a.dt * (tsxp[r] + tz0)) : 0.0f;
-          const float eym = (ly && okym[r]) ? (float)(a.dt * (tsym[r] + tz0)) : 0.0f;
-          const float eyp = (ly && okyp[r]) ? (float)(a.dt * (tsyp[r] + tz0)) : 0.0f;
-          const float ezm = (ly && okzm) ? (float)(a.dt * (tsc[r] + tzm)) : 0.0f;
-          const float ezp = (ly && okzp) ? (float)(a.dt * (tsc[r] + tzp)) : 0.0f;
-          dex = exp_ - exm;
-          dey = eyp - eym;
-          dez = ezp - ezm;
+          // table mode: non-layer points take eta = 0 like the array mode's
+          // out-of-range loads (their phi' is dropped, so gx..gz do not
+          // matter there)
+          e = sl.lay[r] ? (float)(a.dt * (tsc[r] + tzr[B])) : 0.0f;
+          gx = dqx[r];
+          gy = dqy[r];
+          gz = dzr[B];
         }
         res = upd_layer(c, pu, vp, lap, e, ph[B][r]);
-        const float nph = upd_phi(ph[B][r], e, dex, row[1] - row[-1], dey, row[LW] - row[-LW],
-                                  dez, q[(Sl + kR + 1) % 10][r] - q[(Sl + kR - 1) % 10][r],
-                                  a.q[0], a.q[1], a.q[2]);
+        const float nph = upd_phi(ph[B][r], e, gx, row[1] - row[-1], gy, row[LW] - row[-LW], gz,
+                                  q[(Sl + kR + 1) % L][r] - q[(Sl + kR - 1) % L][r]);
         // stored for every point; points outside the layer have an out-of-
         // range offset, so their store is dropped
-        bst_f32(rph, eo[r], nph);
+        bst_f32(rph, eo[r], sz4, nph);
       } else {
         res = upd_inner(c, pu, vp, lap);
       }
       // points past the grid (clamped to ghost cells) write zero there: no
       // branch around the store
-      S::bst(rn, sl.ro[r] * ES, sl.valid[r] ? res : 0.0f);
+      S::bst(rn, vo[r], sz, sl.valid[r] ? res : 0.0f);
     }
   };
 
   using std::integral_constant;
-  for (int z = zb; z < ze; z += 10) {
-    body(integral_constant<int, 0>{}, z);
-    if (z + 1 >= ze) break;
-    body(integral_constant<int, 1>{}, z + 1);
-    if (z + 2 >= ze) break;
-    body(integral_constant<int, 2>{}, z + 2);
-    if (z + 3 >= ze) break;
-    body(integral_constant<int, 3>{}, z + 3);
-    if (z + 4 >= ze) break;
-    body(integral_constant<int, 4>{}, z + 4);
-    if (z + 5 >= ze) break;
-    body(integral_constant<int, 5>{}, z + 5);
-    if (z + 6 >= ze) break;
-    body(integral_constant<int, 6>{}, z + 6);
-    if (z + 7 >= ze) break;
-    body(integral_constant<int, 7>{}, z + 7);
-    if (z + 8 >= ze) break;
-    body(integral_constant<int, 8>{}, z + 8);
-    if (z + 9 >= ze) break;
-    body(integral_constant<int, 9>{}, z + 9);
+  static_assert(L == 10 || L == 12 || L == 16, "unrolled loop below covers ring lengths 10, 12, 16");
+  for (int z = zb; z < ze; z += L) {
+#define WAVE_BODY(J)                                   \
+  if constexpr ((J) < L) {                             \
+    if ((J) > 0 && z + (J) >= ze) break;               \
+    body(integral_constant<int, (J) % L>{}, z + (J));  \
+  }
+    WAVE_BODY(0) WAVE_BODY(1) WAVE_BODY(2) WAVE_BODY(3) WAVE_BODY(4) WAVE_BODY(5)
+    WAVE_BODY(6) WAVE_BODY(7) WAVE_BODY(8) WAVE_BODY(9) WAVE_BODY(10) WAVE_BODY(11)
+    WAVE_BODY(12) WAVE_BODY(13) WAVE_BODY(14) WAVE_BODY(15)
+#undef WAVE_BODY
   }
 }
 
@@ -581,7 +614,7 @@ __device__ __forceinline__ void stream_tile(const SweepArgs& a,
 
 // Occupancy target in wavefronts per SIMD for one-row tiles.
 #ifndef WAVE_STREAM_WAVES_PER_SIMD
-#define WAVE_STREAM_WAVES_PER_SIMD 5
+#define WAVE_STREAM_WAVES_PER_SIMD 4
 #endif
 template <class S, int RY, int NW>
 __global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) void k_sweep_stream(
@@ -795,6 +828,7 @@ hipError_t sweep_stream_t(const SweepArgs& a, int zchunk, hipStream_t st) {
   constexpr int TY = RY * NW;
   const int tiles_x = (a.nx + kTX - 1) / kTX;
   const int tiles_y = (a.ny + TY - 1) / TY;
+  if (zchunk > stream_zchunk_limit(a.plane)) return hipErrorInvalidValue;
   const int chunks = chunk_count(a.nz, a.w, zchunk, a.damping != 0);
   const int64_t blocks = (int64_t)tiles_x * tiles_y * chunks;
   if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
@@ -817,6 +851,15 @@ hipError_t sweep_stream_s(const SweepArgs& a, int ry, int nw, int zchunk, hipStr
 bool stream_config_supported(int ry, int nw) {
   return (ry == 1 && nw == 16) || (ry == 1 && nw == 8) || (ry == 2 && nw == 8) ||
          (ry == 2 && nw == 4);
+}
+
+// Bytes a chunk window of a float array may span (keeps every in-range offset
+// plus kOOB below 2^32 and kOOB out of range).
+constexpr int64_t kWindowMax = 0x7FF00000;
+
+int stream_zchunk_limit(int64_t plane) {
+  const int64_t z = kWindowMax / (plane * 4) - 2 * kR;
+  return (int)std::min<int64_t>(z, 1 << 30);
 }
 
 int auto_zchunk(int nx, int ny, int nz, int ry, int nw) {

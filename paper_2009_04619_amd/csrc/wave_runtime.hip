@@ -64,6 +64,8 @@ bool desc_ok(const wave_desc* d, std::string* why) {
 bool damping_on(const wave_desc* d) { return !(d->flags & WAVE_DAMPING_OFF) && d->w > 0; }
 bool eta_array(const wave_desc* d) { return damping_on(d) && (d->flags & WAVE_ETA_ARRAY); }
 
+size_t eta_tables_bytes(const wave_desc* d);
+
 struct ArenaPlan {
   size_t u[2], vp, eta, etab, phi, src_off, wavelet, rec_off, traces, partial, eres, total;
 };
@@ -84,7 +86,7 @@ ArenaPlan plan_arena(const wave_desc* d) {
   a.vp = take((size_t)L.elems * 4);
   const bool damp = damping_on(d);
   a.eta = eta_array(d) ? take((size_t)L.elems * 4) : (size_t)-1;
-  a.etab = (damp && !eta_array(d)) ? take((size_t)(d->nx + d->ny + d->nz + 6) * 8) : (size_t)-1;
+  a.etab = (damp && !eta_array(d)) ? take(eta_tables_bytes(d)) : (size_t)-1;
   a.phi = damp ? take((size_t)L.elems * 4) : (size_t)-1;
   a.src_off = take((size_t)std::max(d->max_src, 1) * 8);
   a.wavelet = take((size_t)std::max(d->max_src, 1) * std::max(d->max_steps, 1) * 4);
@@ -136,25 +138,43 @@ void eta_plane(const wave_desc* d, double vmax, int k, float* out) {
   }
 }
 
-// Per-axis terms of the default profile: t[i + 1] = d0 (depth/w)^2 for
-// i = -1..n (0 outside the layer and at i = -1, n).  eta = fl32(dt *
-// ((tx + ty) + tz)), the sum eta_plane forms.
-void eta_tables(const wave_desc* d, double vmax, std::vector<double>& t) {
+// Tables of the default profile in table mode, back to back:
+//  * double t_a[i + 1] = d0_a (depth/w)^2 for i = -1..n_a, axes x, y, z (the
+//    depth continues one cell beyond each face: w + 1 there), so that
+//    eta = fl32(dt * ((tx + ty) + tz)), the sum eta_plane forms;
+//  * float dq_a[i] = fl32(fl32(dt * (t_a[i + 1] - t_a[i - 1])) * q_a) for
+//    i = 0..n_a-1: the profile's central difference along axis a (the other
+//    axes' terms cancel in a sum of one-axis functions) times q_a.
+size_t eta_tables_bytes(const wave_desc* d) {
+  const size_t n = (size_t)d->nx + d->ny + d->nz;
+  return (n + 6) * 8 + align_up(n * 4, 8);
+}
+
+void eta_tables(const wave_desc* d, double vmax, const float q[3], std::vector<unsigned char>& out) {
   const double h[3] = {d->dx, d->dy, d->dz};
   const int n[3] = {d->nx, d->ny, d->nz};
-  t.assign((size_t)(d->nx + d->ny + d->nz + 6), 0.0);
-  size_t base = 0;
+  std::vector<double> t((size_t)d->nx + d->ny + d->nz + 6, 0.0);
+  std::vector<float> dq((size_t)d->nx + d->ny + d->nz, 0.0f);
+  size_t base = 0, qbase = 0;
   for (int a = 0; a < 3; ++a) {
     const double d0 = 3.0 * vmax * log(1.0 / d->refl) / (2.0 * ((double)d->w * h[a]));
-    for (int i = 0; i < n[a]; ++i) {
+    for (int i = -1; i <= n[a]; ++i) {
       const double cells = depth_cells(i, n[a], d->w);
       if (cells > 0.0) {
         const double r = cells / (double)d->w;
         t[base + 1 + i] = d0 * r * r;
       }
     }
+    for (int i = 0; i < n[a]; ++i) {
+      const float de = (float)(d->dt * (t[base + 2 + i] - t[base + i]));
+      dq[qbase + i] = de * q[a];
+    }
     base += (size_t)n[a] + 2;
+    qbase += (size_t)n[a];
   }
+  out.assign(eta_tables_bytes(d), 0);
+  memcpy(out.data(), t.data(), t.size() * 8);
+  memcpy(out.data() + t.size() * 8, dq.data(), dq.size() * 4);
 }
 
 uint16_t host_bf16(float f) {
@@ -302,6 +322,7 @@ wave::SweepArgs sweep_args(const wave_ctx* c) {
   sa.vp = c->f_origin(c->plan.vp);
   sa.eta = c->f_origin(c->plan.eta);
   sa.etab = c->plan.etab == (size_t)-1 ? nullptr : reinterpret_cast<const double*>(c->at(c->plan.etab));
+  sa.etq = sa.etab ? reinterpret_cast<const float*>(sa.etab + (L.nx + L.ny + L.nz + 6)) : nullptr;
   sa.dt = c->d.dt;
   sa.phi = c->f_origin(c->plan.phi);
   sa.nx = L.nx;
@@ -311,6 +332,11 @@ wave::SweepArgs sweep_args(const wave_ctx* c) {
   sa.pitch = L.pitch;
   sa.plane = L.plane;
   memcpy(sa.c, c->c, sizeof(sa.c));
+  // residual of the float weights: c_xyz + 2 sum c_am is zero in exact
+  // arithmetic; summed in double it is exact for float weights
+  double e = (double)sa.c[0];
+  for (int m = 1; m < 13; ++m) e += 2.0 * (double)sa.c[m];
+  sa.ce = (float)(-e);
   memcpy(sa.q, c->q, sizeof(sa.q));
   sa.damping = c->damp ? 1 : 0;
   return sa;
@@ -392,6 +418,16 @@ int batch_fail(wave_batch* b, hipError_t e, const char* what) {
   } while (0)
 
 // Rebuild the member tables (static part); targets are filled per run.
+// z-chunk length a streaming sweep of this context uses with tile (ry, nw):
+// the requested one (or the automatic one), cut to what the kernels' 32-bit
+// chunk window allows.  0 when even one plane is too large to stream.
+int stream_zchunk(const wave_ctx* c, int ry, int nw, int zchunk) {
+  const int lim = wave::stream_zchunk_limit(c->L.plane);
+  if (lim < 1) return 0;
+  const int zc = zchunk > 0 ? zchunk : wave::auto_zchunk(c->L.nx, c->L.ny, c->L.nz, ry, nw);
+  return std::min(zc, lim);
+}
+
 void batch_layout(wave_batch* b) {
   b->h_shots.resize(b->members.size());
   int64_t begin = 0;
@@ -405,7 +441,7 @@ void batch_layout(wave_batch* b) {
     e.u[1] = c->u_origin(1);
     e.tiles_x = (c->L.nx + wave::kTX - 1) / wave::kTX;
     e.tiles_y = (c->L.ny + ty - 1) / ty;
-    e.zchunk = c->zchunk > 0 ? c->zchunk : wave::auto_zchunk(c->L.nx, c->L.ny, c->L.nz, b->ry, b->nw);
+    e.zchunk = stream_zchunk(c, b->ry, b->nw, c->zchunk);
     const int chunks = wave::stream_chunk_count(c->L.nz, c->d.w, e.zchunk, c->damp);
     e.block_begin = begin;
     begin += (int64_t)e.tiles_x * e.tiles_y * chunks;
@@ -561,9 +597,9 @@ int wave_alloc(const wave_desc* d, const float* vel, const float* eta, void* dev
       if (rc) return bail(rc);
     }
   } else if (damp) {
-    std::vector<double> t;
-    eta_tables(d, vmax, t);
-    hipError_t he = hipMemcpyAsync(c->at(plan.etab), t.data(), t.size() * 8, hipMemcpyHostToDevice, c->stream);
+    std::vector<unsigned char> t;
+    eta_tables(d, vmax, c->q, t);
+    hipError_t he = hipMemcpyAsync(c->at(plan.etab), t.data(), t.size(), hipMemcpyHostToDevice, c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     if (he != hipSuccess) return bail(dev_fail(nullptr, he, "eta tables upload"));
   }
@@ -633,7 +669,8 @@ int wave_step(wave_ctx* c, int32_t n) {
   if (c->step + n > 0x7fffffff) return fail(WAVE_EINVAL, "step counter overflow");
   const Layout& L = c->L;
   wave::SweepArgs sa = sweep_args(c);
-  const int zc = c->zchunk > 0 ? c->zchunk : wave::auto_zchunk(L.nx, L.ny, L.nz, c->ry, c->nw);
+  const int zc = stream_zchunk(c, c->ry, c->nw, c->zchunk);
+  const bool direct = c->variant == WAVE_KERNEL_DIRECT || zc < 1;
 
   wave::InjectArgs ia = inject_args(c);
 
@@ -653,8 +690,7 @@ int wave_step(wave_ctx* c, int32_t n) {
       c->events_used += 1;
       HIPCHK(c, hipEventRecord(e0, c->stream), "hipEventRecord");
     }
-    hipError_t e = (c->variant == WAVE_KERNEL_DIRECT)
-                       ? wave::launch_sweep_direct(sa, c->d.storage, c->stream)
+    hipError_t e = direct ? wave::launch_sweep_direct(sa, c->d.storage, c->stream)
                        : wave::launch_sweep_stream(sa, c->d.storage, c->ry, c->nw, zc, c->stream);
     if (e != hipSuccess) return dev_fail(c, e, "sweep launch");
     if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream), "hipEventRecord");
@@ -804,10 +840,17 @@ int wave_tune(wave_ctx* c, int32_t trial_steps, int32_t chosen[3]) {
   for (int k = 0; k < nshape; ++k) {
     const int ry = kShapes[k][0], nw = kShapes[k][1];
     const int za = wave::auto_zchunk(c->L.nx, c->L.ny, nz, ry, nw);
-    for (int zc : {za, std::max(8, za / 2), std::min(nz, 2 * za)}) {
+    for (int z : {za, std::max(8, za / 2), std::min(nz, 2 * za)}) {
+      const int zc = stream_zchunk(c, ry, nw, z);
+      if (zc < 1) continue;
       std::array<int, 3> e = {ry, nw, zc};
       if (std::find(cand.begin(), cand.end(), e) == cand.end()) cand.push_back(e);
     }
+  }
+  if (cand.empty()) {  // planes too large to stream: the direct kernel is the only choice
+    c->variant = WAVE_KERNEL_DIRECT;
+    if (chosen) chosen[0] = chosen[1] = chosen[2] = 0;
+    return WAVE_OK;
   }
   if (c->nrec > 0 && (int64_t)c->trace_count + (int64_t)cand.size() * trial_steps > c->d.max_steps)
     return fail(WAVE_EINVAL, "tuning steps would overflow the trace buffer");
@@ -960,6 +1003,8 @@ int wave_batch_add(wave_batch* b, wave_ctx* c, int32_t nsteps) {
   if (c->nrec > 0 && (int64_t)c->trace_count + nsteps > c->d.max_steps)
     return fail(WAVE_EINVAL, "trace buffer would overflow max_steps");
   if (c->step + nsteps > 0x7fffffff) return fail(WAVE_EINVAL, "step counter overflow");
+  if (wave::stream_zchunk_limit(c->L.plane) < 1)
+    return fail(WAVE_EINVAL, "z planes too large for the batched streaming kernel");
   b->members.push_back(c);
   b->remaining.push_back(nsteps);
   c->batch = b;

@@ -15,6 +15,7 @@ P9  source/receiver reciprocity (damping off)
 P10 causality cone of the radius-4 star stencil
 P11 the paper's Table III block counts from the Sec. III-B decomposition
 P12 free-space amplitude of a point source
+P13 table-mode eta gradient: closed-form derivative of the quadratic profile
 plus closed forms of the damping profile, (V dt)^2 and 16-bit rounding.
 """
 import math
@@ -413,6 +414,95 @@ def test_eta_profile_closed_form():
     assert np.all(e64[~np.pad(np.ones((nz - 2 * w, ny - 2 * w, nx - 2 * w), bool), w)] > 0)
 
 
+def test_eta_axis_tables_closed_form_and_sum():
+    nx, ny, nz, w = 30, 26, 34, 6
+    dx, dy, dz, dt, vmax, refl = 10.0, 12.5, 8.0, 1.5e-3, 3200.0, 1e-3
+    tx, ty, tz = oracle.eta_axis_tables(nx, ny, nz, w, dx, dy, dz, vmax, refl)
+    e64, _ = oracle.eta_default(nx, ny, nz, w, dx, dy, dz, dt, vmax, refl)
+    for t, n, h in ((tx, nx, dx), (ty, ny, dy), (tz, nz, dz)):
+        d0 = 3.0 * vmax * math.log(1.0 / refl) / (2.0 * w * h)
+        assert t.shape == (n + 2,)
+        for i in range(-1, n + 1):
+            depth = w - i if i < w else (i - (n - 1 - w) if i > n - 1 - w else 0)
+            assert t[i + 1] == pytest.approx(d0 * (depth / w) ** 2, rel=1e-14, abs=0.0), (n, i)
+    # eta of the array is dt ((t_x + t_y) + t_z), bit for bit
+    s = (tx[1:-1][None, None, :] + ty[1:-1][None, :, None]) + tz[1:-1][:, None, None]
+    assert np.array_equal(dt * s, e64)
+
+
+# ---------------------------------------------------------------- P13 -----
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_p13_table_gradient_is_the_profile_derivative(axis):
+    """One float64 step from u = a ramp along one axis, u_prev = u, phi = 0:
+    phi' = -(de_a / (4 h_a^2)) (u(+a) - u(-a)) / (1 + eta) on layer points.
+    For the quadratic profile the central difference is exact:
+    de_a(i) = -4 dt d0 (w - i) / w^2 in the low layer, +4 dt d0 (i - (n-1-w)) / w^2
+    in the high one, 0 between -- including the outermost cells, where the
+    profile continues past the face."""
+    n3 = [22, 19, 24]
+    w = 5
+    h3 = [10.0, 12.0, 9.0]
+    nz, ny, nx = n3[2], n3[1], n3[0]
+    dt, vmax = 1e-3, 2500.0
+    vel = np.full((nz, ny, nx), vmax, np.float32)
+    idx = np.indices((nz, ny, nx))[2 - axis].astype(np.float64)
+    u = 1.0 + idx                    # ramp along `axis`
+    st = dict(u=u, u_prev=u.copy(), phi=np.zeros_like(u))
+    r = oracle.run(nx, ny, nz, w, h3[0], h3[1], h3[2], dt, vel, 1, precision="f64",
+                   state=st, eta="default")
+    e64 = r["eta"]
+    n = n3[axis]
+    d0 = 3.0 * vmax * math.log(1.0 / 1e-3) / (2.0 * w * h3[axis])
+    up = np.pad(u, 1)                # zero beyond the faces
+    sl_p = [slice(1, -1)] * 3
+    sl_m = [slice(1, -1)] * 3
+    sl_p[2 - axis] = slice(2, None)
+    sl_m[2 - axis] = slice(0, -2)
+    du = up[tuple(sl_p)] - up[tuple(sl_m)]
+    lay = ~np.pad(np.ones((nz - 2 * w, ny - 2 * w, nx - 2 * w), bool), w)
+    de = np.where(lay, -r["phi"] * (1.0 + e64) * 4.0 * h3[axis] ** 2 / du, 0.0)
+    i = idx.astype(int)
+    # (the first inner cell next to the layer sees one layer neighbour of
+    # depth 1: -+ dt d0 / w^2)
+    want = np.where(i < w, -4.0 * dt * d0 * (w - i) / w ** 2,
+                    np.where(i > n - 1 - w, 4.0 * dt * d0 * (i - (n - 1 - w)) / w ** 2, 0.0))
+    want = np.where(i == w, -dt * d0 / w ** 2, np.where(i == n - 1 - w, dt * d0 / w ** 2, want))
+    # points off the other axes' outer faces (there the zero beyond the face
+    # gives the ramp a difference along those axes too)
+    other = np.ones((nz, ny, nx), bool)
+    for b in range(3):
+        if b != axis:
+            j = np.indices((nz, ny, nx))[2 - b]
+            other &= (j >= 1) & (j <= n3[b] - 2)
+    m = lay & other
+    assert m.sum() > 100 and np.any(m & (i == 0)) and np.any(m & (i == n - 1))
+    np.testing.assert_allclose(de[m], want[m], rtol=1e-9, atol=1e-15)
+    # the float32 mode rounds the same differences once
+    r32 = oracle.run(nx, ny, nz, w, h3[0], h3[1], h3[2], dt, vel, 1, precision="f32",
+                     state=st, eta="default")
+    np.testing.assert_allclose(r32["phi"][lay], r["phi"][lay], rtol=2e-6, atol=0)
+
+
+def test_table_and_array_gradients_agree_off_the_faces():
+    """The axis-term gradient equals the array difference wherever both
+    neighbours are inside the grid (the other axes' terms cancel); they
+    differ on the outermost cells, where the array is zero beyond the face."""
+    nx, ny, nz, w = 20, 18, 16, 4
+    dt, h = 1e-3, 10.0
+    vel = np.full((nz, ny, nx), 2000.0, np.float32)
+    rng = np.random.default_rng(5)
+    st = dict(u=rng.standard_normal((nz, ny, nx)), u_prev=rng.standard_normal((nz, ny, nx)),
+              phi=rng.standard_normal((nz, ny, nx)))
+    a = oracle.run(nx, ny, nz, w, h, h, h, dt, vel, 1, precision="f64", state=st, eta="default")
+    b = oracle.run(nx, ny, nz, w, h, h, h, dt, vel, 1, precision="f64", state=st,
+                   eta="default-array")
+    assert np.array_equal(a["u"], b["u"])             # the gradient only enters phi
+    interior = np.zeros((nz, ny, nx), bool)
+    interior[1:-1, 1:-1, 1:-1] = True
+    np.testing.assert_allclose(a["phi"][interior], b["phi"][interior], rtol=1e-12, atol=1e-15)
+    assert not np.allclose(a["phi"][~interior], b["phi"][~interior], rtol=1e-6)
+
+
 def test_vp_is_v_dt_squared():
     vel = np.array([1500.0, 2000.0, 4321.5], np.float32)
     v64, v32 = oracle.vp(vel, 1.7e-3)
@@ -449,8 +539,9 @@ def test_fp32_mode_tracks_fp64_within_tolerance():
 
 def test_fp32_mode_long_damped_run_within_tolerance():
     """400 steps with the layer absorbing most of the wave: the float32 mode
-    (Eq. 3 with the centre weight folded into the pairs, updates around the
-    increment u - u_prev) stays within 1e-5 relative L2 of float64."""
+    (Eq. 3 in its printed order with the float weights' residual removed,
+    updates around the increment u - u_prev) stays within 1e-5 relative L2
+    of float64."""
     shot = synth.config_small_layered(64, 56, 48, 10, 400, seed=41)
     shot.src = [(32, 28, 15)]
     shot.wavelet = synth.ricker(400, shot.dt)[None, :]

@@ -126,21 +126,18 @@ def batched_rate(W, torch, count):
         out[f"batched_{storage}"] = {"value": round(work / dt / 1e9, 3), "unit": "Gpoints/s",
                                      "seconds": round(dt, 3), "tile": list(cfg)}
         log(f"[bench] batched {storage}: {work / dt / 1e9:.1f} Gpt/s ({dt:.2f} s)")
-    # the same shots one at a time, plain float32 launches
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    # the same shots one at a time, plain float32 launches (set-up untimed,
+    # like the batched leg's)
+    solo = 0.0
     for s in shots:
         m = W.shot_from_synth(s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         m.step(s.steps)
         m.sync()
+        solo += time.perf_counter() - t0
         m.close()
-    dt_alloc = time.perf_counter() - t0
-    # allocation and set-up are outside the batched timing: time them alone
-    t1 = time.perf_counter()
-    for s in shots:
-        W.shot_from_synth(s).close()
-    dt_setup = time.perf_counter() - t1
-    solo = max(dt_alloc - dt_setup, 1e-9)
+    solo = max(solo, 1e-9)
     out["one_at_a_time_f32"] = {"value": round(work / solo / 1e9, 3), "unit": "Gpoints/s",
                                 "seconds": round(solo, 3)}
     log(f"[bench] one at a time f32: {work / solo / 1e9:.1f} Gpt/s ({solo:.2f} s)")

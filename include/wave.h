@@ -113,12 +113,17 @@ int wave_eta_default(const wave_desc *d, double vmax, float *out);
  *              [nz][ny][nx] (stored as a device array).  Without the flag:
  *              NULL, and the default profile (wave_eta_default with vmax =
  *              max V) is used; being a sum of three per-axis profiles it is
- *              kept as three 1-D tables and evaluated in the kernels with the
- *              same float64 operations as on the host (same float result),
- *              so no eta array is stored or read.  Ignored (must be NULL)
- *              with WAVE_DAMPING_OFF.
+ *              kept as 1-D tables and evaluated in the kernels with the same
+ *              float64 operations as on the host (same float result), so no
+ *              eta array is stored or read.  Its differences in the layer
+ *              update are those of the per-axis terms, which continue the
+ *              profile one cell past each face (an eta array instead has
+ *              zeros beyond the faces).  Ignored (must be NULL) with
+ *              WAVE_DAMPING_OFF.
  *   dev_arena  device pointer, 256-byte aligned, arena_bytes long.
- *   hip_stream hipStream_t (NULL = the null stream).
+ *   hip_stream hipStream_t (NULL = the null stream).  Set-up is enqueued
+ *              there (one host-to-device copy per input array, kernels form
+ *              vp and the padded layout) and waited for once before return.
  * Errors: EINVAL (descriptor, pointers, alignment, non-finite input, eta
  * given without WAVE_ETA_ARRAY or missing with it), ENOMEM (arena too
  * small), EUNSTABLE (wave_stability > 1), EDEVICE. */
@@ -205,9 +210,12 @@ int wave_energy(wave_ctx *ctx, double *out);
  * waves_per_group (NW) give a 64 x (RY*NW) xy tile; zchunk is the number of
  * z planes one workgroup streams (0 = automatic).  Only compiled
  * combinations are accepted (EINVAL otherwise): (RY, NW) in
- * {(1,16), (1,8), (2,8), (2,4)}; the default is (1,16).  Results do not depend on the
- * choice: every variant evaluates each point with the same operations in
- * the same order. */
+ * {(1,16), (1,8), (2,8), (2,4)}; the default is (1,16).  The streaming
+ * kernel addresses a chunk's planes with 32-bit offsets, so zchunk is cut
+ * to what keeps zchunk + 8 float planes below 2 GiB; a grid whose single
+ * plane is too large for that runs the direct kernel.  Results do not
+ * depend on the choice: every variant evaluates each point with the same
+ * operations in the same order. */
 int wave_set_kernel(wave_ctx *ctx, int32_t variant, int32_t rows_per_wave,
                     int32_t waves_per_group, int32_t zchunk);
 
@@ -216,8 +224,9 @@ int wave_set_kernel(wave_ctx *ctx, int32_t variant, int32_t rows_per_wave,
  * identical results, so the trials are ordinary steps of the run), time each
  * with HIP events, and keep the fastest.  Takes candidates x trial_steps
  * steps in total; *chosen receives {rows_per_wave, waves_per_group, zchunk}
- * (may be NULL).  Synchronises.  EINVAL if the steps would overflow the
- * trace buffer. */
+ * (may be NULL; {0, 0, 0} when the planes are too large to stream and the
+ * direct kernel is kept).  Synchronises.  EINVAL if the steps would
+ * overflow the trace buffer. */
 int wave_tune(wave_ctx *ctx, int32_t trial_steps, int32_t chosen[3]);
 
 /* When on, wave_step brackets every sweep-kernel launch with HIP events on
@@ -245,7 +254,11 @@ int wave_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream)
  * one launch for all members' sources and receivers.  Each member takes the
  * same steps, with the same arithmetic, as under wave_step, so its results
  * are identical to a run on its own.  Members must share the batch's storage
- * type and its stream.  While a context is a member, wave_step on it returns
+ * type; their streams may differ from the batch's: the batch's launches
+ * wait (by event) for the work queued on a member's stream when it is
+ * added, and a member's own later calls wait for the runs it took part in,
+ * so set-up and read-out on other streams overlap with running blocks.
+ * While a context is a member, wave_step on it returns
  * WAVE_EINVAL; state access (read/write field, traces, energy) stays valid
  * between runs. */
 typedef struct wave_batch wave_batch;
@@ -255,14 +268,17 @@ size_t wave_batch_bytes_required(int32_t max_shots);
 
 /* Create a batch.  storage is the members' wave_storage; the arena (256-byte
  * aligned, >= wave_batch_bytes_required) holds the member tables and stays
- * the caller's; hip_stream is the members' stream.  The batch keeps a
+ * the caller's; hip_stream is the caller's stream.  The batch keeps a
  * stream of its own for its launches (ordered after and before the caller's
- * stream with events) so that step blocks can be captured as graphs. */
+ * stream with events) so that step blocks can be captured as graphs, and
+ * two pinned host buffers for its tables, so runs are enqueued without
+ * waiting for earlier runs. */
 int wave_batch_create(int32_t storage, int32_t max_shots, void *dev_arena, size_t arena_bytes,
                       void *hip_stream, wave_batch **out);
 
-/* Add ctx with `nsteps` steps still to take (EINVAL: wrong storage or
- * stream, already a member, batch full, trace buffer too small). */
+/* Add ctx with `nsteps` steps still to take (EINVAL: wrong storage,
+ * already a member, batch full, trace buffer too small, z planes too large
+ * for the streaming kernel). */
 int wave_batch_add(wave_batch *b, wave_ctx *ctx, int32_t nsteps);
 
 /* Remove ctx (it keeps its state and may step on its own again). */

@@ -125,6 +125,10 @@ int stream_zchunk_limit(int64_t plane);
 hipError_t launch_inject_record(const InjectArgs& a, int storage, hipStream_t s);
 hipError_t launch_energy(const EnergyArgs& a, int storage, hipStream_t s);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// Scatter a compact [nz][ny][nx] float field into a padded array whose
+// element (0, 0, 0) is at dst; with dt > 0 store fl32((v dt)^2) instead of v.
+hipError_t launch_setup_field(float* dst, const float* src, int nx, int ny, int nz, int pitch,
+                              int64_t plane, double dt, hipStream_t s);
 int stream_chunk_count(int nz, int w, int zchunk, bool damping);
 int stream_tiles_y(int ny, int ry, int nw);
 hipError_t launch_sweep_batch(const BatchShot* shots, BatchState* state, int nshots,

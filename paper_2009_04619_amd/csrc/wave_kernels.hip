@@ -796,6 +796,28 @@ __global__ __launch_bounds__(1024) void k_energy_final(double* partial, int64_t 
   }
 }
 
+// ---- set-up: compact host-order field -> padded layout --------------------------
+// dst points at element (0, 0, 0) of a padded array.  With dt > 0 the value
+// stored is vp = fl32((v dt)^2) formed in double (Eq. 2's dt^2 V^2),
+// otherwise the value itself.
+__global__ __launch_bounds__(256) void k_setup_field(float* __restrict__ dst,
+                                                     const float* __restrict__ src, int nx,
+                                                     int ny, int64_t n, int pitch, int64_t plane,
+                                                     double dt) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += stride) {
+    const int64_t i = p % nx, r = p / nx;
+    const int64_t j = r % ny, k = r / ny;
+    const float v = src[p];
+    float o = v;
+    if (dt > 0.0) {
+      const double s = (double)v * dt;
+      o = (float)(s * s);
+    }
+    dst[k * plane + j * pitch + i] = o;
+  }
+}
+
 // ---- plain copy (bandwidth reference) -------------------------------------------
 // Each thread moves four 16-byte words, all four loads issued before the
 // stores, so every wavefront keeps 4 KB in flight.
@@ -916,6 +938,16 @@ hipError_t launch_energy(const EnergyArgs& a, int storage, hipStream_t s) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(1024), 0, s, a.partial,
                      (int64_t)a.ny * a.nz, a.result);
+  return hipGetLastError();
+}
+
+hipError_t launch_setup_field(float* dst, const float* src, int nx, int ny, int nz, int pitch,
+                              int64_t plane, double dt, hipStream_t s) {
+  const int64_t n = (int64_t)nx * ny * nz;
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_setup_field, dim3((unsigned)blocks), dim3(256), 0, s, dst, src, nx, ny, n,
+                     pitch, plane, dt);
   return hipGetLastError();
 }
 

@@ -215,6 +215,9 @@ struct wave_ctx {
   bool timing;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t events_used;
+  hipEvent_t ev_join;         // orders a batch after this context's stream
+  hipEvent_t ev_left;         // batch work up to this context's removal
+  bool left_pending;          // the stream has not yet waited on ev_left
   double timing_ms;
   int64_t timing_launches;
 
@@ -375,6 +378,9 @@ struct wave_batch {
   hipStream_t user_stream;   // the members' stream
   hipStream_t stream;        // the batch's own stream (graphs can be captured on it)
   hipEvent_t ev_in, ev_out;
+  hipEvent_t ev_copy[2];      // table upload from pinned slot k done
+  char* pinned[2];            // pinned host copies of the tables, alternating
+  int64_t runs;               // runs issued (selects the pinned slot)
   char* arena;
   size_t arena_bytes;
   wave::BatchShot* d_shots;
@@ -387,10 +393,34 @@ struct wave_batch {
   int64_t total_blocks;
   bool layout_dirty;          // membership or tile shape changed
   int graph_steps;            // steps per captured graph (0 = plain launches)
-  hipGraphExec_t gexec;
-  bool graph_valid;
+  // captured step blocks, one per number of active members K (the active
+  // members are the first K: runs order members by steps left)
+  std::vector<std::pair<int, hipGraphExec_t>> graphs;
+  std::vector<int64_t> prefix_blocks;  // workgroups of the first k members
   bool broken;
 };
+
+namespace {
+// Orders the context stream after the batch work that touched the context:
+// the latest run while it is a member (unless its stream is the batch's
+// caller stream, which waits on every run already), or the runs up to its
+// removal.  Every context entry point that enqueues work calls it first.
+int join_batch_work(wave_ctx* c) {
+  if (c->batch && c->stream != c->batch->user_stream)
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->batch->ev_out, 0), "hipStreamWaitEvent");
+  if (c->left_pending) {
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_left, 0), "hipStreamWaitEvent");
+    c->left_pending = false;
+  }
+  return WAVE_OK;
+}
+}  // namespace
+
+#define JOIN_CTX(c)                          \
+  do {                                       \
+    const int _rc = join_batch_work(c);      \
+    if (_rc != WAVE_OK) return _rc;          \
+  } while (0)
 
 namespace {
 
@@ -417,7 +447,6 @@ int batch_fail(wave_batch* b, hipError_t e, const char* what) {
     if ((b)->broken) return fail(WAVE_ESTATE, "batch broken by an earlier device error");  \
   } while (0)
 
-// Rebuild the member tables (static part); targets are filled per run.
 // z-chunk length a streaming sweep of this context uses with tile (ry, nw):
 // the requested one (or the automatic one), cut to what the kernels' 32-bit
 // chunk window allows.  0 when even one plane is too large to stream.
@@ -428,8 +457,15 @@ int stream_zchunk(const wave_ctx* c, int ry, int nw, int zchunk) {
   return std::min(zc, lim);
 }
 
+void batch_drop_graphs(wave_batch* b) {
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.second);
+  b->graphs.clear();
+}
+
+// Rebuild the member tables (static part); targets are filled per run.
 void batch_layout(wave_batch* b) {
   b->h_shots.resize(b->members.size());
+  b->prefix_blocks.assign(1, 0);
   int64_t begin = 0;
   const int ty = b->ry * b->nw;
   for (size_t i = 0; i < b->members.size(); ++i) {
@@ -445,20 +481,40 @@ void batch_layout(wave_batch* b) {
     const int chunks = wave::stream_chunk_count(c->L.nz, c->d.w, e.zchunk, c->damp);
     e.block_begin = begin;
     begin += (int64_t)e.tiles_x * e.tiles_y * chunks;
+    b->prefix_blocks.push_back(begin);
     e.target = 0;
     e.inj = inject_args(c);
   }
   b->total_blocks = begin;
   b->layout_dirty = false;
-  b->graph_valid = false;
+  batch_drop_graphs(b);
 }
 
-hipError_t batch_launch_step(wave_batch* b) {
-  const int n = (int)b->members.size();
-  hipError_t e = wave::launch_sweep_batch(b->d_shots, b->d_state, n, b->total_blocks, b->storage,
-                                          b->ry, b->nw, b->stream);
+// One step of the first k members (those still taking steps in this run).
+hipError_t batch_launch_step(wave_batch* b, int k) {
+  hipError_t e = wave::launch_sweep_batch(b->d_shots, b->d_state, k, b->prefix_blocks[k],
+                                          b->storage, b->ry, b->nw, b->stream);
   if (e != hipSuccess) return e;
-  return wave::launch_inject_batch(b->d_shots, b->d_state, n, b->storage, b->stream);
+  return wave::launch_inject_batch(b->d_shots, b->d_state, k, b->storage, b->stream);
+}
+
+// The captured block of graph_steps steps for the first k members.
+hipError_t batch_graph(wave_batch* b, int k, hipGraphExec_t* out) {
+  for (auto& g : b->graphs)
+    if (g.first == k) {
+      *out = g.second;
+      return hipSuccess;
+    }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return e;
+  for (int t = 0; t < b->graph_steps && e == hipSuccess; ++t) e = batch_launch_step(b, k);
+  hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e == hipSuccess) b->graphs.emplace_back(k, *out);
+  return e;
 }
 
 }  // namespace
@@ -567,6 +623,9 @@ int wave_alloc(const wave_desc* d, const float* vel, const float* eta, void* dev
   c->zchunk = 0;
   c->timing = false;
   c->events_used = 0;
+  c->ev_join = nullptr;
+  c->ev_left = nullptr;
+  c->left_pending = false;
   c->timing_ms = 0.0;
   c->timing_launches = 0;
 
@@ -574,35 +633,37 @@ int wave_alloc(const wave_desc* d, const float* vel, const float* eta, void* dev
     delete c;
     return rc;
   };
+  // Set-up runs on the context stream without waiting between steps: zero
+  // the arena, bring the compact velocity (and eta) over in one copy each to
+  // a staging area (the two u arrays, zeroed again afterwards), and let
+  // kernels form vp = (V dt)^2 and scatter into the padded layout.
+  const size_t stage_bytes = plan.u[1] + (size_t)c->L.elems * c->es - plan.u[0];
+  if (n * 4 > stage_bytes) return bail(fail(WAVE_EINVAL, "internal: staging area too small"));
+  char* stage = c->at(plan.u[0]);
   hipError_t e = hipMemsetAsync(c->arena, 0, plan.total, c->stream);
-  if (e != hipSuccess) return bail(dev_fail(nullptr, e, "hipMemsetAsync"));
-  e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) return bail(dev_fail(nullptr, e, "hipStreamSynchronize"));
-
-  // vp = (V dt)^2 in double, rounded once to float
-  const size_t pn = (size_t)d->nx * d->ny;
-  std::vector<float> plane(pn);
-  for (int k = 0; k < d->nz; ++k) {
-    const float* vk = vel + (size_t)k * pn;
-    for (size_t p = 0; p < pn; ++p) {
-      const double v = (double)vk[p] * d->dt;
-      plane[p] = (float)(v * v);
-    }
-    int rc = upload_plane(c, c->at(plan.vp), 4, k, plane.data());
-    if (rc) return bail(rc);
+  if (e == hipSuccess) e = hipMemcpyAsync(stage, vel, n * 4, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = wave::launch_setup_field(reinterpret_cast<float*>(c->at(plan.vp)) + c->L.origin,
+                                 reinterpret_cast<const float*>(stage), d->nx, d->ny, d->nz,
+                                 c->L.pitch, c->L.plane, d->dt, c->stream);
+  if (e == hipSuccess && eta_array(d)) {
+    e = hipMemcpyAsync(stage, eta, n * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+      e = wave::launch_setup_field(reinterpret_cast<float*>(c->at(plan.eta)) + c->L.origin,
+                                   reinterpret_cast<const float*>(stage), d->nx, d->ny, d->nz,
+                                   c->L.pitch, c->L.plane, 0.0, c->stream);
   }
-  if (eta_array(d)) {
-    for (int k = 0; k < d->nz; ++k) {
-      int rc = upload_plane(c, c->at(plan.eta), 4, k, eta + (size_t)k * pn);
-      if (rc) return bail(rc);
-    }
-  } else if (damp) {
-    std::vector<unsigned char> t;
+  if (e == hipSuccess) e = hipMemsetAsync(stage, 0, stage_bytes, c->stream);
+  if (e != hipSuccess) return bail(dev_fail(nullptr, e, "set-up"));
+  std::vector<unsigned char> t;
+  if (damp && !eta_array(d)) {
     eta_tables(d, vmax, c->q, t);
-    hipError_t he = hipMemcpyAsync(c->at(plan.etab), t.data(), t.size(), hipMemcpyHostToDevice, c->stream);
-    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
-    if (he != hipSuccess) return bail(dev_fail(nullptr, he, "eta tables upload"));
+    e = hipMemcpyAsync(c->at(plan.etab), t.data(), t.size(), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return bail(dev_fail(nullptr, e, "eta tables upload"));
   }
+  // the host buffers above are pageable and local: wait once, here
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return bail(dev_fail(nullptr, e, "set-up"));
   *out = c;
   return WAVE_OK;
 }
@@ -610,11 +671,16 @@ int wave_alloc(const wave_desc* d, const float* vel, const float* eta, void* dev
 int wave_free(wave_ctx* c) {
   if (!c) return WAVE_OK;
   if (c->batch) (void)wave_batch_remove(c->batch, c);
-  if (!c->broken) (void)hipStreamSynchronize(c->stream);
+  if (!c->broken) {
+    (void)join_batch_work(c);
+    (void)hipStreamSynchronize(c->stream);
+  }
   for (auto& ev : c->events) {
     (void)hipEventDestroy(ev.first);
     (void)hipEventDestroy(ev.second);
   }
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->ev_left) (void)hipEventDestroy(c->ev_left);
   delete c;
   return WAVE_OK;
 }
@@ -622,6 +688,7 @@ int wave_free(wave_ctx* c) {
 int wave_inject(wave_ctx* c, int32_t i, int32_t j, int32_t k, const float* samples,
                 int32_t nsamples) {
   CHECK_CTX(c);
+  JOIN_CTX(c);
   if (!in_grid(c, i, j, k)) return fail(WAVE_EINVAL, "source index outside the grid");
   if (nsamples < 0 || nsamples > c->d.max_steps) return fail(WAVE_EINVAL, "nsamples outside [0, max_steps]");
   if (nsamples > 0 && !samples) return fail(WAVE_EINVAL, "samples is NULL");
@@ -642,6 +709,7 @@ int wave_inject(wave_ctx* c, int32_t i, int32_t j, int32_t k, const float* sampl
 
 int wave_record(wave_ctx* c, const int32_t* ijk, int32_t nrec) {
   CHECK_CTX(c);
+  JOIN_CTX(c);
   if (nrec < 0 || nrec > c->d.max_rec) return fail(WAVE_EINVAL, "nrec outside [0, max_rec]");
   if (nrec > 0 && !ijk) return fail(WAVE_EINVAL, "receiver list is NULL");
   std::vector<int64_t> off((size_t)std::max(nrec, 1));
@@ -662,6 +730,7 @@ int wave_record(wave_ctx* c, const int32_t* ijk, int32_t nrec) {
 
 int wave_step(wave_ctx* c, int32_t n) {
   CHECK_CTX(c);
+  JOIN_CTX(c);
   if (c->batch) return fail(WAVE_EINVAL, "context is a batch member (step it with wave_batch_run)");
   if (n < 0) return fail(WAVE_EINVAL, "n < 0");
   if (c->nrec > 0 && (int64_t)c->trace_count + n > c->d.max_steps)
@@ -711,6 +780,7 @@ int wave_step(wave_ctx* c, int32_t n) {
 
 int wave_sync(wave_ctx* c) {
   CHECK_CTX(c);
+  JOIN_CTX(c);
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   return WAVE_OK;
 }
@@ -719,6 +789,7 @@ int64_t wave_step_count(const wave_ctx* c) { return c ? c->step : -1; }
 
 int wave_read_field(wave_ctx* c, int32_t which, float* out) {
   CHECK_CTX(c);
+  JOIN_CTX(c);
   if (!out) return fail(WAVE_EINVAL, "out is NULL");
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   const size_t pn = (size_t)c->L.nx * c->L.ny;
@@ -750,6 +821,7 @@ int wave_read_field(wave_ctx* c, int32_t which, float* out) {
 
 int wave_write_field(wave_ctx* c, int32_t which, const float* in) {
   CHECK_CTX(c);
+  JOIN_CTX(c);
   if (!in) return fail(WAVE_EINVAL, "input is NULL");
   const size_t n = (size_t)c->L.nx * c->L.ny * c->L.nz;
   for (size_t p = 0; p < n; ++p)
@@ -773,6 +845,7 @@ int wave_write_field(wave_ctx* c, int32_t which, const float* in) {
 
 int wave_read_traces(wave_ctx* c, double* out, int32_t* steps_out) {
   CHECK_CTX(c);
+  JOIN_CTX(c);
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   if (steps_out) *steps_out = c->trace_count;
   if (out && c->nrec > 0 && c->trace_count > 0) {
@@ -787,6 +860,7 @@ int wave_read_traces(wave_ctx* c, double* out, int32_t* steps_out) {
 
 int wave_energy(wave_ctx* c, double* out) {
   CHECK_CTX(c);
+  JOIN_CTX(c);
   if (!out) return fail(WAVE_EINVAL, "out is NULL");
   wave::EnergyArgs ea;
   ea.cur = c->u_origin(c->cur);
@@ -902,6 +976,7 @@ int wave_tune(wave_ctx* c, int32_t trial_steps, int32_t chosen[3]) {
 
 int wave_set_timing(wave_ctx* c, int32_t on) {
   CHECK_CTX(c);
+  JOIN_CTX(c);
   c->timing = on != 0;
   c->events_used = 0;
   c->timing_ms = 0.0;
@@ -911,6 +986,7 @@ int wave_set_timing(wave_ctx* c, int32_t on) {
 
 int wave_read_timing(wave_ctx* c, double* ms_total, int64_t* launches) {
   CHECK_CTX(c);
+  JOIN_CTX(c);
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   for (size_t k = 0; k < c->events_used; ++k) {
     float ms = 0.0f;
@@ -954,6 +1030,21 @@ size_t wave_batch_bytes_required(int32_t max_shots) {
   return batch_table_bytes(max_shots, nullptr);
 }
 
+namespace {
+// Releases what wave_batch_create acquired (any subset of it).
+void batch_release(wave_batch* b) {
+  batch_drop_graphs(b);
+  for (int k = 0; k < 2; ++k) {
+    if (b->ev_copy[k]) (void)hipEventDestroy(b->ev_copy[k]);
+    if (b->pinned[k]) (void)hipHostFree(b->pinned[k]);
+  }
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+}  // namespace
+
 int wave_batch_create(int32_t storage, int32_t max_shots, void* dev_arena, size_t arena_bytes,
                       void* hip_stream, wave_batch** out) {
   if (!out) return fail(WAVE_EINVAL, "out is NULL");
@@ -978,15 +1069,21 @@ int wave_batch_create(int32_t storage, int32_t max_shots, void* dev_arena, size_
   b->total_blocks = 0;
   b->layout_dirty = true;
   b->graph_steps = 0;
-  b->gexec = nullptr;
-  b->graph_valid = false;
   b->broken = false;
+  b->runs = 0;
+  b->stream = nullptr;
+  b->ev_in = b->ev_out = b->ev_copy[0] = b->ev_copy[1] = nullptr;
+  b->pinned[0] = b->pinned[1] = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    e = hipEventCreateWithFlags(&b->ev_copy[k], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->pinned[k]), need, hipHostMallocDefault);
+  }
   if (e != hipSuccess) {
-    delete b;
-    return fail(WAVE_EDEVICE, std::string("batch stream/events: ") + hipGetErrorString(e));
+    batch_release(b);
+    return fail(WAVE_EDEVICE, std::string("batch stream/events/pinned tables: ") + hipGetErrorString(e));
   }
   *out = b;
   return WAVE_OK;
@@ -997,7 +1094,6 @@ int wave_batch_add(wave_batch* b, wave_ctx* c, int32_t nsteps) {
   CHECK_CTX(c);
   if (c->batch) return fail(WAVE_EINVAL, "context already in a batch");
   if (c->d.storage != b->storage) return fail(WAVE_EINVAL, "storage type differs from the batch's");
-  if (c->stream != b->user_stream) return fail(WAVE_EINVAL, "context stream differs from the batch's");
   if ((int)b->members.size() >= b->max_shots) return fail(WAVE_EINVAL, "batch full");
   if (nsteps < 0) return fail(WAVE_EINVAL, "nsteps < 0");
   if (c->nrec > 0 && (int64_t)c->trace_count + nsteps > c->d.max_steps)
@@ -1005,6 +1101,13 @@ int wave_batch_add(wave_batch* b, wave_ctx* c, int32_t nsteps) {
   if (c->step + nsteps > 0x7fffffff) return fail(WAVE_EINVAL, "step counter overflow");
   if (wave::stream_zchunk_limit(c->L.plane) < 1)
     return fail(WAVE_EINVAL, "z planes too large for the batched streaming kernel");
+  // the batch's launches come after everything queued so far on the member's stream
+  JOIN_CTX(c);
+  if (c->stream != b->user_stream) {
+    if (!c->ev_join) HIPCHK(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "hipEventCreate");
+    HIPCHK(c, hipEventRecord(c->ev_join, c->stream), "hipEventRecord");
+    BCHK(b, hipStreamWaitEvent(b->stream, c->ev_join, 0), "hipStreamWaitEvent");
+  }
   b->members.push_back(c);
   b->remaining.push_back(nsteps);
   c->batch = b;
@@ -1024,6 +1127,12 @@ int wave_batch_remove(wave_batch* b, wave_ctx* c) {
   }
   c->batch = nullptr;
   b->layout_dirty = true;
+  if (c->stream != b->user_stream && !b->broken) {
+    // the context's next work waits for the runs it took part in
+    if (!c->ev_left) HIPCHK(c, hipEventCreateWithFlags(&c->ev_left, hipEventDisableTiming), "hipEventCreate");
+    HIPCHK(c, hipEventRecord(c->ev_left, b->stream), "hipEventRecord");
+    c->left_pending = true;
+  }
   return WAVE_OK;
 }
 
@@ -1050,7 +1159,7 @@ int wave_batch_set_graph(wave_batch* b, int32_t steps_per_graph) {
   CHECK_BATCH(b);
   if (steps_per_graph < 0 || steps_per_graph > 4096) return fail(WAVE_EINVAL, "steps_per_graph outside [0, 4096]");
   b->graph_steps = steps_per_graph;
-  b->graph_valid = false;
+  batch_drop_graphs(b);
   return WAVE_OK;
 }
 
@@ -1061,6 +1170,29 @@ int wave_batch_run(wave_batch* b, int32_t n) {
     if (c->broken) return fail(WAVE_ESTATE, "a member context is broken");
   const size_t nm = b->members.size();
   if (nm == 0 || n == 0) return WAVE_OK;
+  // members ordered by the steps they take in this run, most first: at every
+  // step the members still running are a prefix, and only their workgroups
+  // are launched
+  {
+    std::vector<size_t> order(nm);
+    for (size_t i = 0; i < nm; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+      return std::min(b->remaining[x], n) > std::min(b->remaining[y], n);
+    });
+    bool moved = false;
+    for (size_t i = 0; i < nm; ++i) moved = moved || order[i] != i;
+    if (moved) {
+      std::vector<wave_ctx*> m(nm);
+      std::vector<int32_t> r(nm);
+      for (size_t i = 0; i < nm; ++i) {
+        m[i] = b->members[order[i]];
+        r[i] = b->remaining[order[i]];
+      }
+      b->members.swap(m);
+      b->remaining.swap(r);
+      b->layout_dirty = true;
+    }
+  }
   if (b->layout_dirty) batch_layout(b);
   // per-run targets and start state
   int32_t steps = 0;
@@ -1079,39 +1211,44 @@ int wave_batch_run(wave_batch* b, int32_t n) {
   // order after the caller's stream, upload tables, launch
   BCHK(b, hipEventRecord(b->ev_in, b->user_stream), "hipEventRecord");
   BCHK(b, hipStreamWaitEvent(b->stream, b->ev_in, 0), "hipStreamWaitEvent");
-  BCHK(b, hipMemcpyAsync(b->d_shots, b->h_shots.data(), nm * sizeof(wave::BatchShot), hipMemcpyHostToDevice, b->stream),
-       "hipMemcpyAsync");
-  BCHK(b, hipMemcpyAsync(b->d_state, b->h_state.data(), nm * sizeof(wave::BatchState), hipMemcpyHostToDevice, b->stream),
-       "hipMemcpyAsync");
-  // the host copies are pageable: wait so the vectors may change afterwards
-  BCHK(b, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
-  int32_t left = steps;
-  if (b->graph_steps > 0 && steps >= b->graph_steps) {
-    if (!b->graph_valid) {
-      if (b->gexec) {
-        (void)hipGraphExecDestroy(b->gexec);
-        b->gexec = nullptr;
-      }
-      hipGraph_t g = nullptr;
-      BCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
-      hipError_t e = hipSuccess;
-      for (int t = 0; t < b->graph_steps && e == hipSuccess; ++t) e = batch_launch_step(b);
-      hipError_t e2 = hipStreamEndCapture(b->stream, &g);
-      if (e != hipSuccess) return batch_fail(b, e, "batch launch during capture");
-      if (e2 != hipSuccess) return batch_fail(b, e2, "hipStreamEndCapture");
-      e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (e != hipSuccess) return batch_fail(b, e, "hipGraphInstantiate");
-      b->graph_valid = true;
-    }
-    while (left >= b->graph_steps) {
-      BCHK(b, hipGraphLaunch(b->gexec, b->stream), "hipGraphLaunch");
-      left -= b->graph_steps;
-    }
+  // tables go up from a pinned slot (asynchronous); a slot is rewritten only
+  // after the copy that last used it has completed, so runs queue up without
+  // waiting for each other
+  {
+    const int k = (int)(b->runs & 1);
+    BCHK(b, hipEventSynchronize(b->ev_copy[k]), "hipEventSynchronize");
+    size_t soff = 0;
+    (void)batch_table_bytes(b->max_shots, &soff);
+    memcpy(b->pinned[k], b->h_shots.data(), nm * sizeof(wave::BatchShot));
+    memcpy(b->pinned[k] + soff, b->h_state.data(), nm * sizeof(wave::BatchState));
+    BCHK(b, hipMemcpyAsync(b->d_shots, b->pinned[k], nm * sizeof(wave::BatchShot), hipMemcpyHostToDevice, b->stream),
+         "hipMemcpyAsync");
+    BCHK(b, hipMemcpyAsync(b->d_state, b->pinned[k] + soff, nm * sizeof(wave::BatchState), hipMemcpyHostToDevice,
+                           b->stream),
+         "hipMemcpyAsync");
+    BCHK(b, hipEventRecord(b->ev_copy[k], b->stream), "hipEventRecord");
+    b->runs += 1;
   }
-  for (; left > 0; --left) {
-    hipError_t e = batch_launch_step(b);
-    if (e != hipSuccess) return batch_fail(b, e, "batch launch");
+  // segments of constant active count k: steps [j, t_{k-1}) run the first k
+  // members; whole captured blocks where a segment is long enough
+  int32_t j = 0;
+  size_t k = nm;
+  while (j < steps) {
+    while (k > 0 && b->h_shots[k - 1].target <= j) --k;
+    const int32_t seg_end = b->h_shots[k - 1].target;
+    int32_t left = seg_end - j;
+    if (b->graph_steps > 0 && left >= b->graph_steps) {
+      hipGraphExec_t g = nullptr;
+      hipError_t e = batch_graph(b, (int)k, &g);
+      if (e != hipSuccess) return batch_fail(b, e, "batch graph capture");
+      for (; left >= b->graph_steps; left -= b->graph_steps)
+        BCHK(b, hipGraphLaunch(g, b->stream), "hipGraphLaunch");
+    }
+    for (; left > 0; --left) {
+      hipError_t e = batch_launch_step(b, (int)k);
+      if (e != hipSuccess) return batch_fail(b, e, "batch launch");
+    }
+    j = seg_end;
   }
   BCHK(b, hipEventRecord(b->ev_out, b->stream), "hipEventRecord");
   BCHK(b, hipStreamWaitEvent(b->user_stream, b->ev_out, 0), "hipStreamWaitEvent");
@@ -1174,11 +1311,7 @@ int wave_batch_free(wave_batch* b) {
   if (!b) return WAVE_OK;
   if (!b->broken) (void)hipStreamSynchronize(b->stream);
   for (wave_ctx* c : b->members) c->batch = nullptr;
-  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-  (void)hipEventDestroy(b->ev_in);
-  (void)hipEventDestroy(b->ev_out);
-  (void)hipStreamDestroy(b->stream);
-  delete b;
+  batch_release(b);
   return WAVE_OK;
 }
 

@@ -10,7 +10,8 @@ numerical work happens in the HIP library through `wave`; this module only
 schedules.
 
 A request's result is identical to a run of the same shot on its own: batch
-members take exactly the steps and arithmetic of a solo run.
+members take exactly the steps and arithmetic of a solo run.  Set-up and
+read-out of requests overlap with the blocks running on the GPU.
 """
 from __future__ import annotations
 
@@ -49,9 +50,16 @@ class Request:
 
 class Executor:
     """The device side of the server (a seam so that scheduling can be tested
-    on the CPU with a fake).  `start` allocates and admits a request into its
-    batch, `advance` runs every batch by up to n steps and waits, `remaining`
-    and `finish` read a request out and release it."""
+    on the CPU with a fake).
+
+    start     allocate a request and add it to the batch of its storage type
+    launch    enqueue up to n steps for every admitted request, return a token
+    wait      block until the launch behind a token has completed
+    remaining steps a request has left after everything launched so far
+    detach    take a request with no steps left out of its batch (no wait)
+    finish    read a detached request out and release it (after the launch
+              that completed it has been waited for)
+    """
 
     def bytes_for(self, req: Request) -> int:
         raise NotImplementedError
@@ -59,10 +67,16 @@ class Executor:
     def start(self, req: Request) -> None:
         raise NotImplementedError
 
-    def advance(self, n: int) -> None:
+    def launch(self, n: int):
+        raise NotImplementedError
+
+    def wait(self, token) -> None:
         raise NotImplementedError
 
     def remaining(self, req: Request) -> int:
+        raise NotImplementedError
+
+    def detach(self, req: Request) -> None:
         raise NotImplementedError
 
     def finish(self, req: Request, keep_field: bool) -> None:
@@ -70,6 +84,11 @@ class Executor:
 
 
 class GpuExecutor(Executor):
+    """Batches per storage type on the caller's stream; set-up and read-out
+    of requests on a stream of their own, so that they overlap with the
+    blocks the batches are running (the library orders the two with
+    events)."""
+
     def __init__(self, device="cuda:0", graph_steps=0, max_shots=128):
         import torch
         self.torch = torch
@@ -78,6 +97,8 @@ class GpuExecutor(Executor):
         self.max_shots = max_shots
         self.batches: Dict[str, W.Batch] = {}
         self.shots: Dict[int, W.Shot] = {}
+        self.run_stream = torch.cuda.current_stream(device)
+        self.io_stream = torch.cuda.Stream(device=device)
 
     def bytes_for(self, req: Request) -> int:
         s = req.shot
@@ -89,29 +110,39 @@ class GpuExecutor(Executor):
     def _batch(self, storage: str) -> W.Batch:
         b = self.batches.get(storage)
         if b is None:
-            b = W.Batch(storage=storage, max_shots=self.max_shots, device=self.device)
+            b = W.Batch(storage=storage, max_shots=self.max_shots, device=self.device,
+                        stream=self.run_stream)
             b.set_graph(self.graph_steps)
             self.batches[storage] = b
         return b
 
     def start(self, req: Request) -> None:
-        sh = W.shot_from_synth(req.shot, storage=req.storage, device=self.device)
+        sh = W.shot_from_synth(req.shot, storage=req.storage, device=self.device,
+                               stream=self.io_stream)
         self._batch(req.storage).add(sh, int(req.shot.steps))
         self.shots[req.rid] = sh
 
-    def advance(self, n: int) -> None:
+    def launch(self, n: int):
         for b in self.batches.values():
             if b.members:
                 b.run(n)
-        self.torch.cuda.synchronize(self.device)
+        ev = self.torch.cuda.Event()
+        ev.record(self.run_stream)      # the caller's stream waits on every run
+        return ev
+
+    def wait(self, token) -> None:
+        token.synchronize()
 
     def remaining(self, req: Request) -> int:
         sh = self.shots[req.rid]
-        return self.batches[req.storage].remaining(sh)
+        b = self.batches[req.storage]
+        return b.remaining(sh) if sh in b.members else 0
+
+    def detach(self, req: Request) -> None:
+        self.batches[req.storage].remove(self.shots[req.rid])
 
     def finish(self, req: Request, keep_field: bool) -> None:
         sh = self.shots.pop(req.rid)
-        self.batches[req.storage].remove(sh)
         req.traces = sh.traces()
         if keep_field:
             req.field = sh.read(W.WAVE_FIELD_U)
@@ -128,7 +159,14 @@ class Server:
 
     run(requests) replays the requests' arrival times against the wall clock
     (time_scale < 1 compresses them) and returns the requests with their
-    latencies.  A request larger than the whole budget is rejected."""
+    latencies.  A request larger than the whole budget is rejected.
+
+    The loop keeps one block in flight: it admits what has arrived, enqueues
+    the next block, takes the requests that this block completes out of
+    their batches, and only then waits for the previous block and reads out
+    the requests it completed, so the GPU has queued work while the host
+    does set-up and read-out.  A finished request holds its memory until it
+    has been read out."""
 
     def __init__(self, executor: Executor, budget_bytes: int, block_steps: int = 50,
                  clock: Callable[[], float] = time.perf_counter,
@@ -148,9 +186,10 @@ class Server:
         active: List[Request] = []
         sizes: Dict[int, int] = {}
         done: List[Request] = []
+        inflight = None                  # (token, requests that block completes)
         t0 = self.clock()
         now = lambda: (self.clock() - t0) / time_scale
-        while pending or waiting or active:
+        while pending or waiting or active or inflight is not None:
             t = now()
             while pending and pending[0].arrival <= t:
                 waiting.append(pending.popleft())
@@ -174,19 +213,26 @@ class Server:
                 r.admitted = now()
                 active.append(r)
                 self.log.append(("admit", r.rid, r.admitted, self.in_use))
-            if not active:
-                if pending:
-                    self.sleep(max(0.0, (pending[0].arrival - now()) * time_scale))
-                continue
-            self.ex.advance(self.block)
-            for r in list(active):
-                if self.ex.remaining(r) == 0:
+            launched = None
+            if active:
+                token = self.ex.launch(self.block)
+                ending = [r for r in active if self.ex.remaining(r) == 0]
+                for r in ending:
+                    self.ex.detach(r)
+                    active.remove(r)
+                launched = (token, ending)
+            if inflight is not None:
+                token, ending = inflight
+                self.ex.wait(token)
+                for r in ending:
                     self.ex.finish(r, keep_field=r.rid in keep_fields)
                     r.finished = now()
-                    active.remove(r)
                     self.in_use -= sizes.pop(r.rid)
                     done.append(r)
                     self.log.append(("finish", r.rid, r.finished, self.in_use))
+            inflight = launched
+            if not active and inflight is None and not waiting and pending:
+                self.sleep(max(0.0, (pending[0].arrival - now()) * time_scale))
         return sorted(done, key=lambda r: r.rid)
 
 

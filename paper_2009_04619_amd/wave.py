@@ -312,8 +312,11 @@ class Shot:
         if nbytes == 0:
             raise WaveError(WAVE_EINVAL, "wave_bytes_required")
         self.nbytes = nbytes
-        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # the arena belongs to the context's stream (the caching allocator
+        # reuses it there only after the context has waited for its work)
+        with torch.cuda.stream(self.stream):
+            self.arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         vel = np.ascontiguousarray(vel, dtype=np.float32)
         assert vel.shape == (nz, ny, nx)
         eta_a = None if (eta is None or not damping) else np.ascontiguousarray(eta, dtype=np.float32)
@@ -396,14 +399,15 @@ class Shot:
             pass
 
 
-def shot_from_synth(s, storage="f32", damping=True, device="cuda:0", max_steps=None, eta=None):
+def shot_from_synth(s, storage="f32", damping=True, device="cuda:0", max_steps=None, eta=None,
+                    stream=None):
     """A `Shot` for a synth.Shot (sources injected, receivers set)."""
     steps = s.steps if max_steps is None else max_steps
     nrec = 0 if s.rec is None else len(s.rec)
     sh = Shot(s.nx, s.ny, s.nz, s.w, s.dx, s.dy, s.dz, s.dt, s.vel, eta=eta, storage=storage,
               damping=damping, max_src=max(1, len(s.src)), max_rec=nrec,
               max_steps=max(steps, s.wavelet.shape[1] if s.wavelet is not None else 0),
-              device=device)
+              device=device, stream=stream)
     for q, (i, j, k) in enumerate(s.src):
         sh.inject(i, j, k, s.wavelet[q])
     if nrec:
@@ -414,7 +418,8 @@ def shot_from_synth(s, storage="f32", damping=True, device="cuda:0", max_steps=N
 class Batch:
     """Several `Shot`s advanced together (one sweep launch per step for all).
 
-    All members share the batch's storage type and the torch stream."""
+    All members share the batch's storage type; their streams may differ
+    from the batch's (the library orders them with events)."""
 
     def __init__(self, storage="f32", max_shots=64, device="cuda:0", stream=None):
         self.device = torch.device(device)

@@ -187,3 +187,27 @@ def test_tuned_runs_stay_exact(W):
     b.close()
     for x in m:
         x.close()
+
+
+def test_members_on_another_stream(W):
+    """Members set up on a stream other than the batch's: the batch waits for
+    their set-up, and a member that leaves waits for the runs it took part in
+    before its own next step and reads."""
+    import torch
+    shots = shots_for(SHAPES[:3], seed0=500)
+    say("case members on another stream")
+    ref = [solo(W, s) for s in shots]
+    side = torch.cuda.Stream()
+    b = W.Batch(max_shots=4)
+    m = [W.shot_from_synth(s, stream=side) for s in shots]
+    for s, x in zip(shots, m):
+        b.add(x, s.steps)
+    b.run(7)
+    b.remove(m[0])                    # leaves midway, continues on the side stream
+    m[0].step(shots[0].steps - 7)
+    b.run(100)
+    for q in range(3):
+        same(read_all(W, m[q]), ref[q], f"member {q}")
+    b.close()
+    for x in m:
+        x.close()

@@ -19,15 +19,18 @@ class FakeClock:
 
 
 class FakeExecutor(Executor):
-    """Each request needs `steps`; advance(n) moves every admitted request
-    by n steps and costs `sec_per_step` of simulated time."""
+    """Each request needs `steps`; launch(n) moves every admitted request by
+    n steps and costs `sec_per_step` of simulated time."""
 
     def __init__(self, clock, sec_per_step=0.001, fail_on=None):
         self.clock = clock
         self.sps = sec_per_step
         self.left = {}
         self.started = []
+        self.detached = []
         self.finished = []
+        self.waited = []
+        self.launches = 0
         self.fail_on = fail_on
 
     def bytes_for(self, r):
@@ -37,15 +40,27 @@ class FakeExecutor(Executor):
         self.left[r.rid] = r.shot.steps
         self.started.append(r.rid)
 
-    def advance(self, n):
+    def launch(self, n):
         self.clock.t += n * self.sps
         for k in self.left:
-            self.left[k] = max(0, self.left[k] - n)
+            if k not in self.detached:
+                self.left[k] = max(0, self.left[k] - n)
+        self.launches += 1
+        return self.launches
+
+    def wait(self, token):
+        self.waited.append(token)
 
     def remaining(self, r):
         return self.left[r.rid]
 
+    def detach(self, r):
+        assert self.left[r.rid] == 0
+        self.detached.append(r.rid)
+
     def finish(self, r, keep_field):
+        # read out only after the launch that completed it has been waited for
+        assert r.rid in self.detached and self.waited and self.waited[-1] <= self.launches
         del self.left[r.rid]
         self.finished.append(r.rid)
         r.traces = "traces"
@@ -103,3 +118,18 @@ def test_idle_server_sleeps_until_next_arrival():
     done = srv.run([req(0, 5.0, 10, 10)])
     assert done[0].admitted >= 5.0
     assert done[0].latency == pytest.approx(10 * 0.001, abs=1e-3)
+
+
+def test_next_block_is_queued_before_the_previous_is_collected():
+    """Read-out of the requests a block completes happens after the next
+    block has been launched (one block in flight), and every launch is
+    waited for exactly once."""
+    clk = FakeClock()
+    ex = FakeExecutor(clk)
+    srv = Server(ex, budget_bytes=1000, block_steps=10, clock=clk, sleep=clk.sleep)
+    srv.run([req(0, 0.0, 10, 10), req(1, 0.0, 30, 10)])
+    assert ex.finished == [0, 1]
+    assert sorted(ex.waited) == list(range(1, ex.launches + 1))
+    # request 0 completes with launch 1 and is read out after launch 2 was issued
+    fin = {e[1]: e[2] for e in srv.log if e[0] == "finish"}
+    assert fin[0] == pytest.approx(2 * 10 * 0.001)

@@ -229,8 +229,12 @@ def main():
     log(f"[bench] building workload {args.n}^3 w{args.w}")
     total = args.warmup + args.steps
     shot = synth.config_c2(steps=total + 64, n=args.n, w=args.w)
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
     sh = W.shot_from_synth(shot, storage=args.storage,
                            max_steps=total + 64 + args.roofline_steps)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - s0          # host-to-device set-up (vel over PCIe)
     stream = sh.stream
     log(f"[bench] warmup {args.warmup} steps")
     if args.kernel == "tune":
@@ -272,8 +276,11 @@ def main():
     traffic = measured_traffic(workload, alg_bytes)
     log(f"[bench] sweep kernel avg {avg_ms:.4f} ms over {launches} launches, "
         f"{alg_bytes / pts:.2f} B/pt algorithmic -> {achieved:.0f} GB/s")
+    r0 = time.perf_counter()
     tr = sh.traces()
+    readout_s = time.perf_counter() - r0        # receiver traces back to the host
     assert np.isfinite(tr).all()
+    log(f"[bench] set-up {setup_s * 1e3:.1f} ms, trace read-out {readout_s * 1e3:.1f} ms")
     sh.close()
     del sh
 
@@ -312,9 +319,14 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": None if traffic is None else round(traffic / 1e9, 4),
+                     "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "kernel": "k_sweep_stream", "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_kernel_ms": round(avg_ms, 5)},
         "copy_gbps": None if copy_gbs is None else round(copy_gbs, 1),
+        "host_io": {"setup_s": round(setup_s, 4), "trace_readout_s": round(readout_s, 4),
+                    "value_incl_host_io": round(pts * args.steps / (ms / 1e3 + setup_s + readout_s) / 1e9, 3),
+                    "note": "value with the set-up (velocity upload, vp) and the trace read-out "
+                            "added to the timed steps"},
         "extras": extras,
         "cpu_baseline": cpu,
     }

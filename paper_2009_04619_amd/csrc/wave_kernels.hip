@@ -885,15 +885,15 @@ int stream_zchunk_limit(int64_t plane) {
 }
 
 int auto_zchunk(int nx, int ny, int nz, int ry, int nw) {
-  // enough workgroups to give every CU several (256 CUs), but chunks long
-  // enough that the 8-plane queue warm-up stays a small overhead
+  // About nz/16 planes (the measured optimum at 512^3 and 1024^3: short
+  // enough that tiles of unequal cost balance over many workgroups per CU),
+  // shortened further when the grid would have fewer than ~8192 workgroups,
+  // but at least 32 planes so a chunk's 8-plane warm-up stays a modest cost.
   const int64_t tiles = (int64_t)((nx + kTX - 1) / kTX) * ((ny + ry * nw - 1) / (ry * nw));
-  int64_t chunks = (2048 + tiles - 1) / tiles;
-  if (chunks < 1) chunks = 1;
-  int zc = (int)((nz + chunks - 1) / chunks);
-  const int minz = nz < 32 ? nz : 32;
-  if (zc < minz) zc = minz;
-  return zc;
+  const int64_t chunks = (8192 + tiles - 1) / tiles;
+  int zc = std::min<int64_t>(nz / 16, (nz + chunks - 1) / chunks);
+  zc = std::max(zc, 32);
+  return std::min(zc, nz);
 }
 
 hipError_t launch_sweep_direct(const SweepArgs& a, int storage, hipStream_t s) {

@@ -58,6 +58,11 @@ def solo(W, s, storage="f32"):
     return r
 
 
+def rel_l2(a, b):
+    n = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / n) if n > 0 else float(np.linalg.norm(a))
+
+
 def same(a, b, what):
     assert a["n"] == b["n"], what
     for k in ("u", "u_prev", "phi", "traces"):
@@ -91,6 +96,15 @@ def test_batch_members_equal_solo_runs(W, storage, graph):
     # and one member against the oracle directly
     o = oracle.run_shot(shots[1], precision="f32", storage=storage)
     assert np.array_equal(got[1]["u"], o["u"]) and np.array_equal(got[1]["traces"], o["traces"])
+    # every member against float64, within its storage type's bound
+    worst = 0.0
+    for q, (g, s) in enumerate(zip(got, shots)):
+        o64 = oracle.run_shot(s, precision="f64")
+        err = max(rel_l2(g["u"], o64["u"]), rel_l2(g["traces"], o64["traces"]))
+        lim = 1e-5 if storage == "f32" else 2.0 * np.sqrt(s.steps) * 2.0 ** -8
+        assert err < lim, (q, storage, err, lim)
+        worst = max(worst, err)
+    say(f"batch {storage}: max rel L2 vs float64 over members {worst:.2e}")
 
 
 def test_graph_replays_match_plain_launches_across_runs(W):

@@ -53,11 +53,11 @@ struct StF32 {
   }
 };
 
+// float -> bfloat16, round to nearest even: gfx950 converts in one
+// instruction (v_cvt_pk_bf16_f32), subnormals included (the library runs
+// with float32 denormals enabled).
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 
 struct StBF16 {

@@ -32,22 +32,39 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_sha() -> str:
-    p = os.path.join(ROOT, "paper_2009_04619_amd", "csrc", "wave_kernels.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+# sweep kernel of each variant: name, profile prefix, sources it is built from
+KERNELS = {1: ("k_sweep_stream", "sweep", ("wave_kernels.hip", "wave_point.h")),
+           2: ("k_sweep2", "sweep2", ("wave_kernels2.hip", "wave_point.h"))}
 
 
-def measured_traffic(workload: str, launches_bytes: float):
+def kernel_source_sha(variant: int = 1) -> str:
+    h = hashlib.sha256()
+    for f in KERNELS[variant][2]:
+        h.update(open(os.path.join(ROOT, "paper_2009_04619_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def describe(cfg) -> str:
+    v, ry, nw, zc = cfg
+    if v == 2:
+        return f"two-step (3.5-D) zchunk={zc}"
+    if v == 0:
+        return "direct"
+    return f"stream rows_per_wave={ry} waves_per_group={nw} zchunk={zc}"
+
+
+def measured_traffic(workload: str, launches_bytes: float, variant: int = 1):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel source; else None."""
-    p = os.path.join(ROOT, "profiles", f"traffic_sweep_{workload}.json")
+    name, prefix, _ = KERNELS[variant]
+    p = os.path.join(ROOT, "profiles", f"traffic_{prefix}_{workload}.json")
     if not os.path.exists(p):
         return None
     try:
         t = json.load(open(p))
     except Exception:
         return None
-    if t.get("kernel_sha") != kernel_source_sha():
+    if t.get("kernel_sha") != kernel_source_sha(variant):
         return None
     return float(t["hbm_bytes_per_launch"])
 
@@ -76,8 +93,8 @@ def plain_rate(W, torch, n, w, storage, steps):
     kernel's algorithmic GB/s."""
     import synth
     shot = synth.config_c2(steps=steps + 20 + 64, n=n, w=w)
-    sh = W.shot_from_synth(shot, storage=storage, max_steps=steps + 20 + 50 + 64)
-    sh.tune(2)
+    sh = W.shot_from_synth(shot, storage=storage, max_steps=steps + 20 + 50 + 64, two_step=True)
+    cfg = sh.tune(2)
     sh.step(max(0, 20 - sh.step_count))
     sh.sync()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -93,8 +110,8 @@ def plain_rate(W, torch, n, w, storage, steps):
     sh.close()
     log(f"[bench] {storage} {n}^3: {shot.points * steps / ms / 1e6:.1f} Gpt/s, sweep {gbs:.0f} GB/s")
     return {"value": round(shot.points * steps / ms / 1e6, 3), "unit": "Gpoints/s",
-            "storage": storage, "steps": steps, "sweep_gbps_algorithmic": round(gbs, 1),
-            "frac": round(gbs / PEAK_HBM_GBS, 4)}
+            "storage": storage, "steps": steps, "kernel": describe(cfg),
+            "sweep_gbps_algorithmic": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
 
 
 def batched_rate(W, torch, count):
@@ -209,6 +226,8 @@ def main():
     ap.add_argument("--kernel", default="tune",
                     help="'tune' (autotune during warmup) or variant,rows_per_wave,waves_per_group,zchunk")
     ap.add_argument("--roofline-steps", type=int, default=200)
+    ap.add_argument("--single-step", action="store_true",
+                    help="do not offer the two-step kernel to the tuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-copy", action="store_true")
@@ -234,7 +253,8 @@ def main():
     torch.cuda.synchronize()
     s0 = time.perf_counter()
     sh = W.shot_from_synth(shot, storage=args.storage,
-                           max_steps=total + 64 + args.roofline_steps)
+                           max_steps=total + 64 + args.roofline_steps,
+                           two_step=not args.single_step)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - s0          # host-to-device set-up (vel over PCIe)
     stream = sh.stream
@@ -242,13 +262,14 @@ def main():
     if args.kernel == "tune":
         # the tuner's trials are ordinary steps of this run (every tile shape
         # computes identical results); they count toward the warmup
-        cfg = sh.tune(max(1, min(4, args.warmup // 12)))
-        kernel = f"stream rows_per_wave={cfg[0]} waves_per_group={cfg[1]} zchunk={cfg[2]} (tuned)"
+        cfg = sh.tune(max(1, min(4, args.warmup // 16)))
+        kernel = describe(cfg) + " (tuned)"
         log(f"[bench] tuned: {kernel} after {sh.step_count} steps")
     else:
         k = [int(v) for v in args.kernel.split(",")]
         sh.set_kernel(*k)
-        kernel = args.kernel
+        cfg = tuple(k)
+        kernel = describe(cfg)
     sh.step(max(0, args.warmup - sh.step_count))
     sh.sync()
 
@@ -275,7 +296,8 @@ def main():
     alg_bytes = sh.sweep_bytes()
     achieved = alg_bytes / (avg_ms / 1e3) / 1e9
     workload = f"{args.n}cube_w{args.w}_{args.storage}"
-    traffic = measured_traffic(workload, alg_bytes)
+    variant = 2 if cfg[0] == 2 else 1
+    traffic = measured_traffic(workload, alg_bytes, variant)
     log(f"[bench] sweep kernel avg {avg_ms:.4f} ms over {launches} launches, "
         f"{alg_bytes / pts:.2f} B/pt algorithmic -> {achieved:.0f} GB/s")
     r0 = time.perf_counter()
@@ -322,7 +344,7 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": None if traffic is None else round(traffic / 1e9, 4),
                      "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
-                     "kernel": "k_sweep_stream", "algorithmic_bytes_per_launch": alg_bytes,
+                     "kernel": KERNELS[variant][0], "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_kernel_ms": round(avg_ms, 5)},
         "copy_gbps": None if copy_gbs is None else round(copy_gbs, 1),
         "host_io": {"setup_s": round(setup_s, 4), "trace_readout_s": round(readout_s, 4),

@@ -58,6 +58,10 @@ typedef enum wave_storage { WAVE_F32 = 0, WAVE_BF16 = 1, WAVE_F16 = 2 } wave_sto
 #define WAVE_DAMPING_OFF 1 /* eta := 0: Eq. 2 on every point */
 #define WAVE_ETA_ARRAY 2   /* eta is supplied per point at wave_alloc (else the
                               default profile, kept as three 1-D tables) */
+#define WAVE_TWO_STEP 4    /* reserve two more u arrays (and a second phi) so
+                              that wave_step can take two time steps per
+                              launch (WAVE_KERNEL_STREAM2); not with an eta
+                              array */
 
 typedef struct wave_desc {
     int32_t nx, ny, nz;  /* total extents incl. the layer, 1..32768, and
@@ -66,7 +70,7 @@ typedef struct wave_desc {
     double dx, dy, dz;   /* grid spacing (m), > 0                          */
     double dt;           /* time step (s), > 0                             */
     int32_t storage;     /* wave_storage of u                              */
-    int32_t flags;       /* WAVE_DAMPING_OFF | WAVE_ETA_ARRAY, or 0        */
+    int32_t flags;       /* WAVE_DAMPING_OFF | WAVE_ETA_ARRAY | WAVE_TWO_STEP */
     double refl;         /* target reflection of the default eta profile,
                             0 < refl < 1 (1e-3 is typical)                 */
     int32_t max_src;     /* source table capacity, >= 0                    */
@@ -205,6 +209,11 @@ int wave_energy(wave_ctx *ctx, double *out);
 #define WAVE_KERNEL_DIRECT 0 /* one thread per point, all reads from memory */
 #define WAVE_KERNEL_STREAM 1 /* xy tile in LDS, z neighbours in registers,
                                 streamed along z (default)               */
+#define WAVE_KERNEL_STREAM2 2 /* two time steps per launch: the second
+                                trails the first by 4 planes along z, the
+                                first step's results stay on chip (needs
+                                WAVE_TWO_STEP); an odd remaining step runs
+                                the single-step kernel                  */
 
 /* Select the sweep kernel and its tile: rows_per_wave (RY) and
  * waves_per_group (NW) give a 64 x (RY*NW) xy tile; zchunk is the number of
@@ -213,21 +222,25 @@ int wave_energy(wave_ctx *ctx, double *out);
  * {(1,16), (1,8), (2,8), (2,4)}; the default is (1,16).  The streaming
  * kernel addresses a chunk's planes with 32-bit offsets, so zchunk is cut
  * to what keeps zchunk + 8 float planes below 2 GiB; a grid whose single
- * plane is too large for that runs the direct kernel.  Results do not
- * depend on the choice: every variant evaluates each point with the same
- * operations in the same order. */
+ * plane is too large for that runs the direct kernel.  With
+ * WAVE_KERNEL_STREAM2 (needs WAVE_TWO_STEP) rows_per_wave and
+ * waves_per_group are ignored and zchunk is the two-step chunk (0 =
+ * automatic; a window of zchunk + 16 planes).  Results do not depend on the
+ * choice: every variant evaluates each point with the same operations in
+ * the same order. */
 int wave_set_kernel(wave_ctx *ctx, int32_t variant, int32_t rows_per_wave,
                     int32_t waves_per_group, int32_t zchunk);
 
 /* Autotuner: advance the simulation by `trial_steps` real steps under each
- * compiled tile shape and a few z-chunk lengths (every candidate computes
- * identical results, so the trials are ordinary steps of the run), time each
- * with HIP events, and keep the fastest.  Takes candidates x trial_steps
- * steps in total; *chosen receives {rows_per_wave, waves_per_group, zchunk}
- * (may be NULL; {0, 0, 0} when the planes are too large to stream and the
- * direct kernel is kept).  Synchronises.  EINVAL if the steps would
- * overflow the trace buffer. */
-int wave_tune(wave_ctx *ctx, int32_t trial_steps, int32_t chosen[3]);
+ * compiled tile shape and a few z-chunk lengths, and, with WAVE_TWO_STEP,
+ * under the two-step kernel with a few z-chunk lengths (trial_steps rounded
+ * up to even there).  Every candidate computes identical results, so the
+ * trials are ordinary steps of the run.  Each is timed with HIP events; the
+ * fastest per step is kept.  *chosen (may be NULL) receives {variant,
+ * rows_per_wave, waves_per_group, zchunk}; {0, 0, 0, 0} when the planes are
+ * too large to stream and the direct kernel is kept.  Synchronises.  EINVAL
+ * if the steps would overflow the trace buffer. */
+int wave_tune(wave_ctx *ctx, int32_t trial_steps, int32_t chosen[4]);
 
 /* When on, wave_step brackets every sweep-kernel launch with HIP events on
  * the context stream; wave_read_timing returns the summed kernel time (ms)

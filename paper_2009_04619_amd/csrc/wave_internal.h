@@ -64,6 +64,22 @@ struct SweepArgs {
   int32_t damping;      // 0: Eq. 2 everywhere
 };
 
+// Two steps per launch (wave_kernels2.hip): u^{n-1}, u^n, phi^n in;
+// u^{n+1}, u^{n+2}, phi^{n+2} out, all distinct arrays; the sources of step n
+// enter u^{n+1} inside the kernel.
+struct Sweep2Args {
+  SweepArgs s;               // s.cur = u^n, s.phi = phi^n (s.nxt unused)
+  const void* prev;          // u^{n-1}
+  void* out1;                // u^{n+1}
+  void* out2;                // u^{n+2}
+  float* phi_out;            // phi^{n+2}
+  int32_t nsrc;
+  const int32_t* src_ijk;    // [nsrc][3] grid indices (i, j, k)
+  const float* wavelet;      // [nsrc][max_steps]
+  int32_t max_steps;
+  int32_t step;              // n
+};
+
 struct InjectArgs {
   void* u;              // u^{n+1} (storage type), offset to (0,0,0)
   const float* vp;
@@ -123,6 +139,11 @@ int auto_zchunk(int nx, int ny, int nz, int ry, int nw);
 // window of zchunk + 8 planes); below 1 when one plane is too large.
 int stream_zchunk_limit(int64_t plane);
 hipError_t launch_inject_record(const InjectArgs& a, int storage, hipStream_t s);
+// Two-step sweep (wave_kernels2.hip): damping off or the default profile's
+// tables; zchunk <= stream2_zchunk_limit(plane) (window of zchunk + 16 planes).
+hipError_t launch_sweep2(const Sweep2Args& g, int storage, int zchunk, hipStream_t s);
+int stream2_zchunk_limit(int64_t plane);
+int auto_zchunk2(int nx, int ny, int nz);
 hipError_t launch_energy(const EnergyArgs& a, int storage, hipStream_t s);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 // Scatter a compact [nz][ny][nx] float field into a padded array whose

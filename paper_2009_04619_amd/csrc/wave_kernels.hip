@@ -1,120 +1,16 @@
 // wave_kernels.hip -- gfx950 kernels of one time step of the 3-D acoustic
-// wave equation (paper Sec. III-A, Eq. 2-3; damping layer after Sec. III-B).
-//
-// Per-point arithmetic (identical in every sweep variant, so results do not
-// depend on tiling): float32, explicit fused multiply-adds only where written
-// (the library is built with -ffp-contract=off), correctly rounded division:
-//   lap = c_xyz * u
-//   lap = fma(c_am, u(+m) + u(-m), lap)   axis x, y, z; m = 1..4
-//   lap = fma(c_e, u, lap)
-// (Eq. 3 in its printed order.  In exact arithmetic c_xyz = -2 sum c_am, so
-// a constant field has zero Laplacian; the float weights miss that identity
-// by a residual, which would act as a spurious term proportional to u -- a
-// frequency shift whose phase error grows with time.  c_e = fl32(-(c_xyz +
-// 2 sum c_am)) over the float weights removes it.)
-//   inner: u' = u + fma(vp, lap, u - u_prev)
-//   layer: t  = fma(-(eta * eta), u, u - u_prev)
-//          u' = u + fma(vp, lap + phi, t) / fma(2, eta, 1)
-// (Eq. 2 and the layer update rearranged around the increment u - u_prev,
-// which a smooth field gives exactly; every small term is then rounded
-// relative to its own size and only the final add rounds at the size of u)
-//          g  = (de_x * q_x) * (u(+x) - u(-x))
-//          g  = fma(de_y * q_y, u(+y) - u(-y), g)
-//          g  = fma(de_z * q_z, u(+z) - u(-z), g)
-//          phi' = (phi - g) / (1 + eta)
-// de_a is eta(+a) - eta(-a) of a per-point eta array (zero beyond the
-// faces), or, for the default profile held as per-axis tables,
-// fl32(dt (t_a(i+1) - t_a(i-1))): the central difference of a sum of
-// one-axis functions along a involves only that axis' term (the tables
-// continue the profile one cell past each face).
-// The layer form with eta = phi = 0 gives the inner form bit for bit, which
-// is the reduction of the damped update to Eq. 2.
+// wave equation (paper Sec. III-A, Eq. 2-3; damping layer after Sec. III-B):
+// the per-point sweeps (direct and 2.5-D streaming, single shot and batched),
+// source add and receiver sample, the float64 energy, set-up and copy.  The
+// per-point arithmetic they share is in wave_point.h.
 #include <algorithm>
 #include <type_traits>
 
 #include "wave_internal.h"
+#include "wave_point.h"
 
 namespace wave {
 namespace {
-
-// ---- wavefield storage types ------------------------------------------------
-struct StF32 {
-  using T = float;
-  static __device__ __forceinline__ float ld(const T* p, int64_t i) { return p[i]; }
-  static __device__ __forceinline__ void st(T* p, int64_t i, float v) { p[i] = v; }
-  static __device__ __forceinline__ float cvt(T v) { return v; }
-  static __device__ __forceinline__ T enc(float v) { return v; }
-  static __device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
-  }
-  static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
-                                             float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)vo, (int)so, 0);
-  }
-};
-
-// float -> bfloat16, round to nearest even: gfx950 converts in one
-// instruction (v_cvt_pk_bf16_f32), subnormals included (the library runs
-// with float32 denormals enabled).
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
-  return __builtin_bit_cast(uint16_t, (__bf16)f);
-}
-
-struct StBF16 {
-  using T = uint16_t;
-  static __device__ __forceinline__ float ld(const T* p, int64_t i) {
-    return __uint_as_float((uint32_t)p[i] << 16);
-  }
-  static __device__ __forceinline__ void st(T* p, int64_t i, float v) { p[i] = f32_to_bf16_rne(v); }
-  static __device__ __forceinline__ float cvt(T v) { return __uint_as_float((uint32_t)v << 16); }
-  static __device__ __forceinline__ T enc(float v) { return f32_to_bf16_rne(v); }
-  static __device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-    return cvt((uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0));
-  }
-  static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
-                                             float v) {
-    __builtin_amdgcn_raw_buffer_store_b16(enc(v), r, (int)vo, (int)so, 0);
-  }
-};
-
-struct StF16 {
-  using T = _Float16;
-  static __device__ __forceinline__ float ld(const T* p, int64_t i) { return (float)p[i]; }
-  static __device__ __forceinline__ void st(T* p, int64_t i, float v) { p[i] = (_Float16)v; }
-  static __device__ __forceinline__ float cvt(T v) { return (float)v; }
-  static __device__ __forceinline__ T enc(float v) { return (_Float16)v; }
-  static __device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-    return cvt(__builtin_bit_cast(
-        _Float16, (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0)));
-  }
-  static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
-                                             float v) {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, enc(v)), r, (int)vo,
-                                          (int)so, 0);
-  }
-};
-
-// ---- per-point update ---------------------------------------------------------
-__device__ __forceinline__ float upd_inner(float c, float pu, float vp, float lap) {
-  return c + __builtin_fmaf(vp, lap, c - pu);
-}
-
-__device__ __forceinline__ float upd_layer(float c, float pu, float vp, float lap, float e,
-                                           float ph) {
-  const float t = __builtin_fmaf(-(e * e), c, c - pu);
-  const float num = __builtin_fmaf(vp, lap + ph, t);
-  return c + num / __builtin_fmaf(2.0f, e, 1.0f);
-}
-
-// phi' from the products dq_a = fl32(de_a * q_a) of the eta differences and
-// 1 / (4 h_a^2), and the u differences du_a.
-__device__ __forceinline__ float upd_phi(float ph, float e, float dqx, float dux, float dqy,
-                                         float duy, float dqz, float duz) {
-  float g = dqx * dux;
-  g = __builtin_fmaf(dqy, duy, g);
-  g = __builtin_fmaf(dqz, duz, g);
-  return (ph - g) / (1.0f + e);
-}
 
 // Default damping profile in table mode: eta(x, y, z) = fl32(dt * ((tx[x] +
 // ty[y]) + tz[z])) (the profile is a sum of three per-axis terms; the double
@@ -213,27 +109,6 @@ __global__ __launch_bounds__(256) void k_sweep_direct(SweepArgs a) {
 // are thus identical on every path, which keeps the prefetch overlapping the
 // compute.
 
-// Buffer resource over memory starting at p (gfx9 family: stride 0, dword 3 =
-// 0x00020000).  Built from a wave-uniform pointer it lives in scalar
-// registers; accesses then take an unsigned 32-bit byte offset per lane plus
-// a wave-uniform one.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_at(const void* p, uint32_t nbytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes,
-                                           0x00020000);
-}
-__device__ __forceinline__ float bld_f32(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
-}
-__device__ __forceinline__ void bst_f32(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
-                                        float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)vo, (int)so, 0);
-}
-
-// Lane offset that is out of range for every eta/phi resource (their range
-// is one chunk window, below kWindowMax); nearby offsets (-4, -pitch) stay
-// out of range, and adding a window offset cannot wrap 32 bits.
-constexpr uint32_t kOOB = 0x80000000u;
-
 // Prefetch distance in planes (the u ring then has 9 + kPD slots and the
 // per-plane operand rings kPD + 1; both divide the unroll length).
 #ifndef WAVE_STREAM_PD
@@ -241,45 +116,6 @@ constexpr uint32_t kOOB = 0x80000000u;
 #endif
 constexpr int kPD = WAVE_STREAM_PD;
 static_assert(kPD == 1 || kPD == 3 || kPD == 7, "prefetch distance must make kPD + 1 divide 9 + kPD");
-
-struct ChunkInfo {
-  int zb, ze;
-  bool cap;  // every point of the chunk is in a z cap of the layer
-};
-
-__host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
-
-// z chunks: pieces of at most zc planes.  With a layer, the z caps [0, w)
-// and [nz-w, nz) and the interior [w, nz-w) are cut separately (a grid with
-// 2w >= nz is all cap).
-__host__ __device__ inline int chunk_count(int nz, int w, int zc, bool damp) {
-  if (!damp || w == 0 || 2 * w >= nz) return cdiv(nz, zc);
-  return 2 * cdiv(w, zc) + cdiv(nz - 2 * w, zc);
-}
-__device__ inline ChunkInfo chunk_of(int ch, int nz, int w, int zc, bool damp) {
-  ChunkInfo c;
-  if (!damp || w == 0 || 2 * w >= nz) {
-    c.zb = ch * zc;
-    c.ze = min(c.zb + zc, nz);
-    c.cap = damp && w > 0;
-    return c;
-  }
-  const int nc = cdiv(w, zc), ni = cdiv(nz - 2 * w, zc);
-  if (ch < nc) {
-    c.zb = ch * zc;
-    c.ze = min(c.zb + zc, w);
-    c.cap = true;
-  } else if (ch < nc + ni) {
-    c.zb = w + (ch - nc) * zc;
-    c.ze = min(c.zb + zc, nz - w);
-    c.cap = false;
-  } else {
-    c.zb = nz - w + (ch - nc - ni) * zc;
-    c.ze = min(c.zb + zc, nz);
-    c.cap = true;
-  }
-  return c;
-}
 
 // Per-thread slot of a tile: which point it owns and where that point lives.
 template <int RY>
@@ -874,10 +710,6 @@ bool stream_config_supported(int ry, int nw) {
   return (ry == 1 && nw == 16) || (ry == 1 && nw == 8) || (ry == 2 && nw == 8) ||
          (ry == 2 && nw == 4);
 }
-
-// Bytes a chunk window of a float array may span (keeps every in-range offset
-// plus kOOB below 2^32 and kOOB out of range).
-constexpr int64_t kWindowMax = 0x7FF00000;
 
 int stream_zchunk_limit(int64_t plane) {
   const int64_t z = kWindowMax / (plane * 4) - 2 * kR;

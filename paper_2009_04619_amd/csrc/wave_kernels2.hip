@@ -1,0 +1,453 @@
+// wave_kernels2.hip -- two time steps per launch on gfx950 (temporal
+// blocking of Alg. 1's loop: the 2.5-D stream of wave_kernels.hip with a
+// second step that trails the first by 4 planes along z, "3.5-D" blocking).
+//
+// Each workgroup owns a 56 x 16 output tile and a 64 x 24 first-step region
+// around it (the output tile plus the 4-cell halo the second step's stencil
+// needs).  Per iteration it
+//  * stages plane za of u^n (with a further 4-cell halo) in LDS and computes
+//    u^{n+1} (and phi^{n+1}) at plane za over the whole first-step region,
+//    adds the sources of step n, rounds to the storage type, and keeps the
+//    result in an LDS ring of 5 planes (phi^{n+1} of the output rows too);
+//    the output points of u^{n+1} also go to memory;
+//  * computes u^{n+2} (and phi^{n+2}) at plane za - 4 of the output tile from
+//    the ring (x and y neighbours) and a per-column register queue of
+//    u^{n+1} (z neighbours), with u^n of that plane as "u_prev".
+// So u^n, u^{n-1}, vp and phi^n cross HBM once for two steps.  The per-point
+// arithmetic is that of wave_point.h, operand for operand, so every value
+// equals the one two single steps produce (the first-step region's halo is
+// recomputed by neighbouring tiles with identical results).
+//
+// Buffers: u^{n-1}, u^n and phi^n are read; u^{n+1}, u^{n+2} and phi^{n+2}
+// go to three other arrays (a neighbouring tile still reads u^{n-1}, u^n and
+// phi^n at points this tile has finished, so nothing is written in place).
+// Supported: damping off, or the default profile held as tables.
+#include <algorithm>
+
+#include "wave_internal.h"
+#include "wave_point.h"
+
+namespace wave {
+namespace {
+
+constexpr int kW2 = 8;                    // wavefronts per workgroup
+constexpr int kTY2 = 16;                  // output rows per tile
+constexpr int kOX2 = kTX - 2 * kR;        // output columns per tile (lanes 4..59)
+constexpr int kAR = kTY2 + 2 * kR;        // first-step rows (24)
+constexpr int kRA = kAR / kW2;            // first-step rows per wavefront (3)
+constexpr int kRB = kTY2 / kW2;           // second-step rows per wavefront (2)
+constexpr int kSR = kAR + 2 * kR;         // staged rows (32)
+constexpr int kSW = kTX + 2 * kR;         // staged columns (72)
+constexpr int kSPL = kSR * kSW;           // staged plane (floats)
+constexpr int kNT2 = 64 * kW2;            // threads
+constexpr int kNH2 = kSPL - kAR * kTX;    // staged halo elements (768)
+constexpr int kHPT2 = (kNH2 + kNT2 - 1) / kNT2;
+constexpr int kRPL = kAR * kTX;           // u^{n+1} ring plane (floats)
+constexpr int kPPL = kTY2 * kTX;          // phi^{n+1} ring plane (floats)
+constexpr int kRing = 5;                  // planes za-4 .. za
+constexpr int kL2 = 10;                   // u^n ring slots = unroll length
+static_assert(kRA * kW2 == kAR && kRB * kW2 == kTY2, "rows must split evenly");
+static_assert(kL2 % kRing == 0 && kL2 % 2 == 0, "ring lengths must divide the unroll");
+
+struct Smem2 {
+  float sa[2][kSPL];                 // staged u^n plane (double-buffered)
+  float rb[kRing][kRPL];             // u^{n+1}, first-step region
+  float pb[kRing][kPPL];             // phi^{n+1}, output rows
+  float dump[kHPT2 * kNT2 - kNH2 + 64];
+};
+
+// z chunks of the two-step sweep: as the single-step ones, with caps 4
+// planes deeper so that the first step of an interior chunk (planes zb-4 ..
+// ze+3) stays out of the z caps.
+__device__ inline ChunkInfo chunk2_of(int ch, int nz, int w, int zc, bool damp) {
+  return chunk_of(ch, nz, (damp && w > 0) ? w + kR : 0, zc, damp && w > 0);
+}
+
+template <class S, int EM>
+__device__ __forceinline__ void s2_loop(const Sweep2Args& g, Smem2& sm, int x0, int y0, int zb,
+                                        int ze) {
+  using T = typename S::T;
+  const SweepArgs& a = g.s;
+  constexpr uint32_t ES = sizeof(T);
+  constexpr bool LAYER = EM != 0;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int P = a.pitch;
+  const int64_t Q = a.plane;
+  const uint32_t pe = (uint32_t)Q * ES, p4 = (uint32_t)Q * 4u;
+  const int nx = a.nx, ny = a.ny, nz = a.nz, w = a.w;
+
+  // window: planes wz0 .. wz1 of every array, from row -4
+  const int wz0 = max(zb - 2 * kR, -kR), wz1 = min(ze + 2 * kR - 1, nz + kR - 1);
+  const int64_t w0 = (int64_t)wz0 * Q - (int64_t)kR * P;
+  const uint32_t wl_e = (uint32_t)(wz1 - wz0 + 1) * pe, wl_4 = (uint32_t)(wz1 - wz0 + 1) * p4;
+  const auto ru = rsrc_at(static_cast<const T*>(a.cur) + w0, 0xffffffffu);
+  const auto rp = rsrc_at(static_cast<const T*>(g.prev) + w0, 0xffffffffu);
+  const auto rv = rsrc_at(a.vp + w0, 0xffffffffu);
+  const auto ro1 = rsrc_at(static_cast<T*>(g.out1) + w0, wl_e);
+  const auto ro2 = rsrc_at(static_cast<T*>(g.out2) + w0, wl_e);
+  const auto rph = rsrc_at(LAYER ? (const void*)(a.phi + w0) : nullptr, LAYER ? wl_4 : 0u);
+  const auto rpo = rsrc_at(LAYER ? (const void*)(g.phi_out + w0) : nullptr, LAYER ? wl_4 : 0u);
+  auto wk = [&](int z) { return (uint32_t)(min(max(z, wz0), wz1) - wz0); };  // window index
+
+  // in-plane element offset of (x, y), clamped to cells that exist (values of
+  // clamped cells are never used by a point inside the grid)
+  auto poff = [&](int x, int y) {
+    const int yy = min(max(y, -kR), ny + kR - 1);
+    const int xx = min(max(x, -kR), P + kR - 1);
+    return (uint32_t)max((yy + kR) * P + xx, 0);
+  };
+
+  const int x = x0 + lane;
+  const bool vx = x >= 0 && x < nx;
+  const bool ownx = lane >= kR && lane < kR + kOX2 && vx;
+  const bool layx = x < w || x >= nx - w;
+
+  // first-step rows ya = y0 - 4 + 3 wv + r; second-step rows yb = y0 + 2 wv + r
+  uint32_t voa[kRA], voa4[kRA], eoa[kRA], sta[kRA];
+  bool va[kRA], lxa[kRA], owna[kRA];
+  int yra[kRA];
+#pragma unroll
+  for (int r = 0; r < kRA; ++r) {
+    const int y = y0 - kR + kRA * wv + r;
+    yra[r] = y;
+    va[r] = vx && y >= 0 && y < ny;
+    lxa[r] = va[r] && (layx || y < w || y >= ny - w);
+    owna[r] = ownx && y >= y0 && y < y0 + kTY2 && y < ny;
+    const uint32_t o = poff(x, y);
+    voa[r] = o * ES;
+    voa4[r] = o * 4u;
+    sta[r] = (uint32_t)((kR + kRA * wv + r) * kSW + kR + lane);
+  }
+  uint32_t vob[kRB], vob4[kRB];
+  bool vb[kRB], lxb[kRB];
+  int yrb[kRB];
+#pragma unroll
+  for (int r = 0; r < kRB; ++r) {
+    const int y = y0 + kRB * wv + r;
+    yrb[r] = y;
+    vb[r] = ownx && y < ny;
+    lxb[r] = vb[r] && (layx || y < w || y >= ny - w);
+    const uint32_t o = poff(x, y);
+    vob[r] = o * ES;
+    vob4[r] = o * 4u;
+  }
+  // staged halo: element h of the staged plane's frame (rows 0-3, 28-31 of 72
+  // columns, then columns 0-3, 68-71 of rows 4-27); threads beyond it write
+  // to a dump area
+  int hl[kHPT2];
+  uint32_t ho[kHPT2];
+#pragma unroll
+  for (int k = 0; k < kHPT2; ++k) {
+    const int h = threadIdx.x + k * kNT2;
+    int sr, sc;
+    if (h < 2 * kR * kSW) {
+      const int rr = h / kSW;
+      sr = rr < kR ? rr : kAR + rr;
+      sc = h % kSW;
+    } else if (h < kNH2) {
+      const int kk = h - 2 * kR * kSW;
+      sr = kR + kk / (2 * kR);
+      const int cc = kk % (2 * kR);
+      sc = cc < kR ? cc : kTX + cc;
+    } else {
+      sr = -1;
+      sc = h - kNH2;
+    }
+    hl[k] = sr >= 0 ? sr * kSW + sc : -1 - sc;
+    ho[k] = poff(x0 - kR + sc, y0 - 2 * kR + max(sr, 0)) * ES;
+  }
+
+  // default profile tables (EM = 2)
+  double tsa[kRA], tsb[kRB];
+  float dqxa = 0.0f, dqya[kRA], dqyb[kRB];
+  const double* tzt = nullptr;
+  const float* dqzt = nullptr;
+  if (EM == 2) {
+    const double* tx = a.etab + 1;
+    const double* ty = tx + nx + 2;
+    tzt = ty + ny + 2;
+    dqzt = a.etq + nx + ny;
+    const int xc = min(max(x, 0), nx - 1);
+    dqxa = a.etq[xc];
+#pragma unroll
+    for (int r = 0; r < kRA; ++r) {
+      const int yc = min(max(yra[r], 0), ny - 1);
+      tsa[r] = tx[xc] + ty[yc];
+      dqya[r] = a.etq[nx + yc];
+    }
+#pragma unroll
+    for (int r = 0; r < kRB; ++r) {
+      const int yc = min(max(yrb[r], 0), ny - 1);
+      tsb[r] = tx[xc] + ty[yc];
+      dqyb[r] = a.etq[nx + yc];
+    }
+  }
+
+  float q[kL2][kRA];                    // u^n(za-4 .. za+5), first-step rows
+  float qb[kL2][kRB];                   // u^{n+1}, second-step rows
+  float pva[2][kRA], vva[2][kRA], pha[2][kRA];
+  float pub[2][kRB], vvb[2][kRB];
+  float hh[2][kHPT2];
+  double tza[2], tzb[2];
+  float dza[2], dzb[2];
+
+  auto load_a = [&](int B, int z) {     // first-step operands of plane z
+    const uint32_t k = wk(z);
+#pragma unroll
+    for (int r = 0; r < kRA; ++r) {
+      pva[B][r] = S::bld(rp, voa[r], k * pe);
+      vva[B][r] = bld_f32(rv, voa4[r], k * p4);
+      if (LAYER) pha[B][r] = bld_f32(rph, eoa[r], k * p4);
+    }
+#pragma unroll
+    for (int kk = 0; kk < kHPT2; ++kk) hh[B][kk] = S::bld(ru, ho[kk], k * pe);
+    if (EM == 2) {
+      const int zc = min(max(z, 0), nz - 1);
+      tza[B] = tzt[zc];
+      dza[B] = dqzt[zc];
+    }
+  };
+  auto load_b = [&](int B, int z) {     // second-step operands of plane z
+    const uint32_t k = wk(z);
+#pragma unroll
+    for (int r = 0; r < kRB; ++r) {
+      pub[B][r] = S::bld(ru, vob[r], k * pe);
+      vvb[B][r] = bld_f32(rv, vob4[r], k * p4);
+    }
+    if (EM == 2) {
+      const int zc = min(max(z, 0), nz - 1);
+      tzb[B] = tzt[zc];
+      dzb[B] = dqzt[zc];
+    }
+  };
+
+  // phi^n offsets: layer points of the first-step region, out of range for
+  // the others (z caps decided per plane in the loop)
+  auto set_eoa = [&](int z) {
+    const bool capz = z < w || z >= nz - w;
+#pragma unroll
+    for (int r = 0; r < kRA; ++r) eoa[r] = (va[r] && (lxa[r] || capz)) ? voa4[r] : kOOB;
+  };
+  const int za0 = zb - kR;
+  if (LAYER) set_eoa(za0);
+#pragma unroll
+  for (int j = 0; j < 2 * kR + 1; ++j) {
+    const uint32_t k = wk(za0 - kR + j);
+#pragma unroll
+    for (int r = 0; r < kRA; ++r) q[j][r] = S::bld(ru, voa[r], k * pe);
+  }
+  load_a(0, za0);
+  load_b(0, za0 - kR);
+
+  auto body = [&](auto SC, const int za) {
+    constexpr int Sl = decltype(SC)::value;
+    constexpr int B = Sl & 1, NB = B ^ 1;
+    constexpr int RS = Sl % kRing;            // ring slot of plane za
+    constexpr int RQ = (Sl + 1) % kRing;      // ring slot of plane za - 4
+    const int zq = za - kR;
+    // requests for the next iteration: u^n(za+5), first-step operands of
+    // za+1, second-step operands of za-3 (all clamped to the window)
+    {
+      const uint32_t k5 = wk(za + kR + 1);
+#pragma unroll
+      for (int r = 0; r < kRA; ++r) q[(Sl + 2 * kR + 1) % kL2][r] = S::bld(ru, voa[r], k5 * pe);
+      if (LAYER) set_eoa(za + 1);
+      load_a(NB, za + 1);
+      load_b(NB, zq + 1);
+    }
+    // stage u^n(za) with its halo
+    float* s = sm.sa[B];
+#pragma unroll
+    for (int r = 0; r < kRA; ++r) s[sta[r]] = q[(Sl + kR) % kL2][r];
+#pragma unroll
+    for (int kk = 0; kk < kHPT2; ++kk) {
+      if (hl[kk] >= 0) s[hl[kk]] = hh[B][kk];
+      else sm.dump[-1 - hl[kk]] = hh[B][kk];
+    }
+    __syncthreads();
+
+    // ---- first step: u^{n+1}, phi^{n+1} at plane za ----
+    const bool inz = za >= 0 && za < nz;
+    const bool ownz = za >= zb && za < ze;
+    const bool capza = za < w || za >= nz - w;
+    const float* srcw = g.wavelet;
+#pragma unroll
+    for (int r = 0; r < kRA; ++r) {
+      const float* row = s + sta[r];
+      const float c = q[(Sl + kR) % kL2][r];
+      float lap = a.c[0] * c;
+#pragma unroll
+      for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(a.c[m], row[m] + row[-m], lap);
+#pragma unroll
+      for (int m = 1; m <= kR; ++m)
+        lap = __builtin_fmaf(a.c[4 + m], row[m * kSW] + row[-m * kSW], lap);
+#pragma unroll
+      for (int m = 1; m <= kR; ++m)
+        lap = __builtin_fmaf(a.c[8 + m], q[(Sl + kR + m) % kL2][r] + q[(Sl + kR - m) % kL2][r], lap);
+      lap = __builtin_fmaf(a.ce, c, lap);
+      float res, nph = 0.0f;
+      bool lay = false;
+      if (LAYER) {
+        lay = va[r] && (lxa[r] || capza);
+        const float e = lay ? (float)(a.dt * (tsa[r] + tza[B])) : 0.0f;
+        res = upd_layer(c, pva[B][r], vva[B][r], lap, e, pha[B][r]);
+        nph = upd_phi(pha[B][r], e, dqxa, row[1] - row[-1], dqya[r], row[kSW] - row[-kSW], dza[B],
+                      q[(Sl + kR + 1) % kL2][r] - q[(Sl + kR - 1) % kL2][r]);
+      } else {
+        res = upd_inner(c, pva[B][r], vva[B][r], lap);
+      }
+      // the stored value (storage rounding), then the sources of step n in
+      // list order, each stored in turn (Alg. 1: the source add follows the
+      // sweep)
+      res = S::cvt(S::enc(res));
+      for (int q2 = 0; q2 < g.nsrc; ++q2) {
+        if (g.src_ijk[3 * q2 + 2] == za) {
+          const float wq = g.step < g.max_steps ? srcw[(int64_t)q2 * g.max_steps + g.step] : 0.0f;
+          if (x == g.src_ijk[3 * q2] && yra[r] == g.src_ijk[3 * q2 + 1])
+            res = S::cvt(S::enc(__builtin_fmaf(vva[B][r], wq, res)));
+        }
+      }
+      const bool live = inz && va[r];
+      res = live ? res : 0.0f;
+      sm.rb[RS][(kRA * wv + r) * kTX + lane] = res;
+      S::bst(ro1, (ownz && owna[r]) ? voa[r] : kOOB, wk(za) * pe, res);
+      // phi^{n+1} of the output rows for the second step, which another
+      // wavefront may compute: written by every wavefront (zero where no
+      // layer point is), whichever loop it runs
+      {
+        const int orow = yra[r] - y0;
+        if (orow >= 0 && orow < kTY2) sm.pb[RS][orow * kTX + lane] = (LAYER && live && lay) ? nph : 0.0f;
+      }
+    }
+    __syncthreads();
+
+    // ---- second step: u^{n+2}, phi^{n+2} at plane zq = za - 4 ----
+#pragma unroll
+    for (int r = 0; r < kRB; ++r) qb[Sl][r] = sm.rb[RS][(kRB * wv + r + kR) * kTX + lane];
+    if (zq >= zb && zq < ze) {
+      const bool capzq = zq < w || zq >= nz - w;
+      const float* rbq = sm.rb[RQ];
+#pragma unroll
+      for (int r = 0; r < kRB; ++r) {
+        const float* row = rbq + (kRB * wv + r + kR) * kTX + lane;
+        const float c = qb[(Sl + kL2 - kR) % kL2][r];
+        float lap = a.c[0] * c;
+#pragma unroll
+        for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(a.c[m], row[m] + row[-m], lap);
+#pragma unroll
+        for (int m = 1; m <= kR; ++m)
+          lap = __builtin_fmaf(a.c[4 + m], row[m * kTX] + row[-m * kTX], lap);
+#pragma unroll
+        for (int m = 1; m <= kR; ++m)
+          lap = __builtin_fmaf(a.c[8 + m],
+                               qb[(Sl + kL2 - kR + m) % kL2][r] + qb[(Sl + kL2 - kR - m) % kL2][r], lap);
+        lap = __builtin_fmaf(a.ce, c, lap);
+        const uint32_t kq = wk(zq);
+        float res;
+        if (LAYER) {
+          const bool lay = vb[r] && (lxb[r] || capzq);
+          const float e = lay ? (float)(a.dt * (tsb[r] + tzb[B])) : 0.0f;
+          const float ph = sm.pb[RQ][(kRB * wv + r) * kTX + lane];
+          res = upd_layer(c, pub[B][r], vvb[B][r], lap, e, ph);
+          const float nph =
+              upd_phi(ph, e, dqxa, row[1] - row[-1], dqyb[r], row[kTX] - row[-kTX], dzb[B],
+                      qb[(Sl + kL2 - kR + 1) % kL2][r] - qb[(Sl + kL2 - kR - 1) % kL2][r]);
+          bst_f32(rpo, lay ? vob4[r] : kOOB, kq * p4, nph);
+        } else {
+          res = upd_inner(c, pub[B][r], vvb[B][r], lap);
+        }
+        S::bst(ro2, vb[r] ? vob[r] : kOOB, kq * pe, res);
+      }
+    }
+  };
+
+  using std::integral_constant;
+  for (int za = za0; za < ze + kR; za += kL2) {
+#define WAVE_BODY2(J)                                   \
+    if ((J) > 0 && za + (J) >= ze + kR) break;          \
+    body(integral_constant<int, (J)>{}, za + (J));
+    WAVE_BODY2(0) WAVE_BODY2(1) WAVE_BODY2(2) WAVE_BODY2(3) WAVE_BODY2(4)
+    WAVE_BODY2(5) WAVE_BODY2(6) WAVE_BODY2(7) WAVE_BODY2(8) WAVE_BODY2(9)
+#undef WAVE_BODY2
+  }
+}
+
+template <class S>
+__global__ __launch_bounds__(kNT2, 2) void k_sweep2(Sweep2Args g, int tiles_x, int tiles_y,
+                                                    int zchunk) {
+  __shared__ Smem2 sm;
+  const SweepArgs& a = g.s;
+  const int nb = gridDim.x, bid = blockIdx.x;
+  const int per = nb >> 3, rem = nb & 7, xcd = bid & 7, slot = bid >> 3;
+  const int logical = (xcd < rem) ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+  const int tx = logical % tiles_x;
+  const int t2 = logical / tiles_x;
+  const int ty = t2 % tiles_y;
+  const int ch = t2 / tiles_y;
+  const int x0 = tx * kOX2 - kR, y0 = ty * kTY2;
+  const bool damp = a.damping != 0;
+  const ChunkInfo c = chunk2_of(ch, a.nz, a.w, zchunk, damp);
+  if (c.zb >= c.ze) return;
+  // wavefront-uniform choice of the loop: any layer point among the
+  // wavefront's first- or second-step points, in any plane of the chunk
+  bool lay = false;
+  if (damp) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int x = x0 + lane;
+    const bool lx = x < a.w || x >= a.nx - a.w;
+    for (int r = 0; r < kRA + kRB; ++r) {
+      const int y = r < kRA ? y0 - kR + kRA * wv + r : y0 + kRB * wv + (r - kRA);
+      lay = lay || (x >= 0 && x < a.nx && y >= 0 && y < a.ny && (lx || y < a.w || y >= a.ny - a.w));
+    }
+    lay = lay || c.cap;
+  }
+  if (!__any(lay))
+    s2_loop<S, 0>(g, sm, x0, y0, c.zb, c.ze);
+  else
+    s2_loop<S, 2>(g, sm, x0, y0, c.zb, c.ze);
+}
+
+template <class S>
+hipError_t sweep2_t(const Sweep2Args& g, int zchunk, hipStream_t st) {
+  const SweepArgs& a = g.s;
+  const int tiles_x = (a.nx + kOX2 - 1) / kOX2;
+  const int tiles_y = (a.ny + kTY2 - 1) / kTY2;
+  const bool damp = a.damping != 0 && a.w > 0;
+  const int chunks = chunk_count(a.nz, damp ? a.w + kR : 0, zchunk, damp);
+  const int64_t blocks = (int64_t)tiles_x * tiles_y * chunks;
+  if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sweep2<S>, dim3((unsigned)blocks), dim3(kNT2), 0, st, g, tiles_x, tiles_y,
+                     zchunk);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int stream2_zchunk_limit(int64_t plane) {
+  const int64_t z = kWindowMax / (plane * 4) - 4 * kR;
+  return (int)std::min<int64_t>(z, 1 << 30);
+}
+
+int auto_zchunk2(int nx, int ny, int nz) {
+  // long chunks: each one recomputes 8 planes of the first step and reads 16
+  // extra planes of u^n; about nz/8 planes, at least 64
+  const int64_t tiles = (int64_t)((nx + kOX2 - 1) / kOX2) * ((ny + kTY2 - 1) / kTY2);
+  const int64_t chunks = (4096 + tiles - 1) / tiles;
+  int zc = (int)std::min<int64_t>(nz / 8, (nz + chunks - 1) / chunks);
+  zc = std::max(zc, 64);
+  return std::min(zc, nz);
+}
+
+hipError_t launch_sweep2(const Sweep2Args& g, int storage, int zchunk, hipStream_t s) {
+  if (zchunk <= 0 || zchunk > stream2_zchunk_limit(g.s.plane)) return hipErrorInvalidValue;
+  if (g.s.damping && !g.s.etab) return hipErrorInvalidValue;   // eta arrays: single steps only
+  switch (storage) {
+    case 0: return sweep2_t<StF32>(g, zchunk, s);
+    case 1: return sweep2_t<StBF16>(g, zchunk, s);
+    case 2: return sweep2_t<StF16>(g, zchunk, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace wave

@@ -53,7 +53,9 @@ bool desc_ok(const wave_desc* d, std::string* why) {
   if (!(d->dt > 0) || !isfinite(d->dt)) return bad("dt must be finite and > 0");
   if (d->storage != WAVE_F32 && d->storage != WAVE_BF16 && d->storage != WAVE_F16)
     return bad("unknown storage type");
-  if (d->flags & ~(WAVE_DAMPING_OFF | WAVE_ETA_ARRAY)) return bad("unknown flags");
+  if (d->flags & ~(WAVE_DAMPING_OFF | WAVE_ETA_ARRAY | WAVE_TWO_STEP)) return bad("unknown flags");
+  if ((d->flags & WAVE_TWO_STEP) && (d->flags & WAVE_ETA_ARRAY) && !(d->flags & WAVE_DAMPING_OFF))
+    return bad("WAVE_TWO_STEP supports the default damping profile only, not an eta array");
   if (!(d->flags & WAVE_DAMPING_OFF) && d->w > 0 && !(d->refl > 0 && d->refl < 1))
     return bad("refl must be in (0, 1)");
   if (d->max_src < 0 || d->max_rec < 0 || d->max_steps < 0) return bad("negative capacity");
@@ -63,11 +65,12 @@ bool desc_ok(const wave_desc* d, std::string* why) {
 
 bool damping_on(const wave_desc* d) { return !(d->flags & WAVE_DAMPING_OFF) && d->w > 0; }
 bool eta_array(const wave_desc* d) { return damping_on(d) && (d->flags & WAVE_ETA_ARRAY); }
+bool two_step(const wave_desc* d) { return (d->flags & WAVE_TWO_STEP) != 0; }
 
 size_t eta_tables_bytes(const wave_desc* d);
 
 struct ArenaPlan {
-  size_t u[2], vp, eta, etab, phi, src_off, wavelet, rec_off, traces, partial, eres, total;
+  size_t u[4], vp, eta, etab, phi[2], src_off, src_ijk, wavelet, rec_off, traces, partial, eres, total;
 };
 
 ArenaPlan plan_arena(const wave_desc* d) {
@@ -83,12 +86,18 @@ ArenaPlan plan_arena(const wave_desc* d) {
   const size_t es = storage_bytes(d->storage);
   a.u[0] = take((size_t)L.elems * es);
   a.u[1] = take((size_t)L.elems * es);
+  // two steps per launch write u^{n+1}, u^{n+2} and phi^{n+2} to arrays of
+  // their own
+  a.u[2] = two_step(d) ? take((size_t)L.elems * es) : (size_t)-1;
+  a.u[3] = two_step(d) ? take((size_t)L.elems * es) : (size_t)-1;
   a.vp = take((size_t)L.elems * 4);
   const bool damp = damping_on(d);
   a.eta = eta_array(d) ? take((size_t)L.elems * 4) : (size_t)-1;
   a.etab = (damp && !eta_array(d)) ? take(eta_tables_bytes(d)) : (size_t)-1;
-  a.phi = damp ? take((size_t)L.elems * 4) : (size_t)-1;
+  a.phi[0] = damp ? take((size_t)L.elems * 4) : (size_t)-1;
+  a.phi[1] = (damp && two_step(d)) ? take((size_t)L.elems * 4) : (size_t)-1;
   a.src_off = take((size_t)std::max(d->max_src, 1) * 8);
+  a.src_ijk = take((size_t)std::max(d->max_src, 1) * 12);
   a.wavelet = take((size_t)std::max(d->max_src, 1) * std::max(d->max_steps, 1) * 4);
   a.rec_off = take((size_t)std::max(d->max_rec, 1) * 8);
   a.traces = take((size_t)std::max(d->max_rec, 1) * std::max(d->max_steps, 1) * 8);
@@ -202,7 +211,9 @@ struct wave_ctx {
   hipStream_t stream;
   char* arena;
   int es;                 // bytes per u element
-  int cur;                // index of u^n among the two u buffers
+  int icur, iprev;         // which of plan.u hold u^n and u^{n-1}
+  int iphi;               // which of plan.phi holds phi^n
+  int zchunk2;            // z chunk of the two-step sweep (0 = automatic)
   int64_t step;           // time level n
   bool broken;
   bool damp;
@@ -327,7 +338,7 @@ wave::SweepArgs sweep_args(const wave_ctx* c) {
   sa.etab = c->plan.etab == (size_t)-1 ? nullptr : reinterpret_cast<const double*>(c->at(c->plan.etab));
   sa.etq = sa.etab ? reinterpret_cast<const float*>(sa.etab + (L.nx + L.ny + L.nz + 6)) : nullptr;
   sa.dt = c->d.dt;
-  sa.phi = c->f_origin(c->plan.phi);
+  sa.phi = c->f_origin(c->plan.phi[c->iphi]);
   sa.nx = L.nx;
   sa.ny = L.ny;
   sa.nz = L.nz;
@@ -473,8 +484,8 @@ void batch_layout(wave_batch* b) {
     wave::BatchShot& e = b->h_shots[i];
     memset(&e, 0, sizeof(e));
     e.sa = sweep_args(c);
-    e.u[0] = c->u_origin(0);
-    e.u[1] = c->u_origin(1);
+    e.u[0] = c->u_origin(std::min(c->icur, c->iprev));
+    e.u[1] = c->u_origin(std::max(c->icur, c->iprev));
     e.tiles_x = (c->L.nx + wave::kTX - 1) / wave::kTX;
     e.tiles_y = (c->L.ny + ty - 1) / ty;
     e.zchunk = stream_zchunk(c, b->ry, b->nw, c->zchunk);
@@ -606,7 +617,10 @@ int wave_alloc(const wave_desc* d, const float* vel, const float* eta, void* dev
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->arena = static_cast<char*>(dev_arena);
   c->es = storage_bytes(d->storage);
-  c->cur = 0;
+  c->icur = 0;
+  c->iprev = 1;
+  c->iphi = 0;
+  c->zchunk2 = 0;
   c->step = 0;
   c->broken = false;
   c->damp = damp;
@@ -700,8 +714,11 @@ int wave_inject(wave_ctx* c, int32_t i, int32_t j, int32_t k, const float* sampl
   const int64_t off = offset_of(c, i, j, k);
   float* wl = reinterpret_cast<float*>(c->at(c->plan.wavelet)) + (size_t)c->nsrc * std::max(c->d.max_steps, 1);
   int64_t* so = reinterpret_cast<int64_t*>(c->at(c->plan.src_off)) + c->nsrc;
+  int32_t* sijk = reinterpret_cast<int32_t*>(c->at(c->plan.src_ijk)) + 3 * c->nsrc;
+  const int32_t ijk3[3] = {i, j, k};
   HIPCHK(c, hipMemcpyAsync(wl, row.data(), row.size() * 4, hipMemcpyHostToDevice, c->stream), "hipMemcpyAsync");
   HIPCHK(c, hipMemcpyAsync(so, &off, 8, hipMemcpyHostToDevice, c->stream), "hipMemcpyAsync");
+  HIPCHK(c, hipMemcpyAsync(sijk, ijk3, 12, hipMemcpyHostToDevice, c->stream), "hipMemcpyAsync");
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   c->nsrc += 1;
   return WAVE_OK;
@@ -728,6 +745,88 @@ int wave_record(wave_ctx* c, const int32_t* ijk, int32_t nrec) {
   return WAVE_OK;
 }
 
+namespace {
+// Events around one sweep launch when timing is on (reused across calls).
+int timing_begin(wave_ctx* c, hipEvent_t* e1) {
+  *e1 = nullptr;
+  if (!c->timing) return WAVE_OK;
+  if (c->events_used == c->events.size()) {
+    hipEvent_t a, b;
+    HIPCHK(c, hipEventCreate(&a), "hipEventCreate");
+    HIPCHK(c, hipEventCreate(&b), "hipEventCreate");
+    c->events.emplace_back(a, b);
+  }
+  hipEvent_t e0 = c->events[c->events_used].first;
+  *e1 = c->events[c->events_used].second;
+  c->events_used += 1;
+  HIPCHK(c, hipEventRecord(e0, c->stream), "hipEventRecord");
+  return WAVE_OK;
+}
+
+// z chunk of the two-step sweep (0: it cannot run for this context).
+int stream2_zchunk(const wave_ctx* c, int zchunk) {
+  if (!two_step(&c->d) || eta_array(&c->d)) return 0;
+  const int lim = wave::stream2_zchunk_limit(c->L.plane);
+  if (lim < 1) return 0;
+  const int zc = zchunk > 0 ? zchunk : wave::auto_zchunk2(c->L.nx, c->L.ny, c->L.nz);
+  return std::min(zc, lim);
+}
+
+// Steps n+1 and n+2 in one launch, then receivers of step n and sources and
+// receivers of step n+1 (Alg. 1 order; the sources of step n are added
+// inside the sweep).
+int step_pair(wave_ctx* c, int zc) {
+  int other[2], k = 0;
+  for (int i = 0; i < 4 && k < 2; ++i)
+    if (i != c->icur && i != c->iprev) other[k++] = i;
+  wave::Sweep2Args g;
+  g.s = sweep_args(c);
+  g.s.cur = c->u_origin(c->icur);
+  g.s.nxt = nullptr;
+  g.prev = c->u_origin(c->iprev);
+  g.out1 = c->u_origin(other[0]);
+  g.out2 = c->u_origin(other[1]);
+  g.phi_out = c->damp ? c->f_origin(c->plan.phi[1 - c->iphi]) : nullptr;
+  g.nsrc = c->nsrc;
+  g.src_ijk = reinterpret_cast<const int32_t*>(c->at(c->plan.src_ijk));
+  g.wavelet = reinterpret_cast<const float*>(c->at(c->plan.wavelet));
+  g.max_steps = std::max(c->d.max_steps, 1);
+  g.step = (int32_t)c->step;
+  hipEvent_t e1;
+  int rc = timing_begin(c, &e1);
+  if (rc) return rc;
+  hipError_t e = wave::launch_sweep2(g, c->d.storage, zc, c->stream);
+  if (e != hipSuccess) return dev_fail(c, e, "two-step sweep launch");
+  if (e1) HIPCHK(c, hipEventRecord(e1, c->stream), "hipEventRecord");
+  wave::InjectArgs ia = inject_args(c);
+  double* traces = c->nrec > 0 ? reinterpret_cast<double*>(c->at(c->plan.traces)) : nullptr;
+  if (c->nrec > 0) {   // receivers of step n: u^{n+1}, its sources already in
+    ia.u = g.out1;
+    ia.nsrc = 0;
+    ia.step = (int32_t)c->step;
+    ia.traces = traces;
+    ia.trace_row = c->trace_count;
+    e = wave::launch_inject_record(ia, c->d.storage, c->stream);
+    if (e != hipSuccess) return dev_fail(c, e, "record launch");
+  }
+  if (c->nsrc > 0 || c->nrec > 0) {   // sources and receivers of step n+1
+    ia.u = g.out2;
+    ia.nsrc = c->nsrc;
+    ia.step = (int32_t)c->step + 1;
+    ia.traces = traces;
+    ia.trace_row = c->trace_count + (c->nrec > 0 ? 1 : 0);
+    e = wave::launch_inject_record(ia, c->d.storage, c->stream);
+    if (e != hipSuccess) return dev_fail(c, e, "inject/record launch");
+  }
+  c->iprev = other[0];
+  c->icur = other[1];
+  if (c->damp) c->iphi = 1 - c->iphi;
+  c->step += 2;
+  if (c->nrec > 0) c->trace_count += 2;
+  return WAVE_OK;
+}
+}  // namespace
+
 int wave_step(wave_ctx* c, int32_t n) {
   CHECK_CTX(c);
   JOIN_CTX(c);
@@ -736,7 +835,17 @@ int wave_step(wave_ctx* c, int32_t n) {
   if (c->nrec > 0 && (int64_t)c->trace_count + n > c->d.max_steps)
     return fail(WAVE_EINVAL, "trace buffer would overflow max_steps");
   if (c->step + n > 0x7fffffff) return fail(WAVE_EINVAL, "step counter overflow");
-  const Layout& L = c->L;
+  // two steps per launch while at least two remain
+  if (c->variant == WAVE_KERNEL_STREAM2) {
+    const int zc2 = stream2_zchunk(c, c->zchunk2);
+    if (zc2 >= 1) {
+      for (; n >= 2; n -= 2) {
+        const int rc = step_pair(c, zc2);
+        if (rc) return rc;
+      }
+    }
+  }
+  if (n == 0) return WAVE_OK;
   wave::SweepArgs sa = sweep_args(c);
   const int zc = stream_zchunk(c, c->ry, c->nw, c->zchunk);
   const bool direct = c->variant == WAVE_KERNEL_DIRECT || zc < 1;
@@ -744,25 +853,15 @@ int wave_step(wave_ctx* c, int32_t n) {
   wave::InjectArgs ia = inject_args(c);
 
   for (int t = 0; t < n; ++t) {
-    sa.cur = c->u_origin(c->cur);
-    sa.nxt = c->u_origin(1 - c->cur);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing) {
-      if (c->events_used == c->events.size()) {
-        hipEvent_t a, b;
-        HIPCHK(c, hipEventCreate(&a), "hipEventCreate");
-        HIPCHK(c, hipEventCreate(&b), "hipEventCreate");
-        c->events.emplace_back(a, b);
-      }
-      e0 = c->events[c->events_used].first;
-      e1 = c->events[c->events_used].second;
-      c->events_used += 1;
-      HIPCHK(c, hipEventRecord(e0, c->stream), "hipEventRecord");
-    }
+    sa.cur = c->u_origin(c->icur);
+    sa.nxt = c->u_origin(c->iprev);
+    hipEvent_t e1;
+    int rc = timing_begin(c, &e1);
+    if (rc) return rc;
     hipError_t e = direct ? wave::launch_sweep_direct(sa, c->d.storage, c->stream)
                        : wave::launch_sweep_stream(sa, c->d.storage, c->ry, c->nw, zc, c->stream);
     if (e != hipSuccess) return dev_fail(c, e, "sweep launch");
-    if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream), "hipEventRecord");
+    if (e1) HIPCHK(c, hipEventRecord(e1, c->stream), "hipEventRecord");
     if (c->nsrc > 0 || c->nrec > 0) {
       ia.u = sa.nxt;
       ia.step = (int32_t)c->step;
@@ -771,7 +870,7 @@ int wave_step(wave_ctx* c, int32_t n) {
       e = wave::launch_inject_record(ia, c->d.storage, c->stream);
       if (e != hipSuccess) return dev_fail(c, e, "inject/record launch");
     }
-    c->cur = 1 - c->cur;
+    std::swap(c->icur, c->iprev);
     c->step += 1;
     if (c->nrec > 0) c->trace_count += 1;
   }
@@ -794,8 +893,8 @@ int wave_read_field(wave_ctx* c, int32_t which, float* out) {
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   const size_t pn = (size_t)c->L.nx * c->L.ny;
   switch (which) {
-    case WAVE_FIELD_U: return download_u(c, c->cur, out);
-    case WAVE_FIELD_UPREV: return download_u(c, 1 - c->cur, out);
+    case WAVE_FIELD_U: return download_u(c, c->icur, out);
+    case WAVE_FIELD_UPREV: return download_u(c, c->iprev, out);
     case WAVE_FIELD_ETA:
       if (c->plan.etab != (size_t)-1) {   // default profile held as tables
         for (int k = 0; k < c->L.nz; ++k) eta_plane(&c->d, c->vmax, k, out + (size_t)k * pn);
@@ -804,7 +903,7 @@ int wave_read_field(wave_ctx* c, int32_t which, float* out) {
       [[fallthrough]];
     case WAVE_FIELD_PHI:
     case WAVE_FIELD_VP: {
-      const size_t off = which == WAVE_FIELD_PHI ? c->plan.phi : which == WAVE_FIELD_VP ? c->plan.vp : c->plan.eta;
+      const size_t off = which == WAVE_FIELD_PHI ? c->plan.phi[c->iphi] : which == WAVE_FIELD_VP ? c->plan.vp : c->plan.eta;
       if (off == (size_t)-1) {
         memset(out, 0, pn * c->L.nz * sizeof(float));
         return WAVE_OK;
@@ -829,12 +928,12 @@ int wave_write_field(wave_ctx* c, int32_t which, const float* in) {
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   const size_t pn = (size_t)c->L.nx * c->L.ny;
   switch (which) {
-    case WAVE_FIELD_U: return upload_u(c, c->cur, in);
-    case WAVE_FIELD_UPREV: return upload_u(c, 1 - c->cur, in);
+    case WAVE_FIELD_U: return upload_u(c, c->icur, in);
+    case WAVE_FIELD_UPREV: return upload_u(c, c->iprev, in);
     case WAVE_FIELD_PHI: {
-      if (c->plan.phi == (size_t)-1) return fail(WAVE_EINVAL, "no phi field with damping off");
+      if (c->plan.phi[c->iphi] == (size_t)-1) return fail(WAVE_EINVAL, "no phi field with damping off");
       for (int k = 0; k < c->L.nz; ++k) {
-        int rc = upload_plane(c, c->at(c->plan.phi), 4, k, in + (size_t)k * pn);
+        int rc = upload_plane(c, c->at(c->plan.phi[c->iphi]), 4, k, in + (size_t)k * pn);
         if (rc) return rc;
       }
       return WAVE_OK;
@@ -863,8 +962,8 @@ int wave_energy(wave_ctx* c, double* out) {
   JOIN_CTX(c);
   if (!out) return fail(WAVE_EINVAL, "out is NULL");
   wave::EnergyArgs ea;
-  ea.cur = c->u_origin(c->cur);
-  ea.prev = c->u_origin(1 - c->cur);
+  ea.cur = c->u_origin(c->icur);
+  ea.prev = c->u_origin(c->iprev);
   ea.vp = c->f_origin(c->plan.vp);
   ea.nx = c->L.nx;
   ea.ny = c->L.ny;
@@ -889,6 +988,14 @@ int wave_set_kernel(wave_ctx* c, int32_t variant, int32_t ry, int32_t nw, int32_
     c->variant = variant;
     return WAVE_OK;
   }
+  if (variant == WAVE_KERNEL_STREAM2) {
+    if (stream2_zchunk(c, 0) < 1)
+      return fail(WAVE_EINVAL, "two steps per launch need WAVE_TWO_STEP, no eta array, and planes small enough");
+    if (zchunk < 0) return fail(WAVE_EINVAL, "zchunk < 0");
+    c->variant = variant;
+    c->zchunk2 = zchunk;
+    return WAVE_OK;
+  }
   if (variant != WAVE_KERNEL_STREAM) return fail(WAVE_EINVAL, "unknown kernel variant");
   if (!wave::stream_config_supported(ry, nw)) return fail(WAVE_EINVAL, "tile (rows_per_wave, waves) not compiled");
   if (zchunk < 0) return fail(WAVE_EINVAL, "zchunk < 0");
@@ -904,54 +1011,72 @@ namespace {
 constexpr int kShapes[][2] = {{1, 16}, {1, 8}, {2, 8}, {2, 4}};
 }  // namespace
 
-int wave_tune(wave_ctx* c, int32_t trial_steps, int32_t chosen[3]) {
+int wave_tune(wave_ctx* c, int32_t trial_steps, int32_t chosen[4]) {
   CHECK_CTX(c);
   if (c->batch) return fail(WAVE_EINVAL, "context is a batch member (use wave_batch_tune)");
   if (trial_steps < 1) return fail(WAVE_EINVAL, "trial_steps < 1");
   const int nshape = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
   const int nz = c->L.nz;
-  std::vector<std::array<int, 3>> cand;
+  // candidates {variant, rows_per_wave, waves_per_group, zchunk}
+  std::vector<std::array<int, 4>> cand;
+  auto add = [&](const std::array<int, 4>& e) {
+    if (std::find(cand.begin(), cand.end(), e) == cand.end()) cand.push_back(e);
+  };
   for (int k = 0; k < nshape; ++k) {
     const int ry = kShapes[k][0], nw = kShapes[k][1];
     const int za = wave::auto_zchunk(c->L.nx, c->L.ny, nz, ry, nw);
     for (int z : {za, std::max(8, za / 2), std::min(nz, 2 * za)}) {
       const int zc = stream_zchunk(c, ry, nw, z);
-      if (zc < 1) continue;
-      std::array<int, 3> e = {ry, nw, zc};
-      if (std::find(cand.begin(), cand.end(), e) == cand.end()) cand.push_back(e);
+      if (zc >= 1) add({WAVE_KERNEL_STREAM, ry, nw, zc});
+    }
+  }
+  if (stream2_zchunk(c, 0) >= 1) {
+    const int za = wave::auto_zchunk2(c->L.nx, c->L.ny, nz);
+    for (int z : {za, std::max(32, za / 2), std::min(nz, 2 * za)}) {
+      const int zc = stream2_zchunk(c, z);
+      if (zc >= 1) add({WAVE_KERNEL_STREAM2, c->ry, c->nw, zc});
     }
   }
   if (cand.empty()) {  // planes too large to stream: the direct kernel is the only choice
     c->variant = WAVE_KERNEL_DIRECT;
-    if (chosen) chosen[0] = chosen[1] = chosen[2] = 0;
+    if (chosen) chosen[0] = chosen[1] = chosen[2] = chosen[3] = 0;
     return WAVE_OK;
   }
-  if (c->nrec > 0 && (int64_t)c->trace_count + (int64_t)cand.size() * trial_steps > c->d.max_steps)
+  // a two-step candidate runs an even number of steps
+  const int32_t trial2 = trial_steps + (trial_steps & 1);
+  int64_t total = 0;
+  for (const auto& e : cand) total += e[0] == WAVE_KERNEL_STREAM2 ? trial2 : trial_steps;
+  if (c->nrec > 0 && (int64_t)c->trace_count + total > c->d.max_steps)
     return fail(WAVE_EINVAL, "tuning steps would overflow the trace buffer");
+  if (c->step + total > 0x7fffffff) return fail(WAVE_EINVAL, "step counter overflow");
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0), "hipEventCreate");
   HIPCHK(c, hipEventCreate(&e1), "hipEventCreate");
-  const int variant = c->variant, ry0 = c->ry, nw0 = c->nw, zc0 = c->zchunk;
+  const int variant = c->variant, ry0 = c->ry, nw0 = c->nw, zc0 = c->zchunk, zc20 = c->zchunk2;
   float best = 0.0f;
-  std::array<int, 3> pick = {ry0, nw0, zc0};
+  std::array<int, 4> pick = {variant, ry0, nw0, zc0};
   int rc = WAVE_OK;
   for (const auto& e : cand) {
-    c->variant = WAVE_KERNEL_STREAM;
-    c->ry = e[0];
-    c->nw = e[1];
-    c->zchunk = e[2];
+    c->variant = e[0];
+    c->ry = e[1];
+    c->nw = e[2];
+    if (e[0] == WAVE_KERNEL_STREAM2) c->zchunk2 = e[3]; else c->zchunk = e[3];
+    const int32_t steps = e[0] == WAVE_KERNEL_STREAM2 ? trial2 : trial_steps;
     hipError_t he = hipEventRecord(e0, c->stream);
-    if (he == hipSuccess) rc = wave_step(c, trial_steps);
+    if (he == hipSuccess) rc = wave_step(c, steps);
     if (he == hipSuccess && rc == WAVE_OK) he = hipEventRecord(e1, c->stream);
     if (he == hipSuccess && rc == WAVE_OK) he = hipEventSynchronize(e1);
     float ms = 0.0f;
     if (he == hipSuccess && rc == WAVE_OK) he = hipEventElapsedTime(&ms, e0, e1);
     if (he != hipSuccess) rc = dev_fail(c, he, "tuning");
     if (rc != WAVE_OK) break;
-    if (best == 0.0f || ms < best) {
-      best = ms;
+    const float per = ms / (float)steps;
+    if (best == 0.0f || per < best) {
+      best = per;
       pick = e;
     }
+    // the single-step settings stay those of the best single-step candidate
+    if (e[0] == WAVE_KERNEL_STREAM2) c->zchunk2 = zc20;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -960,17 +1085,19 @@ int wave_tune(wave_ctx* c, int32_t trial_steps, int32_t chosen[3]) {
     c->ry = ry0;
     c->nw = nw0;
     c->zchunk = zc0;
+    c->zchunk2 = zc20;
     return rc;
   }
-  c->variant = WAVE_KERNEL_STREAM;
-  c->ry = pick[0];
-  c->nw = pick[1];
-  c->zchunk = pick[2];
-  if (chosen) {
-    chosen[0] = pick[0];
-    chosen[1] = pick[1];
-    chosen[2] = pick[2];
+  c->variant = pick[0];
+  c->ry = pick[1];
+  c->nw = pick[2];
+  if (pick[0] == WAVE_KERNEL_STREAM2) {
+    c->zchunk2 = pick[3];
+  } else {
+    c->zchunk = pick[3];
   }
+  if (chosen)
+    for (int k = 0; k < 4; ++k) chosen[k] = pick[k];
   return WAVE_OK;
 }
 
@@ -1011,6 +1138,10 @@ double wave_sweep_bytes(const wave_ctx* c) {
   const double layer = total - inner;
   const double es = c->es;
   const double eta_b = c->plan.eta == (size_t)-1 ? 0.0 : 4.0;
+  if (c->variant == WAVE_KERNEL_STREAM2 && stream2_zchunk(c, c->zchunk2) >= 1)
+    // one launch = two steps: u^n, u^{n-1}, vp read, u^{n+1}, u^{n+2}
+    // written; a layer point adds phi^n read and phi^{n+2} written
+    return inner * (4.0 * es + 4.0) + layer * (4.0 * es + 12.0);
   return inner * (3.0 * es + 4.0) + layer * (3.0 * es + 12.0 + eta_b);
 }
 
@@ -1201,7 +1332,7 @@ int wave_batch_run(wave_batch* b, int32_t n) {
     wave_ctx* c = b->members[i];
     const int32_t t = std::min(b->remaining[i], n);
     b->h_shots[i].target = t;
-    b->h_state[i].cur = c->cur;
+    b->h_state[i].cur = c->icur < c->iprev ? 0 : 1;
     b->h_state[i].step = (int32_t)c->step;
     b->h_state[i].done = 0;
     b->h_state[i].trace_row = c->trace_count;
@@ -1256,7 +1387,7 @@ int wave_batch_run(wave_batch* b, int32_t n) {
   for (size_t i = 0; i < nm; ++i) {
     wave_ctx* c = b->members[i];
     const int32_t t = b->h_shots[i].target;
-    if (t & 1) c->cur = 1 - c->cur;
+    if (t & 1) std::swap(c->icur, c->iprev);
     c->step += t;
     if (c->nrec > 0) c->trace_count += t;
     b->remaining[i] -= t;

@@ -185,7 +185,7 @@ def test_tuned_runs_stay_exact(W):
     ref = [solo(W, s) for s in shots]
     sh = W.shot_from_synth(shots[0])
     cfg = sh.tune(2)                  # <= 12 candidates x 2 steps
-    assert len(cfg) == 3
+    assert len(cfg) == 4
     sh.step(60 - sh.step_count)
     same(read_all(W, sh), ref[0], "tuned shot")
     sh.close()

@@ -459,15 +459,31 @@ __global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) 
   constexpr int LSZ = (TY + 2 * kR) * (kTX + 2 * kR) + 64;  // + a dump row
   __shared__ float sm[2][LSZ];
 
-  // XCD-aware tile order: dispatch sends block b to XCD b % 8; give each XCD
-  // a contiguous range of logical tiles.
+  // XCD-aware tile order: dispatch sends block b to XCD b % 8.
   const int nb = gridDim.x, bid = blockIdx.x;
-  const int per = nb >> 3, rem = nb & 7, xcd = bid & 7, slot = bid >> 3;
-  const int logical = (xcd < rem) ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
-  const int tx = logical % tiles_x;
-  const int t2 = logical / tiles_x;
-  const int ty = t2 % tiles_y;
-  const int ch = t2 / tiles_y;
+  const int xcd = bid & 7, slot = bid >> 3;
+  int tx, ty, ch;
+  if ((tiles_y & 7) == 0) {
+    // each XCD owns a slab of tile rows for every z chunk and walks it chunk
+    // by chunk: the tiles it runs at once are x and y neighbours, and the
+    // planes a chunk shares with the one below were read just before, so
+    // halos and chunk warm-ups come from its L2 rather than HBM (the
+    // workgroup count is tiles_x * tiles_y * chunks, a multiple of 8, so
+    // every XCD gets the same share)
+    const int sh = tiles_y >> 3;
+    tx = slot % tiles_x;
+    const int t2 = slot / tiles_x;
+    ty = xcd * sh + t2 % sh;
+    ch = t2 / sh;
+  } else {
+    // each XCD gets a contiguous range of logical tiles
+    const int per = nb >> 3, rem = nb & 7;
+    const int logical = (xcd < rem) ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+    tx = logical % tiles_x;
+    const int t2 = logical / tiles_x;
+    ty = t2 % tiles_y;
+    ch = t2 / tiles_y;
+  }
   const int x0 = tx * kTX, y0 = ty * TY;
   const bool damp = a.damping != 0;
   const ChunkInfo c = chunk_of(ch, a.nz, a.w, zchunk, damp);
@@ -717,13 +733,12 @@ int stream_zchunk_limit(int64_t plane) {
 }
 
 int auto_zchunk(int nx, int ny, int nz, int ry, int nw) {
-  // About nz/16 planes (the measured optimum at 512^3 and 1024^3: short
-  // enough that tiles of unequal cost balance over many workgroups per CU),
-  // shortened further when the grid would have fewer than ~8192 workgroups,
+  // 64 planes (the measured optimum at 512^3 and 1024^3 with the slab tile
+  // order), shortened when the grid would have fewer than ~2048 workgroups,
   // but at least 32 planes so a chunk's 8-plane warm-up stays a modest cost.
   const int64_t tiles = (int64_t)((nx + kTX - 1) / kTX) * ((ny + ry * nw - 1) / (ry * nw));
-  const int64_t chunks = (8192 + tiles - 1) / tiles;
-  int zc = std::min<int64_t>(nz / 16, (nz + chunks - 1) / chunks);
+  const int64_t chunks = (2048 + tiles - 1) / tiles;
+  int zc = (int)std::min<int64_t>(64, (nz + chunks - 1) / chunks);
   zc = std::max(zc, 32);
   return std::min(zc, nz);
 }

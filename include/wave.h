@@ -236,7 +236,8 @@ int wave_set_kernel(wave_ctx *ctx, int32_t variant, int32_t rows_per_wave,
  * under the two-step kernel with a few z-chunk lengths (trial_steps rounded
  * up to even there).  Every candidate computes identical results, so the
  * trials are ordinary steps of the run.  Each is timed with HIP events; the
- * fastest per step is kept.  *chosen (may be NULL) receives {variant,
+ * fastest per step is kept (a candidate later in the list must be at least
+ * 1.5 % faster to replace an earlier one, so near-ties pick stably).  *chosen (may be NULL) receives {variant,
  * rows_per_wave, waves_per_group, zchunk}; {0, 0, 0, 0} when the planes are
  * too large to stream and the direct kernel is kept.  Synchronises.  EINVAL
  * if the steps would overflow the trace buffer. */

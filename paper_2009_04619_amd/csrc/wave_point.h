@@ -40,6 +40,15 @@
 namespace wave {
 namespace {
 
+// Cache-policy bits of the buffer accesses (gfx950: bit 0 sc0, bit 1 nt,
+// bit 4 sc1).  Loads of data read once per sweep (u^{n-1}, vp, phi) and the
+// stores of u^{n+1} and phi carry the non-temporal hint, so they do not
+// displace the u^n planes that neighbouring tiles and the next z chunk
+// re-read from L2 (measured: 2.8 % faster at 512^3, 5.4 % at 1000^3; the
+// hint on the loads alone is slower, on the stores alone neutral).
+constexpr int kLdOnce = 2;
+constexpr int kSt = 2;
+
 // ---- wavefield storage types ------------------------------------------------
 struct StF32 {
   using T = float;
@@ -50,9 +59,12 @@ struct StF32 {
   static __device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
   }
+  static __device__ __forceinline__ float bld1(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, kLdOnce));
+  }
   static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
                                              float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)vo, (int)so, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)vo, (int)so, kSt);
   }
 };
 
@@ -74,9 +86,12 @@ struct StBF16 {
   static __device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
     return cvt((uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0));
   }
+  static __device__ __forceinline__ float bld1(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return cvt((uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, kLdOnce));
+  }
   static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
                                              float v) {
-    __builtin_amdgcn_raw_buffer_store_b16(enc(v), r, (int)vo, (int)so, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(enc(v), r, (int)vo, (int)so, kSt);
   }
 };
 
@@ -90,10 +105,14 @@ struct StF16 {
     return cvt(__builtin_bit_cast(
         _Float16, (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0)));
   }
+  static __device__ __forceinline__ float bld1(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return cvt(__builtin_bit_cast(
+        _Float16, (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, kLdOnce)));
+  }
   static __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
                                              float v) {
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, enc(v)), r, (int)vo,
-                                          (int)so, 0);
+                                          (int)so, kSt);
   }
 };
 
@@ -130,9 +149,12 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_at(const void* p, uint32_
 __device__ __forceinline__ float bld_f32(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
   return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
 }
+__device__ __forceinline__ float bld1_f32(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, kLdOnce));
+}
 __device__ __forceinline__ void bst_f32(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so,
                                         float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)vo, (int)so, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)vo, (int)so, kSt);
 }
 
 // Lane offset that is out of range for every eta/phi resource (their range

@@ -213,7 +213,10 @@ int wave_energy(wave_ctx *ctx, double *out);
                                 trails the first by 4 planes along z, the
                                 first step's results stay on chip (needs
                                 WAVE_TWO_STEP); an odd remaining step runs
-                                the single-step kernel                  */
+                                the single-step kernel, and so do all
+                                steps while some 56 x 16 output tile's
+                                region (plus 4 cells) holds more than 32
+                                sources                                 */
 
 /* Select the sweep kernel and its tile: rows_per_wave (RY) and
  * waves_per_group (NW) give a 64 x (RY*NW) xy tile; zchunk is the number of

@@ -143,6 +143,9 @@ hipError_t launch_inject_record(const InjectArgs& a, int storage, hipStream_t s)
 // tables; zchunk <= stream2_zchunk_limit(plane) (window of zchunk + 16 planes).
 hipError_t launch_sweep2(const Sweep2Args& g, int storage, int zchunk, hipStream_t s);
 int stream2_zchunk_limit(int64_t plane);
+// Whether every two-step tile holds at most the number of sources the kernel
+// gathers per tile (ijk: [n][3] grid indices, host memory).
+bool sweep2_sources_fit(const int32_t* ijk, int n);
 int auto_zchunk2(int nx, int ny, int nz);
 hipError_t launch_energy(const EnergyArgs& a, int storage, hipStream_t s);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);

@@ -23,6 +23,7 @@
 // phi^n at points this tile has finished, so nothing is written in place).
 // Supported: damping off, or the default profile held as tables.
 #include <algorithm>
+#include <unordered_map>
 
 #include "wave_internal.h"
 #include "wave_point.h"
@@ -49,11 +50,21 @@ constexpr int kL2 = 10;                   // u^n ring slots = unroll length
 static_assert(kRA * kW2 == kAR && kRB * kW2 == kTY2, "rows must split evenly");
 static_assert(kL2 % kRing == 0 && kL2 % 2 == 0, "ring lengths must divide the unroll");
 
+// A source that falls in a tile's first-step region and chunk window: lane
+// (x - x0), y, z and its wavelet sample w[n].
+struct TileSrc {
+  int lane, y, z;
+  float wq;
+};
+constexpr int kMaxTileSrc = 32;
+
 struct Smem2 {
   float sa[2][kSPL];                 // staged u^n plane (double-buffered)
   float rb[kRing][kRPL];             // u^{n+1}, first-step region
   float pb[kRing][kPPL];             // phi^{n+1}, output rows
   float dump[kHPT2 * kNT2 - kNH2 + 64];
+  TileSrc src[kMaxTileSrc];          // the tile's sources, in list order
+  int nsrc;
 };
 
 // z chunks of the two-step sweep: as the single-step ones, with caps 4
@@ -62,6 +73,20 @@ struct Smem2 {
 __device__ inline ChunkInfo chunk2_of(int ch, int nz, int w, int zc, bool damp) {
   return chunk_of(ch, nz, (damp && w > 0) ? w + kR : 0, zc, damp && w > 0);
 }
+
+#ifndef K2_CV
+#define K2_CV 1
+#endif
+__device__ __forceinline__ float vreg_copy(float x) {
+  float v;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
+  return v;
+}
+#if K2_CV
+#define K2_VREG(x) vreg_copy(x)
+#else
+#define K2_VREG(x) (x)
+#endif
 
 template <class S, int EM>
 __device__ __forceinline__ void s2_loop(const Sweep2Args& g, Smem2& sm, int x0, int y0, int zb,
@@ -229,6 +254,44 @@ __device__ __forceinline__ void s2_loop(const Sweep2Args& g, Smem2& sm, int x0, 
 #pragma unroll
     for (int r = 0; r < kRA; ++r) eoa[r] = (va[r] && (lxa[r] || capz)) ? voa4[r] : kOOB;
   };
+  // the tile's sources, gathered once in list order (wave 0, 64 at a time):
+  // the plane loop then tests LDS entries instead of reading the source
+  // list from memory, whose waits would also drain the operand prefetch
+  if (wv == 0) {
+    int n = 0;
+    for (int base = 0; base < g.nsrc; base += 64) {
+      const int q2 = base + lane;
+      bool hit = false;
+      TileSrc e{0, 0, 0, 0.0f};
+      if (q2 < g.nsrc) {
+        const int sx = g.src_ijk[3 * q2], sy = g.src_ijk[3 * q2 + 1], sz = g.src_ijk[3 * q2 + 2];
+        hit = sx >= x0 && sx < x0 + kTX && sy >= y0 - kR && sy < y0 + kTY2 + kR &&
+              sz >= zb - kR && sz < ze + kR;
+        if (hit)
+          e = TileSrc{sx - x0, sy, sz,
+                      g.step < g.max_steps ? g.wavelet[(int64_t)q2 * g.max_steps + g.step] : 0.0f};
+      }
+      const uint64_t m = __ballot(hit);
+      if (hit) {
+        const int pos = n + __popcll(m & ((1ull << lane) - 1ull));
+        if (pos < kMaxTileSrc) sm.src[pos] = e;
+      }
+      n += __popcll(m);
+    }
+    if (lane == 0) sm.nsrc = n;
+  }
+  __syncthreads();
+  // (the host runs single steps instead when a tile would hold more; the
+  // bound only keeps the reads inside the list)
+  const int nts = min(__builtin_amdgcn_readfirstlane(sm.nsrc), kMaxTileSrc);
+
+  // the stencil weights in vector registers: this loop has more wave-uniform
+  // values than scalar registers, and a weight kept in a vector register
+  // costs the multiply-adds nothing
+  float cv[14];
+#pragma unroll
+  for (int m = 0; m < 14; ++m) cv[m] = K2_VREG(m < 13 ? a.c[m] : a.ce);
+
   const int za0 = zb - kR;
   if (LAYER) set_eoa(za0);
 #pragma unroll
@@ -271,53 +334,60 @@ __device__ __forceinline__ void s2_loop(const Sweep2Args& g, Smem2& sm, int x0, 
     const bool inz = za >= 0 && za < nz;
     const bool ownz = za >= zb && za < ze;
     const bool capza = za < w || za >= nz - w;
-    const float* srcw = g.wavelet;
+    float res[kRA], nph[kRA];
+    bool lay[kRA];
 #pragma unroll
     for (int r = 0; r < kRA; ++r) {
       const float* row = s + sta[r];
       const float c = q[(Sl + kR) % kL2][r];
-      float lap = a.c[0] * c;
+      float lap = cv[0] * c;
 #pragma unroll
-      for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(a.c[m], row[m] + row[-m], lap);
-#pragma unroll
-      for (int m = 1; m <= kR; ++m)
-        lap = __builtin_fmaf(a.c[4 + m], row[m * kSW] + row[-m * kSW], lap);
+      for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(cv[m], row[m] + row[-m], lap);
 #pragma unroll
       for (int m = 1; m <= kR; ++m)
-        lap = __builtin_fmaf(a.c[8 + m], q[(Sl + kR + m) % kL2][r] + q[(Sl + kR - m) % kL2][r], lap);
-      lap = __builtin_fmaf(a.ce, c, lap);
-      float res, nph = 0.0f;
-      bool lay = false;
+        lap = __builtin_fmaf(cv[4 + m], row[m * kSW] + row[-m * kSW], lap);
+#pragma unroll
+      for (int m = 1; m <= kR; ++m)
+        lap = __builtin_fmaf(cv[8 + m], q[(Sl + kR + m) % kL2][r] + q[(Sl + kR - m) % kL2][r], lap);
+      lap = __builtin_fmaf(cv[13], c, lap);
+      nph[r] = 0.0f;
+      lay[r] = false;
       if (LAYER) {
-        lay = va[r] && (lxa[r] || capza);
-        const float e = lay ? (float)(a.dt * (tsa[r] + tza[B])) : 0.0f;
-        res = upd_layer(c, pva[B][r], vva[B][r], lap, e, pha[B][r]);
-        nph = upd_phi(pha[B][r], e, dqxa, row[1] - row[-1], dqya[r], row[kSW] - row[-kSW], dza[B],
-                      q[(Sl + kR + 1) % kL2][r] - q[(Sl + kR - 1) % kL2][r]);
+        lay[r] = va[r] && (lxa[r] || capza);
+        const float e = lay[r] ? (float)(a.dt * (tsa[r] + tza[B])) : 0.0f;
+        res[r] = upd_layer(c, pva[B][r], vva[B][r], lap, e, pha[B][r]);
+        nph[r] = upd_phi(pha[B][r], e, dqxa, row[1] - row[-1], dqya[r], row[kSW] - row[-kSW], dza[B],
+                         q[(Sl + kR + 1) % kL2][r] - q[(Sl + kR - 1) % kL2][r]);
       } else {
-        res = upd_inner(c, pva[B][r], vva[B][r], lap);
+        res[r] = upd_inner(c, pva[B][r], vva[B][r], lap);
       }
-      // the stored value (storage rounding), then the sources of step n in
-      // list order, each stored in turn (Alg. 1: the source add follows the
-      // sweep)
-      res = S::cvt(S::enc(res));
-      for (int q2 = 0; q2 < g.nsrc; ++q2) {
-        if (g.src_ijk[3 * q2 + 2] == za) {
-          const float wq = g.step < g.max_steps ? srcw[(int64_t)q2 * g.max_steps + g.step] : 0.0f;
-          if (x == g.src_ijk[3 * q2] && yra[r] == g.src_ijk[3 * q2 + 1])
-            res = S::cvt(S::enc(__builtin_fmaf(vva[B][r], wq, res)));
-        }
+      // the stored value (storage rounding)
+      res[r] = S::cvt(S::enc(res[r]));
+    }
+    // then the sources of step n in list order, each stored in turn (Alg. 1:
+    // the source add follows the sweep); entries of other planes are skipped
+    // with a scalar test, and the add is a select, not a branch
+    for (int q2 = 0; q2 < nts; ++q2) {
+      const TileSrc e = sm.src[q2];
+      if (__builtin_amdgcn_readfirstlane(e.z) != za) continue;
+#pragma unroll
+      for (int r = 0; r < kRA; ++r) {
+        const float v = S::cvt(S::enc(__builtin_fmaf(vva[B][r], e.wq, res[r])));
+        res[r] = (lane == e.lane && yra[r] == e.y) ? v : res[r];
       }
+    }
+#pragma unroll
+    for (int r = 0; r < kRA; ++r) {
       const bool live = inz && va[r];
-      res = live ? res : 0.0f;
-      sm.rb[RS][(kRA * wv + r) * kTX + lane] = res;
-      S::bst(ro1, (ownz && owna[r]) ? voa[r] : kOOB, wk(za) * pe, res);
+      const float rv1 = live ? res[r] : 0.0f;
+      sm.rb[RS][(kRA * wv + r) * kTX + lane] = rv1;
+      S::bst(ro1, (ownz && owna[r]) ? voa[r] : kOOB, wk(za) * pe, rv1);
       // phi^{n+1} of the output rows for the second step, which another
       // wavefront may compute: written by every wavefront (zero where no
       // layer point is), whichever loop it runs
       {
         const int orow = yra[r] - y0;
-        if (orow >= 0 && orow < kTY2) sm.pb[RS][orow * kTX + lane] = (LAYER && live && lay) ? nph : 0.0f;
+        if (orow >= 0 && orow < kTY2) sm.pb[RS][orow * kTX + lane] = (LAYER && live && lay[r]) ? nph[r] : 0.0f;
       }
     }
     __syncthreads();
@@ -332,17 +402,17 @@ __device__ __forceinline__ void s2_loop(const Sweep2Args& g, Smem2& sm, int x0, 
       for (int r = 0; r < kRB; ++r) {
         const float* row = rbq + (kRB * wv + r + kR) * kTX + lane;
         const float c = qb[(Sl + kL2 - kR) % kL2][r];
-        float lap = a.c[0] * c;
+        float lap = cv[0] * c;
 #pragma unroll
-        for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(a.c[m], row[m] + row[-m], lap);
-#pragma unroll
-        for (int m = 1; m <= kR; ++m)
-          lap = __builtin_fmaf(a.c[4 + m], row[m * kTX] + row[-m * kTX], lap);
+        for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(cv[m], row[m] + row[-m], lap);
 #pragma unroll
         for (int m = 1; m <= kR; ++m)
-          lap = __builtin_fmaf(a.c[8 + m],
+          lap = __builtin_fmaf(cv[4 + m], row[m * kTX] + row[-m * kTX], lap);
+#pragma unroll
+        for (int m = 1; m <= kR; ++m)
+          lap = __builtin_fmaf(cv[8 + m],
                                qb[(Sl + kL2 - kR + m) % kL2][r] + qb[(Sl + kL2 - kR - m) % kL2][r], lap);
-        lap = __builtin_fmaf(a.ce, c, lap);
+        lap = __builtin_fmaf(cv[13], c, lap);
         const uint32_t kq = wk(zq);
         float res;
         if (LAYER) {
@@ -427,6 +497,24 @@ hipError_t sweep2_t(const Sweep2Args& g, int zchunk, hipStream_t st) {
 int stream2_zchunk_limit(int64_t plane) {
   const int64_t z = kWindowMax / (plane * 4) - 4 * kR;
   return (int)std::min<int64_t>(z, 1 << 30);
+}
+
+bool sweep2_sources_fit(const int32_t* ijk, int n) {
+  // first-step region of tile (tx, ty): x in [56 tx - 4, 56 tx + 60),
+  // y in [16 ty - 4, 16 ty + 20); each point lies in at most 2 x 2 tiles
+  std::unordered_map<int64_t, int> count;
+  for (int s = 0; s < n; ++s) {
+    const int i = ijk[3 * s], j = ijk[3 * s + 1];
+    const int tx1 = (i + kR) / kOX2, ty1 = (j + kR) / kTY2;
+    for (int tx = std::max(tx1 - 1, 0); tx <= tx1; ++tx) {
+      if (i < tx * kOX2 - kR || i >= tx * kOX2 - kR + kTX) continue;
+      for (int ty = std::max(ty1 - 1, 0); ty <= ty1; ++ty) {
+        if (j < ty * kTY2 - kR || j >= ty * kTY2 + kTY2 + kR) continue;
+        if (++count[((int64_t)tx << 32) | (uint32_t)ty] > kMaxTileSrc) return false;
+      }
+    }
+  }
+  return true;
 }
 
 int auto_zchunk2(int nx, int ny, int nz) {

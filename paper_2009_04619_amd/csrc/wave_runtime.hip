@@ -222,6 +222,8 @@ struct wave_ctx {
   double c64[13];
   double vmax;
   int nsrc, nrec, trace_count;
+  std::vector<int32_t> src_host;   // (i, j, k) of the sources
+  bool src_fit2;                   // the sources fit the two-step kernel's tiles
   int variant, ry, nw, zchunk;
   bool timing;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -631,6 +633,8 @@ int wave_alloc(const wave_desc* d, const float* vel, const float* eta, void* dev
   c->q[1] = (float)(1.0 / (4.0 * d->dy * d->dy));
   c->q[2] = (float)(1.0 / (4.0 * d->dz * d->dz));
   c->nsrc = c->nrec = c->trace_count = 0;
+  c->src_host.clear();
+  c->src_fit2 = true;
   c->variant = WAVE_KERNEL_STREAM;
   c->ry = 1;
   c->nw = 16;
@@ -721,6 +725,8 @@ int wave_inject(wave_ctx* c, int32_t i, int32_t j, int32_t k, const float* sampl
   HIPCHK(c, hipMemcpyAsync(sijk, ijk3, 12, hipMemcpyHostToDevice, c->stream), "hipMemcpyAsync");
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   c->nsrc += 1;
+  c->src_host.insert(c->src_host.end(), ijk3, ijk3 + 3);
+  c->src_fit2 = wave::sweep2_sources_fit(c->src_host.data(), c->nsrc);
   return WAVE_OK;
 }
 
@@ -835,8 +841,9 @@ int wave_step(wave_ctx* c, int32_t n) {
   if (c->nrec > 0 && (int64_t)c->trace_count + n > c->d.max_steps)
     return fail(WAVE_EINVAL, "trace buffer would overflow max_steps");
   if (c->step + n > 0x7fffffff) return fail(WAVE_EINVAL, "step counter overflow");
-  // two steps per launch while at least two remain
-  if (c->variant == WAVE_KERNEL_STREAM2) {
+  // two steps per launch while at least two remain (and the sources fit its
+  // tiles' lists)
+  if (c->variant == WAVE_KERNEL_STREAM2 && c->src_fit2) {
     const int zc2 = stream2_zchunk(c, c->zchunk2);
     if (zc2 >= 1) {
       for (; n >= 2; n -= 2) {

@@ -146,3 +146,23 @@ def test_two_step_tuner_and_errors(W):
     d = W.make_desc(shot.nx, shot.ny, shot.nz, shot.w, shot.dx, shot.dy, shot.dz, shot.dt,
                     eta_array=True, two_step=True, max_steps=10)
     assert W.wave_bytes_required(d) == 0
+
+
+@pytest.mark.parametrize("count", [20, 40])
+def test_many_sources_in_one_tile(W, count):
+    """20 sources in one tile (two on the same cell, added in list order) go
+    through the kernel's per-tile list; 40 exceed it, and the context then
+    takes single steps. Both end where the oracle ends."""
+    nx, ny, nz, w, steps = 100, 40, 30, 4, 12
+    shot = synth.config_small_layered(nx, ny, nz, w, steps, seed=61, nsrc=1)
+    rng = np.random.default_rng(count)
+    pts = [(int(rng.integers(8, 60)), int(rng.integers(4, 20)), int(rng.integers(2, 28)))
+           for _ in range(count - 1)]
+    pts.append(pts[3])
+    shot.src = pts
+    shot.wavelet = np.stack([synth.ricker(steps, shot.dt, t0=(0.1 + 0.02 * s) / 15.0)
+                             for s in range(count)])
+    shot.rec = np.array([list(p) for p in pts[:6]], np.int32)
+    say(f"case two-step {count} sources in one tile")
+    got = run_two_step(W, shot, steps, "f32", True, 16)
+    assert_same(got, oracle_ref(shot, steps, "f32", True), f"two-step {count} sources")

@@ -33,8 +33,12 @@ def log(*a):
 
 
 # sweep kernel of each variant: name, profile prefix, sources it is built from
-KERNELS = {1: ("k_sweep_stream", "sweep", ("wave_kernels.hip", "wave_point.h")),
-           2: ("k_sweep2", "sweep2", ("wave_kernels2.hip", "wave_point.h"))}
+KERNELS = {0: ("k_sweep_direct", "direct", ("wave_kernels.hip", "wave_direct.h", "wave_point.h")),
+           1: ("k_sweep_stream", "sweep", ("wave_kernels.hip", "wave_point.h")),
+           2: ("k_sweep2", "sweep2", ("wave_kernels2.hip", "wave_point.h")),
+           3: ("k_sweep_gmem", "gmem", ("wave_shapes.hip", "wave_direct.h", "wave_point.h")),
+           4: ("k_sweep_ring", "ring", ("wave_shapes.hip", "wave_direct.h", "wave_point.h")),
+           5: ("k_sweep_shift", "shift", ("wave_shapes.hip", "wave_direct.h", "wave_point.h"))}
 
 
 def kernel_source_sha(variant: int = 1) -> str:
@@ -50,6 +54,11 @@ def describe(cfg) -> str:
         return f"two-step (3.5-D) zchunk={zc}"
     if v == 0:
         return "direct"
+    if v == 3:
+        return f"3-D tile {ry}x{nw}x{zc}, all operands from memory"
+    if v in (4, 5):
+        return f"2.5-D {'ring of 9 LDS planes' if v == 4 else 'LDS plane + shifted registers'} " \
+               f"64x{nw} zchunk={zc}"
     return f"stream rows_per_wave={ry} waves_per_group={nw} zchunk={zc}"
 
 
@@ -112,6 +121,43 @@ def plain_rate(W, torch, n, w, storage, steps):
     return {"value": round(shot.points * steps / ms / 1e6, 3), "unit": "Gpoints/s",
             "storage": storage, "steps": steps, "kernel": describe(cfg),
             "sweep_gbps_algorithmic": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
+
+
+# the paper's code shapes (Sec. IV, Table II) on this GPU: wave_set_kernel
+# arguments and a label
+SHAPES = [((1, 1, 16, 0), "2.5-D stream, LDS plane + register ring, prefetch (default)"),
+          ((0, 0, 0, 0), "3-D 64x4x1, all operands from memory (direct)"),
+          ((3, 8, 8, 8), "gmem 8x8x8"), ((3, 4, 4, 4), "gmem 4x4x4"),
+          ((3, 16, 16, 4), "gmem 16x16x4"), ((3, 32, 32, 1), "gmem 32x32x1"),
+          ((3, 64, 4, 4), "gmem 64x4x4"),
+          ((4, 1, 8, 0), "st_smem 64x8 (ring of 9 LDS planes)"),
+          ((4, 1, 16, 0), "st_smem 64x16 (ring of 9 LDS planes)"),
+          ((5, 1, 8, 0), "st_reg_shft 64x8 (LDS plane + 9 shifted registers)"),
+          ((5, 1, 16, 0), "st_reg_shft 64x16 (LDS plane + 9 shifted registers)")]
+
+
+def shapes_rate(W, torch, n, w, steps=20):
+    """Sweep-kernel time of each code shape on one shot (kernel time from HIP
+    events on the shot's stream; identical results by construction)."""
+    import synth
+    shot = synth.config_c2(steps=len(SHAPES) * (steps + 2) + 8, n=n, w=w)
+    sh = W.shot_from_synth(shot, max_steps=len(SHAPES) * (steps + 2) + 8)
+    out = []
+    for cfg, label in SHAPES:
+        sh.set_kernel(*cfg)
+        sh.step(2)
+        sh.set_timing(True)
+        sh.step(steps)
+        kms, k = sh.read_timing()
+        sh.set_timing(False)
+        avg = kms / max(k, 1)
+        gbs = sh.sweep_bytes() / (avg / 1e3) / 1e9
+        log(f"[bench] shape {label}: {avg:.3f} ms, {shot.points / avg / 1e6:.1f} Gpt/s")
+        out.append({"shape": label, "args": list(cfg), "ms": round(avg, 4),
+                    "gpoints_per_s": round(shot.points / avg / 1e6, 2),
+                    "frac": round(gbs / PEAK_HBM_GBS, 4)})
+    sh.close()
+    return out
 
 
 def batched_rate(W, torch, count):
@@ -296,7 +342,7 @@ def main():
     alg_bytes = sh.sweep_bytes()
     achieved = alg_bytes / (avg_ms / 1e3) / 1e9
     workload = f"{args.n}cube_w{args.w}_{args.storage}"
-    variant = 2 if cfg[0] == 2 else 1
+    variant = cfg[0] if cfg[0] in KERNELS else 1
     traffic = measured_traffic(workload, alg_bytes, variant)
     log(f"[bench] sweep kernel avg {avg_ms:.4f} ms over {launches} launches, "
         f"{alg_bytes / pts:.2f} B/pt algorithmic -> {achieved:.0f} GB/s")
@@ -312,7 +358,8 @@ def main():
     if not args.no_extras:
         extras = {"bf16_plain": plain_rate(W, torch, args.n, args.w, "bf16", 200),
                   "batched": batched_rate(W, torch, args.batch_shots),
-                  "serve": serve_run(W, torch, args.serve_requests)}
+                  "serve": serve_run(W, torch, args.serve_requests),
+                  "code_shapes": shapes_rate(W, torch, args.n, args.w)}
 
     copy_gbs = None if args.no_copy else copy_bandwidth(W, torch)
     if copy_gbs:

@@ -218,6 +218,22 @@ int wave_energy(wave_ctx *ctx, double *out);
                                 region (plus 4 cells) holds more than 32
                                 sources                                 */
 
+/* The paper's other code shapes (Sec. IV), for comparison and tuning; each
+ * evaluates every point with the same operations as the others. */
+#define WAVE_KERNEL_GMEM 3   /* 3-D tile, one thread per point, every stencil
+                                operand read from memory; the block extents
+                                (bx, by, bz) are passed as (rows_per_wave,
+                                waves_per_group, zchunk): (8,8,8), (4,4,4),
+                                (16,16,4), (32,32,1), (64,4,1), (64,4,4)  */
+#define WAVE_KERNEL_RING 4   /* 2.5-D: 64 x ty tile streamed along z through
+                                a ring of 9 staged planes in LDS (all
+                                neighbours from LDS); rows_per_wave = 1,
+                                waves_per_group = ty in {8, 16}, zchunk as
+                                for the streaming kernel (0 = automatic)  */
+#define WAVE_KERNEL_SHIFT 5  /* 2.5-D: one staged plane in LDS for the x/y
+                                neighbours, the z neighbours in 9 registers
+                                shifted each plane; parameters as RING     */
+
 /* Select the sweep kernel and its tile: rows_per_wave (RY) and
  * waves_per_group (NW) give a 64 x (RY*NW) xy tile; zchunk is the number of
  * z planes one workgroup streams (0 = automatic).  Only compiled
@@ -237,11 +253,14 @@ int wave_set_kernel(wave_ctx *ctx, int32_t variant, int32_t rows_per_wave,
 /* Autotuner: advance the simulation by `trial_steps` real steps under each
  * compiled tile shape and a few z-chunk lengths, and, with WAVE_TWO_STEP,
  * under the two-step kernel with a few z-chunk lengths (trial_steps rounded
- * up to even there).  Every candidate computes identical results, so the
- * trials are ordinary steps of the run.  Each is timed with HIP events; the
- * fastest per step is kept (a candidate later in the list must be at least
- * 1.5 % faster to replace an earlier one, so near-ties pick stably).  *chosen (may be NULL) receives {variant,
- * rows_per_wave, waves_per_group, zchunk}; {0, 0, 0, 0} when the planes are
+ * up to even there), then under four of the paper's other code shapes
+ * (WAVE_KERNEL_GMEM 8x8x8 and 64x4x4, RING and SHIFT with 16 rows).  Every
+ * candidate computes identical results, so the trials are ordinary steps of
+ * the run.  Each is timed with HIP events; the fastest per step is kept (a
+ * candidate later in the list must be at least 1.5 % faster to replace an
+ * earlier one, so near-ties pick stably).  *chosen (may be NULL) receives
+ * the wave_set_kernel arguments {variant, rows_per_wave, waves_per_group,
+ * zchunk} of the pick; {0, 0, 0, 0} when the planes are
  * too large to stream and the direct kernel is kept.  Synchronises.  EINVAL
  * if the steps would overflow the trace buffer. */
 int wave_tune(wave_ctx *ctx, int32_t trial_steps, int32_t chosen[4]);
@@ -256,7 +275,10 @@ int wave_read_timing(wave_ctx *ctx, double *ms_total, int64_t *launches);
  * or written once per point.  Float32 storage: 16 bytes per inner point
  * (u^n, u^{n-1}, vp read, u^{n+1} written); a layer point adds phi read and
  * written (8) and, with WAVE_ETA_ARRAY, eta read (4).  u is 2 bytes per
- * access with 16-bit storage. */
+ * access with 16-bit storage.  When the two-step kernel is in use, one
+ * launch covers two steps: u^n, u^{n-1}, vp read and u^{n+1}, u^{n+2}
+ * written per point (20 bytes in float32), phi read and written once more
+ * in the layer. */
 double wave_sweep_bytes(const wave_ctx *ctx);
 
 /* Device-to-device copy of `bytes` (multiple of 16, both pointers 16-byte

@@ -147,6 +147,16 @@ int stream2_zchunk_limit(int64_t plane);
 // gathers per tile (ijk: [n][3] grid indices, host memory).
 bool sweep2_sources_fit(const int32_t* ijk, int n);
 int auto_zchunk2(int nx, int ny, int nz);
+// The paper's other code shapes (wave_shapes.hip): 3-D tiles of bx x by x bz
+// threads reading every operand from memory, and 2.5-D tiles of 64 x ty
+// streamed through z chunks, shape 0 = ring of 9 staged planes, 1 = staged
+// plane plus a shifted register queue along z.
+bool gmem_config_supported(int bx, int by, int bz);
+hipError_t launch_sweep_gmem(const SweepArgs& a, int storage, int bx, int by, int bz,
+                             hipStream_t s);
+hipError_t launch_sweep_25d(const SweepArgs& a, int storage, int shape, int ty, int zchunk,
+                            hipStream_t s);
+int auto_zchunk25(int nx, int ny, int nz, int ty);
 hipError_t launch_energy(const EnergyArgs& a, int storage, hipStream_t s);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 // Scatter a compact [nz][ny][nx] float field into a padded array whose

@@ -6,74 +6,21 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "wave_direct.h"
 #include "wave_internal.h"
 #include "wave_point.h"
 
 namespace wave {
 namespace {
 
-// Default damping profile in table mode: eta(x, y, z) = fl32(dt * ((tx[x] +
-// ty[y]) + tz[z])) (the profile is a sum of three per-axis terms; the double
-// operations match the host's).  Its differences come from the dq tables.
-__device__ __forceinline__ float eta_tab(const SweepArgs& a, int x, int y, int z) {
-  const double* tx = a.etab + 1;
-  const double* ty = tx + a.nx + 2;
-  const double* tz = ty + a.ny + 2;
-  return (float)(a.dt * ((tx[x] + ty[y]) + tz[z]));
-}
-
-__device__ __forceinline__ bool in_layer(const SweepArgs& a, int x, int y, int z) {
-  return x < a.w || x >= a.nx - a.w || y < a.w || y >= a.ny - a.w || z < a.w ||
-         z >= a.nz - a.w;
-}
-
 // ---- variant 0: one thread per point, every operand read from memory -------
 template <class S>
 __global__ __launch_bounds__(256) void k_sweep_direct(SweepArgs a) {
-  using T = typename S::T;
   const int x = blockIdx.x * kTX + threadIdx.x;
   const int y = blockIdx.y * 4 + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= a.nx || y >= a.ny) return;
-  const T* u = static_cast<const T*>(a.cur);
-  T* un = static_cast<T*>(a.nxt);
-  const int64_t P = a.pitch, Q = a.plane;
-  const int64_t p = (int64_t)z * Q + (int64_t)y * P + x;
-  const float c = S::ld(u, p);
-  float lap = a.c[0] * c;
-#pragma unroll
-  for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(a.c[m], S::ld(u, p + m) + S::ld(u, p - m), lap);
-#pragma unroll
-  for (int m = 1; m <= kR; ++m)
-    lap = __builtin_fmaf(a.c[4 + m], S::ld(u, p + m * P) + S::ld(u, p - m * P), lap);
-#pragma unroll
-  for (int m = 1; m <= kR; ++m)
-    lap = __builtin_fmaf(a.c[8 + m], S::ld(u, p + m * Q) + S::ld(u, p - m * Q), lap);
-  lap = __builtin_fmaf(a.ce, c, lap);
-  const float pu = S::ld(un, p);
-  const float vp = a.vp[p];
-  float r;
-  if (a.damping && in_layer(a, x, y, z)) {
-    float e, dqx, dqy, dqz;
-    if (a.etab) {
-      e = eta_tab(a, x, y, z);
-      dqx = a.etq[x];
-      dqy = a.etq[a.nx + y];
-      dqz = a.etq[a.nx + a.ny + z];
-    } else {
-      e = a.eta[p];
-      dqx = (a.eta[p + 1] - a.eta[p - 1]) * a.q[0];
-      dqy = (a.eta[p + P] - a.eta[p - P]) * a.q[1];
-      dqz = (a.eta[p + Q] - a.eta[p - Q]) * a.q[2];
-    }
-    const float ph = a.phi[p];
-    r = upd_layer(c, pu, vp, lap, e, ph);
-    a.phi[p] = upd_phi(ph, e, dqx, S::ld(u, p + 1) - S::ld(u, p - 1), dqy,
-                       S::ld(u, p + P) - S::ld(u, p - P), dqz, S::ld(u, p + Q) - S::ld(u, p - Q));
-  } else {
-    r = upd_inner(c, pu, vp, lap);
-  }
-  S::st(un, p, r);
+  direct_point<S>(a, x, y, z);
 }
 
 // ---- variant 1: 2.5-D streaming ------------------------------------------------

@@ -225,6 +225,7 @@ struct wave_ctx {
   std::vector<int32_t> src_host;   // (i, j, k) of the sources
   bool src_fit2;                   // the sources fit the two-step kernel's tiles
   int variant, ry, nw, zchunk;
+  int shp[3];             // WAVE_KERNEL_GMEM: block (bx, by, bz); RING/SHIFT: (1, ty, zchunk)
   bool timing;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t events_used;
@@ -636,6 +637,7 @@ int wave_alloc(const wave_desc* d, const float* vel, const float* eta, void* dev
   c->src_host.clear();
   c->src_fit2 = true;
   c->variant = WAVE_KERNEL_STREAM;
+  c->shp[0] = c->shp[1] = c->shp[2] = 0;
   c->ry = 1;
   c->nw = 16;
   c->zchunk = 0;
@@ -856,6 +858,19 @@ int wave_step(wave_ctx* c, int32_t n) {
   wave::SweepArgs sa = sweep_args(c);
   const int zc = stream_zchunk(c, c->ry, c->nw, c->zchunk);
   const bool direct = c->variant == WAVE_KERNEL_DIRECT || zc < 1;
+  const bool shape25 = c->variant == WAVE_KERNEL_RING || c->variant == WAVE_KERNEL_SHIFT;
+  const int zc25 = !shape25 ? 0
+                   : c->shp[2] > 0 ? std::min(c->shp[2], c->L.nz)
+                                   : wave::auto_zchunk25(c->L.nx, c->L.ny, c->L.nz, c->shp[1]);
+  auto launch_one = [&](const wave::SweepArgs& s) -> hipError_t {
+    if (c->variant == WAVE_KERNEL_GMEM)
+      return wave::launch_sweep_gmem(s, c->d.storage, c->shp[0], c->shp[1], c->shp[2], c->stream);
+    if (shape25)
+      return wave::launch_sweep_25d(s, c->d.storage, c->variant == WAVE_KERNEL_RING ? 0 : 1,
+                                    c->shp[1], zc25, c->stream);
+    return direct ? wave::launch_sweep_direct(s, c->d.storage, c->stream)
+                  : wave::launch_sweep_stream(s, c->d.storage, c->ry, c->nw, zc, c->stream);
+  };
 
   wave::InjectArgs ia = inject_args(c);
 
@@ -865,8 +880,7 @@ int wave_step(wave_ctx* c, int32_t n) {
     hipEvent_t e1;
     int rc = timing_begin(c, &e1);
     if (rc) return rc;
-    hipError_t e = direct ? wave::launch_sweep_direct(sa, c->d.storage, c->stream)
-                       : wave::launch_sweep_stream(sa, c->d.storage, c->ry, c->nw, zc, c->stream);
+    hipError_t e = launch_one(sa);
     if (e != hipSuccess) return dev_fail(c, e, "sweep launch");
     if (e1) HIPCHK(c, hipEventRecord(e1, c->stream), "hipEventRecord");
     if (c->nsrc > 0 || c->nrec > 0) {
@@ -1003,6 +1017,24 @@ int wave_set_kernel(wave_ctx* c, int32_t variant, int32_t ry, int32_t nw, int32_
     c->zchunk2 = zchunk;
     return WAVE_OK;
   }
+  if (variant == WAVE_KERNEL_GMEM) {
+    if (!wave::gmem_config_supported(ry, nw, zchunk))
+      return fail(WAVE_EINVAL, "3-D tile (bx, by, bz) not compiled");
+    c->variant = variant;
+    c->shp[0] = ry;
+    c->shp[1] = nw;
+    c->shp[2] = zchunk;
+    return WAVE_OK;
+  }
+  if (variant == WAVE_KERNEL_RING || variant == WAVE_KERNEL_SHIFT) {
+    if (ry != 1 || (nw != 8 && nw != 16)) return fail(WAVE_EINVAL, "2.5-D shape needs rows_per_wave 1, 8 or 16 rows");
+    if (zchunk < 0) return fail(WAVE_EINVAL, "zchunk < 0");
+    c->variant = variant;
+    c->shp[0] = 1;
+    c->shp[1] = nw;
+    c->shp[2] = zchunk;
+    return WAVE_OK;
+  }
   if (variant != WAVE_KERNEL_STREAM) return fail(WAVE_EINVAL, "unknown kernel variant");
   if (!wave::stream_config_supported(ry, nw)) return fail(WAVE_EINVAL, "tile (rows_per_wave, waves) not compiled");
   if (zchunk < 0) return fail(WAVE_EINVAL, "zchunk < 0");
@@ -1044,6 +1076,14 @@ int wave_tune(wave_ctx* c, int32_t trial_steps, int32_t chosen[4]) {
       if (zc >= 1) add({WAVE_KERNEL_STREAM2, c->ry, c->nw, zc});
     }
   }
+  // the paper's other code shapes, last (they must beat the streaming kernel
+  // by the margin below to be picked)
+  if (!cand.empty()) {
+    add({WAVE_KERNEL_GMEM, 8, 8, 8});
+    add({WAVE_KERNEL_GMEM, 64, 4, 4});
+    add({WAVE_KERNEL_RING, 1, 16, 0});
+    add({WAVE_KERNEL_SHIFT, 1, 16, 0});
+  }
   if (cand.empty()) {  // planes too large to stream: the direct kernel is the only choice
     c->variant = WAVE_KERNEL_DIRECT;
     if (chosen) chosen[0] = chosen[1] = chosen[2] = chosen[3] = 0;
@@ -1060,14 +1100,22 @@ int wave_tune(wave_ctx* c, int32_t trial_steps, int32_t chosen[4]) {
   HIPCHK(c, hipEventCreate(&e0), "hipEventCreate");
   HIPCHK(c, hipEventCreate(&e1), "hipEventCreate");
   const int variant = c->variant, ry0 = c->ry, nw0 = c->nw, zc0 = c->zchunk, zc20 = c->zchunk2;
+  const int shp0[3] = {c->shp[0], c->shp[1], c->shp[2]};
+  auto is_shape = [](int v) {
+    return v == WAVE_KERNEL_GMEM || v == WAVE_KERNEL_RING || v == WAVE_KERNEL_SHIFT;
+  };
   float best = 0.0f;
   std::array<int, 4> pick = {variant, ry0, nw0, zc0};
   int rc = WAVE_OK;
   for (const auto& e : cand) {
     c->variant = e[0];
-    c->ry = e[1];
-    c->nw = e[2];
-    if (e[0] == WAVE_KERNEL_STREAM2) c->zchunk2 = e[3]; else c->zchunk = e[3];
+    if (is_shape(e[0])) {
+      for (int k = 0; k < 3; ++k) c->shp[k] = e[k + 1];
+    } else {
+      c->ry = e[1];
+      c->nw = e[2];
+      if (e[0] == WAVE_KERNEL_STREAM2) c->zchunk2 = e[3]; else c->zchunk = e[3];
+    }
     const int32_t steps = e[0] == WAVE_KERNEL_STREAM2 ? trial2 : trial_steps;
     hipError_t he = hipEventRecord(e0, c->stream);
     if (he == hipSuccess) rc = wave_step(c, steps);
@@ -1095,15 +1143,20 @@ int wave_tune(wave_ctx* c, int32_t trial_steps, int32_t chosen[4]) {
     c->nw = nw0;
     c->zchunk = zc0;
     c->zchunk2 = zc20;
+    for (int k = 0; k < 3; ++k) c->shp[k] = shp0[k];
     return rc;
   }
   c->variant = pick[0];
-  c->ry = pick[1];
-  c->nw = pick[2];
-  if (pick[0] == WAVE_KERNEL_STREAM2) {
-    c->zchunk2 = pick[3];
+  if (is_shape(pick[0])) {
+    for (int k = 0; k < 3; ++k) c->shp[k] = pick[k + 1];
   } else {
-    c->zchunk = pick[3];
+    c->ry = pick[1];
+    c->nw = pick[2];
+    if (pick[0] == WAVE_KERNEL_STREAM2) {
+      c->zchunk2 = pick[3];
+    } else {
+      c->zchunk = pick[3];
+    }
   }
   if (chosen)
     for (int k = 0; k < 4; ++k) chosen[k] = pick[k];
@@ -1147,7 +1200,7 @@ double wave_sweep_bytes(const wave_ctx* c) {
   const double layer = total - inner;
   const double es = c->es;
   const double eta_b = c->plan.eta == (size_t)-1 ? 0.0 : 4.0;
-  if (c->variant == WAVE_KERNEL_STREAM2 && stream2_zchunk(c, c->zchunk2) >= 1)
+  if (c->variant == WAVE_KERNEL_STREAM2 && c->src_fit2 && stream2_zchunk(c, c->zchunk2) >= 1)
     // one launch = two steps: u^n, u^{n-1}, vp read, u^{n+1}, u^{n+2}
     // written; a layer point adds phi^n read and phi^{n+2} written
     return inner * (4.0 * es + 4.0) + layer * (4.0 * es + 12.0);

@@ -135,7 +135,7 @@ def test_two_step_tuner_and_errors(W):
     ref = oracle_ref(shot, 60, "f32", True)
     sh = W.shot_from_synth(shot, max_steps=60, two_step=True)
     cfg = sh.tune(2)
-    assert len(cfg) == 4 and cfg[0] in (W.WAVE_KERNEL_STREAM, W.WAVE_KERNEL_STREAM2)
+    assert len(cfg) == 4 and 1 <= cfg[0] <= 5
     sh.step(60 - sh.step_count)
     assert_same(read_all(W, sh), ref, "tuned two-step context")
     sh.close()

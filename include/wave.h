@@ -214,7 +214,7 @@ int wave_energy(wave_ctx *ctx, double *out);
                                 first step's results stay on chip (needs
                                 WAVE_TWO_STEP); an odd remaining step runs
                                 the single-step kernel, and so do all
-                                steps while some 56 x 16 output tile's
+                                steps while some 56 x 24 output tile's
                                 region (plus 4 cells) holds more than 32
                                 sources                                 */
 

@@ -31,24 +31,32 @@
 namespace wave {
 namespace {
 
-constexpr int kW2 = 8;                    // wavefronts per workgroup
-constexpr int kTY2 = 16;                  // output rows per tile
+constexpr int kW2 = 16;                   // wavefronts per workgroup
+constexpr int kTY2 = 24;                  // output rows per tile
 constexpr int kOX2 = kTX - 2 * kR;        // output columns per tile (lanes 4..59)
-constexpr int kAR = kTY2 + 2 * kR;        // first-step rows (24)
-constexpr int kRA = kAR / kW2;            // first-step rows per wavefront (3)
-constexpr int kRB = kTY2 / kW2;           // second-step rows per wavefront (2)
-constexpr int kSR = kAR + 2 * kR;         // staged rows (32)
+constexpr int kAR = kTY2 + 2 * kR;        // first-step rows (32)
+constexpr int kRA = kAR / kW2;            // first-step rows per wavefront (2)
+constexpr int kSR = kAR + 2 * kR;         // staged rows (40)
 constexpr int kSW = kTX + 2 * kR;         // staged columns (72)
 constexpr int kSPL = kSR * kSW;           // staged plane (floats)
 constexpr int kNT2 = 64 * kW2;            // threads
-constexpr int kNH2 = kSPL - kAR * kTX;    // staged halo elements (768)
-constexpr int kHPT2 = (kNH2 + kNT2 - 1) / kNT2;
+constexpr int kNH2 = kSPL - kAR * kTX;    // staged halo elements (832)
 constexpr int kRPL = kAR * kTX;           // u^{n+1} ring plane (floats)
-constexpr int kPPL = kTY2 * kTX;          // phi^{n+1} ring plane (floats)
-constexpr int kRing = 5;                  // planes za-4 .. za
-constexpr int kL2 = 10;                   // u^n ring slots = unroll length
-static_assert(kRA * kW2 == kAR && kRB * kW2 == kTY2, "rows must split evenly");
+constexpr int kRing = 5;                  // u^{n+1} planes za-4 .. za in LDS
+constexpr int kL2 = 10;                   // register ring length = unroll length
+constexpr int kMaxZc2 = 512;              // longest z chunk (the z tables sit in LDS)
+constexpr int kZT = kMaxZc2 + 4 * kR;     // window planes of the longest chunk
+static_assert(kRA == 2 && kAR == 2 * kW2 && kNH2 <= kNT2, "row split assumed below");
 static_assert(kL2 % kRing == 0 && kL2 % 2 == 0, "ring lengths must divide the unroll");
+
+// Rows of the first-step region (index a, y = y0 - 4 + a) owned by wavefront
+// wv: a = 4 + wv (an output row), and a = 12 + wv for wv >= 8 (an output
+// row), else one of the halo rows 0-3, 28-31.  Each wavefront's second-step
+// rows are thus among its own first-step rows, so their u^{n+1} and phi^{n+1}
+// along z stay in its registers.
+__device__ __forceinline__ int region_row(int wv, int k) {
+  return k == 0 ? kR + wv : (wv >= 8 ? 12 + wv : (wv < 4 ? wv : kTY2 + wv));
+}
 
 // A source that falls in a tile's first-step region and chunk window: lane
 // (x - x0), y, z and its wavelet sample w[n].
@@ -61,8 +69,11 @@ constexpr int kMaxTileSrc = 32;
 struct Smem2 {
   float sa[2][kSPL];                 // staged u^n plane (double-buffered)
   float rb[kRing][kRPL];             // u^{n+1}, first-step region
-  float pb[kRing][kPPL];             // phi^{n+1}, output rows
-  float dump[kHPT2 * kNT2 - kNH2 + 64];
+  float f1[kRing][kTY2 * kTX];       // phi^{n+1}, output rows (each wavefront its own)
+  double ts[kAR][kTX];               // default profile: tx + ty of the region's points
+  double tz[kZT];                    // default profile: tz and dq_z of the window's planes
+  float dqz[kZT];
+  float dump[kNT2 - kNH2 + 64];
   TileSrc src[kMaxTileSrc];          // the tile's sources, in list order
   int nsrc;
 };
@@ -74,20 +85,6 @@ __device__ inline ChunkInfo chunk2_of(int ch, int nz, int w, int zc, bool damp) 
   return chunk_of(ch, nz, (damp && w > 0) ? w + kR : 0, zc, damp && w > 0);
 }
 
-#ifndef K2_CV
-#define K2_CV 1
-#endif
-__device__ __forceinline__ float vreg_copy(float x) {
-  float v;
-  asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
-  return v;
-}
-#if K2_CV
-#define K2_VREG(x) vreg_copy(x)
-#else
-#define K2_VREG(x) (x)
-#endif
-
 template <class S, int EM>
 __device__ __forceinline__ void s2_loop(const Sweep2Args& g, Smem2& sm, int x0, int y0, int zb,
                                         int ze) {
@@ -97,6 +94,7 @@ __device__ __forceinline__ void s2_loop(const Sweep2Args& g, Smem2& sm, int x0, 
   constexpr bool LAYER = EM != 0;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool out1 = wv >= 8;           // the second row is an output row too
   const int P = a.pitch;
   const int64_t Q = a.plane;
   const uint32_t pe = (uint32_t)Q * ES, p4 = (uint32_t)Q * 4u;
@@ -128,43 +126,30 @@ __device__ __forceinline__ void s2_loop(const Sweep2Args& g, Smem2& sm, int x0, 
   const bool ownx = lane >= kR && lane < kR + kOX2 && vx;
   const bool layx = x < w || x >= nx - w;
 
-  // first-step rows ya = y0 - 4 + 3 wv + r; second-step rows yb = y0 + 2 wv + r
-  uint32_t voa[kRA], voa4[kRA], eoa[kRA], sta[kRA];
-  bool va[kRA], lxa[kRA], owna[kRA];
-  int yra[kRA];
+  uint32_t vo[kRA], vo4[kRA], eo[kRA], sta[kRA], rbo[kRA];
+  bool va[kRA], lxa[kRA], own[kRA];
+  int yr[kRA];
 #pragma unroll
-  for (int r = 0; r < kRA; ++r) {
-    const int y = y0 - kR + kRA * wv + r;
-    yra[r] = y;
-    va[r] = vx && y >= 0 && y < ny;
-    lxa[r] = va[r] && (layx || y < w || y >= ny - w);
-    owna[r] = ownx && y >= y0 && y < y0 + kTY2 && y < ny;
+  for (int k = 0; k < kRA; ++k) {
+    const int ar = region_row(wv, k);
+    const int y = y0 - kR + ar;
+    yr[k] = y;
+    va[k] = vx && y >= 0 && y < ny;
+    lxa[k] = va[k] && (layx || y < w || y >= ny - w);
+    own[k] = ownx && (k == 0 || out1) && y < ny;
     const uint32_t o = poff(x, y);
-    voa[r] = o * ES;
-    voa4[r] = o * 4u;
-    sta[r] = (uint32_t)((kR + kRA * wv + r) * kSW + kR + lane);
+    vo[k] = o * ES;
+    vo4[k] = o * 4u;
+    sta[k] = (uint32_t)((kR + ar) * kSW + kR + lane);
+    rbo[k] = (uint32_t)(ar * kTX + lane);
   }
-  uint32_t vob[kRB], vob4[kRB];
-  bool vb[kRB], lxb[kRB];
-  int yrb[kRB];
-#pragma unroll
-  for (int r = 0; r < kRB; ++r) {
-    const int y = y0 + kRB * wv + r;
-    yrb[r] = y;
-    vb[r] = ownx && y < ny;
-    lxb[r] = vb[r] && (layx || y < w || y >= ny - w);
-    const uint32_t o = poff(x, y);
-    vob[r] = o * ES;
-    vob4[r] = o * 4u;
-  }
-  // staged halo: element h of the staged plane's frame (rows 0-3, 28-31 of 72
-  // columns, then columns 0-3, 68-71 of rows 4-27); threads beyond it write
+  // staged halo: element h of the staged plane's frame (rows 0-3, 36-39 of 72
+  // columns, then columns 0-3, 68-71 of rows 4-35); threads beyond it write
   // to a dump area
-  int hl[kHPT2];
-  uint32_t ho[kHPT2];
-#pragma unroll
-  for (int k = 0; k < kHPT2; ++k) {
-    const int h = threadIdx.x + k * kNT2;
+  int hl;
+  uint32_t ho;
+  {
+    const int h = threadIdx.x;
     int sr, sc;
     if (h < 2 * kR * kSW) {
       const int rr = h / kSW;
@@ -179,81 +164,60 @@ __device__ __forceinline__ void s2_loop(const Sweep2Args& g, Smem2& sm, int x0, 
       sr = -1;
       sc = h - kNH2;
     }
-    hl[k] = sr >= 0 ? sr * kSW + sc : -1 - sc;
-    ho[k] = poff(x0 - kR + sc, y0 - 2 * kR + max(sr, 0)) * ES;
+    hl = sr >= 0 ? sr * kSW + sc : -1 - sc;
+    ho = poff(x0 - kR + sc, y0 - 2 * kR + max(sr, 0)) * ES;
   }
 
-  // default profile tables (EM = 2)
-  double tsa[kRA], tsb[kRB];
-  float dqxa = 0.0f, dqya[kRA], dqyb[kRB];
-  const double* tzt = nullptr;
-  const float* dqzt = nullptr;
+  // default profile tables (EM = 2); tx + ty of the own points go to LDS
+  float dqx = 0.0f, dqy[kRA];
+  uint32_t tso[kRA];
+#pragma unroll
+  for (int k = 0; k < kRA; ++k) tso[k] = (uint32_t)(region_row(wv, k) * kTX + lane);
   if (EM == 2) {
     const double* tx = a.etab + 1;
     const double* ty = tx + nx + 2;
-    tzt = ty + ny + 2;
-    dqzt = a.etq + nx + ny;
     const int xc = min(max(x, 0), nx - 1);
-    dqxa = a.etq[xc];
+    dqx = a.etq[xc];
 #pragma unroll
-    for (int r = 0; r < kRA; ++r) {
-      const int yc = min(max(yra[r], 0), ny - 1);
-      tsa[r] = tx[xc] + ty[yc];
-      dqya[r] = a.etq[nx + yc];
-    }
-#pragma unroll
-    for (int r = 0; r < kRB; ++r) {
-      const int yc = min(max(yrb[r], 0), ny - 1);
-      tsb[r] = tx[xc] + ty[yc];
-      dqyb[r] = a.etq[nx + yc];
+    for (int k = 0; k < kRA; ++k) {
+      const int yc = min(max(yr[k], 0), ny - 1);
+      (&sm.ts[0][0])[tso[k]] = tx[xc] + ty[yc];
+      dqy[k] = a.etq[nx + yc];
     }
   }
 
-  float q[kL2][kRA];                    // u^n(za-4 .. za+5), first-step rows
-  float qb[kL2][kRB];                   // u^{n+1}, second-step rows
-  float pva[2][kRA], vva[2][kRA], pha[2][kRA];
-  float pub[2][kRB], vvb[2][kRB];
-  float hh[2][kHPT2];
-  double tza[2], tzb[2];
-  float dza[2], dzb[2];
+  float q[kL2][kRA];                    // u^n(za-4 .. za+5)
+  float q1[kL2][kRA];                   // u^{n+1}(za-9 .. za) of the own rows
+  float pva[2][kRA], vva[2][kRA], pha[2][kRA], vvb[kRA];
+  float hh[2];
+  uint32_t f1o[kRA];                    // own output row in the phi^{n+1} ring
+#pragma unroll
+  for (int k = 0; k < kRA; ++k) f1o[k] = (uint32_t)((region_row(wv, k) - kR) * kTX + lane);
 
   auto load_a = [&](int B, int z) {     // first-step operands of plane z
     const uint32_t k = wk(z);
 #pragma unroll
     for (int r = 0; r < kRA; ++r) {
-      pva[B][r] = S::bld(rp, voa[r], k * pe);
-      vva[B][r] = bld_f32(rv, voa4[r], k * p4);
-      if (LAYER) pha[B][r] = bld_f32(rph, eoa[r], k * p4);
+      pva[B][r] = S::bld(rp, vo[r], k * pe);
+      vva[B][r] = bld_f32(rv, vo4[r], k * p4);
+      if (LAYER) pha[B][r] = bld_f32(rph, eo[r], k * p4);
     }
-#pragma unroll
-    for (int kk = 0; kk < kHPT2; ++kk) hh[B][kk] = S::bld(ru, ho[kk], k * pe);
-    if (EM == 2) {
-      const int zc = min(max(z, 0), nz - 1);
-      tza[B] = tzt[zc];
-      dza[B] = dqzt[zc];
-    }
+    hh[B] = S::bld(ru, ho, k * pe);
   };
-  auto load_b = [&](int B, int z) {     // second-step operands of plane z
+  auto load_b = [&](int z) {            // second-step operand of plane z (vp)
     const uint32_t k = wk(z);
 #pragma unroll
-    for (int r = 0; r < kRB; ++r) {
-      pub[B][r] = S::bld(ru, vob[r], k * pe);
-      vvb[B][r] = bld_f32(rv, vob4[r], k * p4);
-    }
-    if (EM == 2) {
-      const int zc = min(max(z, 0), nz - 1);
-      tzb[B] = tzt[zc];
-      dzb[B] = dqzt[zc];
-    }
+    for (int r = 0; r < kRA; ++r) vvb[r] = bld_f32(rv, vo4[r], k * p4);
   };
 
   // phi^n offsets: layer points of the first-step region, out of range for
   // the others (z caps decided per plane in the loop)
-  auto set_eoa = [&](int z) {
+  auto set_eo = [&](int z) {
     const bool capz = z < w || z >= nz - w;
 #pragma unroll
-    for (int r = 0; r < kRA; ++r) eoa[r] = (va[r] && (lxa[r] || capz)) ? voa4[r] : kOOB;
+    for (int r = 0; r < kRA; ++r) eo[r] = (va[r] && (lxa[r] || capz)) ? vo4[r] : kOOB;
   };
+
   // the tile's sources, gathered once in list order (wave 0, 64 at a time):
   // the plane loop then tests LDS entries instead of reading the source
   // list from memory, whose waits would also drain the operand prefetch
@@ -280,54 +244,61 @@ __device__ __forceinline__ void s2_loop(const Sweep2Args& g, Smem2& sm, int x0, 
     }
     if (lane == 0) sm.nsrc = n;
   }
+  // z terms of the default profile for the window's planes (read per plane
+  // from LDS with a uniform address)
+  if (a.damping && a.etab) {
+    const double* tzt = a.etab + 1 + (nx + 2) + (ny + 2);
+    const float* dqzt = a.etq + nx + ny;
+    for (int i = threadIdx.x; i <= wz1 - wz0; i += kNT2) {
+      const int zc = min(max(wz0 + i, 0), nz - 1);
+      sm.tz[i] = tzt[zc];
+      sm.dqz[i] = dqzt[zc];
+    }
+  }
   __syncthreads();
   // (the host runs single steps instead when a tile would hold more; the
   // bound only keeps the reads inside the list)
   const int nts = min(__builtin_amdgcn_readfirstlane(sm.nsrc), kMaxTileSrc);
 
-  // the stencil weights in vector registers: this loop has more wave-uniform
-  // values than scalar registers, and a weight kept in a vector register
-  // costs the multiply-adds nothing
-  float cv[14];
-#pragma unroll
-  for (int m = 0; m < 14; ++m) cv[m] = K2_VREG(m < 13 ? a.c[m] : a.ce);
-
   const int za0 = zb - kR;
-  if (LAYER) set_eoa(za0);
+  if (LAYER) set_eo(za0);
 #pragma unroll
   for (int j = 0; j < 2 * kR + 1; ++j) {
     const uint32_t k = wk(za0 - kR + j);
 #pragma unroll
-    for (int r = 0; r < kRA; ++r) q[j][r] = S::bld(ru, voa[r], k * pe);
+    for (int r = 0; r < kRA; ++r) q[j][r] = S::bld(ru, vo[r], k * pe);
   }
   load_a(0, za0);
-  load_b(0, za0 - kR);
 
+  // Iteration za: stage u^n(za), one barrier, first step at za (into the
+  // LDS ring and the own registers), second step at za - 4 (x/y neighbours
+  // from the ring plane written 4 iterations ago, z neighbours from the own
+  // registers).  A ring slot is rewritten 5 iterations after it was written,
+  // after the barrier that follows its last read; a staged buffer 2
+  // iterations after, likewise.
   auto body = [&](auto SC, const int za) {
     constexpr int Sl = decltype(SC)::value;
     constexpr int B = Sl & 1, NB = B ^ 1;
     constexpr int RS = Sl % kRing;            // ring slot of plane za
     constexpr int RQ = (Sl + 1) % kRing;      // ring slot of plane za - 4
     const int zq = za - kR;
-    // requests for the next iteration: u^n(za+5), first-step operands of
-    // za+1, second-step operands of za-3 (all clamped to the window)
+    // requests: u^n(za+5) and the first-step operands of za+1 for the next
+    // iteration, vp of za-4 for this iteration's second step (all clamped
+    // to the window)
     {
       const uint32_t k5 = wk(za + kR + 1);
 #pragma unroll
-      for (int r = 0; r < kRA; ++r) q[(Sl + 2 * kR + 1) % kL2][r] = S::bld(ru, voa[r], k5 * pe);
-      if (LAYER) set_eoa(za + 1);
+      for (int r = 0; r < kRA; ++r) q[(Sl + 2 * kR + 1) % kL2][r] = S::bld(ru, vo[r], k5 * pe);
+      if (LAYER) set_eo(za + 1);
       load_a(NB, za + 1);
-      load_b(NB, zq + 1);
+      load_b(zq);
     }
     // stage u^n(za) with its halo
     float* s = sm.sa[B];
 #pragma unroll
     for (int r = 0; r < kRA; ++r) s[sta[r]] = q[(Sl + kR) % kL2][r];
-#pragma unroll
-    for (int kk = 0; kk < kHPT2; ++kk) {
-      if (hl[kk] >= 0) s[hl[kk]] = hh[B][kk];
-      else sm.dump[-1 - hl[kk]] = hh[B][kk];
-    }
+    if (hl >= 0) s[hl] = hh[B];
+    else sm.dump[-1 - hl] = hh[B];
     __syncthreads();
 
     // ---- first step: u^{n+1}, phi^{n+1} at plane za ----
@@ -340,24 +311,25 @@ __device__ __forceinline__ void s2_loop(const Sweep2Args& g, Smem2& sm, int x0, 
     for (int r = 0; r < kRA; ++r) {
       const float* row = s + sta[r];
       const float c = q[(Sl + kR) % kL2][r];
-      float lap = cv[0] * c;
+      float lap = a.c[0] * c;
 #pragma unroll
-      for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(cv[m], row[m] + row[-m], lap);
-#pragma unroll
-      for (int m = 1; m <= kR; ++m)
-        lap = __builtin_fmaf(cv[4 + m], row[m * kSW] + row[-m * kSW], lap);
+      for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(a.c[m], row[m] + row[-m], lap);
 #pragma unroll
       for (int m = 1; m <= kR; ++m)
-        lap = __builtin_fmaf(cv[8 + m], q[(Sl + kR + m) % kL2][r] + q[(Sl + kR - m) % kL2][r], lap);
-      lap = __builtin_fmaf(cv[13], c, lap);
+        lap = __builtin_fmaf(a.c[4 + m], row[m * kSW] + row[-m * kSW], lap);
+#pragma unroll
+      for (int m = 1; m <= kR; ++m)
+        lap = __builtin_fmaf(a.c[8 + m], q[(Sl + kR + m) % kL2][r] + q[(Sl + kR - m) % kL2][r], lap);
+      lap = __builtin_fmaf(a.ce, c, lap);
       nph[r] = 0.0f;
       lay[r] = false;
       if (LAYER) {
         lay[r] = va[r] && (lxa[r] || capza);
-        const float e = lay[r] ? (float)(a.dt * (tsa[r] + tza[B])) : 0.0f;
+        const uint32_t kz = wk(za);
+        const float e = lay[r] ? (float)(a.dt * ((&sm.ts[0][0])[tso[r]] + sm.tz[kz])) : 0.0f;
         res[r] = upd_layer(c, pva[B][r], vva[B][r], lap, e, pha[B][r]);
-        nph[r] = upd_phi(pha[B][r], e, dqxa, row[1] - row[-1], dqya[r], row[kSW] - row[-kSW], dza[B],
-                         q[(Sl + kR + 1) % kL2][r] - q[(Sl + kR - 1) % kL2][r]);
+        nph[r] = upd_phi(pha[B][r], e, dqx, row[1] - row[-1], dqy[r], row[kSW] - row[-kSW],
+                         sm.dqz[kz], q[(Sl + kR + 1) % kL2][r] - q[(Sl + kR - 1) % kL2][r]);
       } else {
         res[r] = upd_inner(c, pva[B][r], vva[B][r], lap);
       }
@@ -373,61 +345,55 @@ __device__ __forceinline__ void s2_loop(const Sweep2Args& g, Smem2& sm, int x0, 
 #pragma unroll
       for (int r = 0; r < kRA; ++r) {
         const float v = S::cvt(S::enc(__builtin_fmaf(vva[B][r], e.wq, res[r])));
-        res[r] = (lane == e.lane && yra[r] == e.y) ? v : res[r];
+        res[r] = (lane == e.lane && y0 - kR + region_row(wv, r) == e.y) ? v : res[r];
       }
     }
 #pragma unroll
     for (int r = 0; r < kRA; ++r) {
       const bool live = inz && va[r];
-      const float rv1 = live ? res[r] : 0.0f;
-      sm.rb[RS][(kRA * wv + r) * kTX + lane] = rv1;
-      S::bst(ro1, (ownz && owna[r]) ? voa[r] : kOOB, wk(za) * pe, rv1);
-      // phi^{n+1} of the output rows for the second step, which another
-      // wavefront may compute: written by every wavefront (zero where no
-      // layer point is), whichever loop it runs
-      {
-        const int orow = yra[r] - y0;
-        if (orow >= 0 && orow < kTY2) sm.pb[RS][orow * kTX + lane] = (LAYER && live && lay[r]) ? nph[r] : 0.0f;
-      }
+      const float u1 = live ? res[r] : 0.0f;
+      sm.rb[RS][rbo[r]] = u1;
+      S::bst(ro1, (ownz && own[r]) ? vo[r] : kOOB, wk(za) * pe, u1);
+      q1[Sl][r] = u1;
+      if (LAYER && (r == 0 || out1)) sm.f1[RS][f1o[r]] = (live && lay[r]) ? nph[r] : 0.0f;
     }
-    __syncthreads();
 
     // ---- second step: u^{n+2}, phi^{n+2} at plane zq = za - 4 ----
-#pragma unroll
-    for (int r = 0; r < kRB; ++r) qb[Sl][r] = sm.rb[RS][(kRB * wv + r + kR) * kTX + lane];
     if (zq >= zb && zq < ze) {
       const bool capzq = zq < w || zq >= nz - w;
+      const uint32_t kq = wk(zq);
       const float* rbq = sm.rb[RQ];
 #pragma unroll
-      for (int r = 0; r < kRB; ++r) {
-        const float* row = rbq + (kRB * wv + r + kR) * kTX + lane;
-        const float c = qb[(Sl + kL2 - kR) % kL2][r];
-        float lap = cv[0] * c;
+      for (int r = 0; r < kRA; ++r) {
+        if (r == 1 && !out1) break;
+        const float* row = rbq + rbo[r];
+        const float c = q1[(Sl + kL2 - kR) % kL2][r];
+        float lap = a.c[0] * c;
 #pragma unroll
-        for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(cv[m], row[m] + row[-m], lap);
-#pragma unroll
-        for (int m = 1; m <= kR; ++m)
-          lap = __builtin_fmaf(cv[4 + m], row[m * kTX] + row[-m * kTX], lap);
+        for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(a.c[m], row[m] + row[-m], lap);
 #pragma unroll
         for (int m = 1; m <= kR; ++m)
-          lap = __builtin_fmaf(cv[8 + m],
-                               qb[(Sl + kL2 - kR + m) % kL2][r] + qb[(Sl + kL2 - kR - m) % kL2][r], lap);
-        lap = __builtin_fmaf(cv[13], c, lap);
-        const uint32_t kq = wk(zq);
-        float res;
+          lap = __builtin_fmaf(a.c[4 + m], row[m * kTX] + row[-m * kTX], lap);
+#pragma unroll
+        for (int m = 1; m <= kR; ++m)
+          lap = __builtin_fmaf(a.c[8 + m],
+                               q1[(Sl + kL2 - kR + m) % kL2][r] + q1[(Sl + kL2 - kR - m) % kL2][r], lap);
+        lap = __builtin_fmaf(a.ce, c, lap);
+        const float un = q[Sl % kL2][r];       // u^n(zq), the second step's "previous" level
+        float res2;
         if (LAYER) {
-          const bool lay = vb[r] && (lxb[r] || capzq);
-          const float e = lay ? (float)(a.dt * (tsb[r] + tzb[B])) : 0.0f;
-          const float ph = sm.pb[RQ][(kRB * wv + r) * kTX + lane];
-          res = upd_layer(c, pub[B][r], vvb[B][r], lap, e, ph);
-          const float nph =
-              upd_phi(ph, e, dqxa, row[1] - row[-1], dqyb[r], row[kTX] - row[-kTX], dzb[B],
-                      qb[(Sl + kL2 - kR + 1) % kL2][r] - qb[(Sl + kL2 - kR - 1) % kL2][r]);
-          bst_f32(rpo, lay ? vob4[r] : kOOB, kq * p4, nph);
+          const bool lay2 = own[r] && (lxa[r] || capzq);
+          const float e = lay2 ? (float)(a.dt * ((&sm.ts[0][0])[tso[r]] + sm.tz[kq])) : 0.0f;
+          const float ph = sm.f1[RQ][f1o[r]];
+          res2 = upd_layer(c, un, vvb[r], lap, e, ph);
+          const float nph2 =
+              upd_phi(ph, e, dqx, row[1] - row[-1], dqy[r], row[kTX] - row[-kTX], sm.dqz[kq],
+                      q1[(Sl + kL2 - kR + 1) % kL2][r] - q1[(Sl + kL2 - kR - 1) % kL2][r]);
+          bst_f32(rpo, lay2 ? vo4[r] : kOOB, kq * p4, nph2);
         } else {
-          res = upd_inner(c, pub[B][r], vvb[B][r], lap);
+          res2 = upd_inner(c, un, vvb[r], lap);
         }
-        S::bst(ro2, vb[r] ? vob[r] : kOOB, kq * pe, res);
+        S::bst(ro2, own[r] ? vo[r] : kOOB, kq * pe, res2);
       }
     }
   };
@@ -444,8 +410,8 @@ __device__ __forceinline__ void s2_loop(const Sweep2Args& g, Smem2& sm, int x0, 
 }
 
 template <class S>
-__global__ __launch_bounds__(kNT2, 2) void k_sweep2(Sweep2Args g, int tiles_x, int tiles_y,
-                                                    int zchunk) {
+__global__ __launch_bounds__(kNT2) void k_sweep2(Sweep2Args g, int tiles_x, int tiles_y,
+                                                 int zchunk) {
   __shared__ Smem2 sm;
   const SweepArgs& a = g.s;
   const int nb = gridDim.x, bid = blockIdx.x;
@@ -460,14 +426,14 @@ __global__ __launch_bounds__(kNT2, 2) void k_sweep2(Sweep2Args g, int tiles_x, i
   const ChunkInfo c = chunk2_of(ch, a.nz, a.w, zchunk, damp);
   if (c.zb >= c.ze) return;
   // wavefront-uniform choice of the loop: any layer point among the
-  // wavefront's first- or second-step points, in any plane of the chunk
+  // wavefront's rows, in any plane of the chunk
   bool lay = false;
   if (damp) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int x = x0 + lane;
     const bool lx = x < a.w || x >= a.nx - a.w;
-    for (int r = 0; r < kRA + kRB; ++r) {
-      const int y = r < kRA ? y0 - kR + kRA * wv + r : y0 + kRB * wv + (r - kRA);
+    for (int k = 0; k < kRA; ++k) {
+      const int y = y0 - kR + region_row(wv, k);
       lay = lay || (x >= 0 && x < a.nx && y >= 0 && y < a.ny && (lx || y < a.w || y >= a.ny - a.w));
     }
     lay = lay || c.cap;
@@ -496,12 +462,12 @@ hipError_t sweep2_t(const Sweep2Args& g, int zchunk, hipStream_t st) {
 
 int stream2_zchunk_limit(int64_t plane) {
   const int64_t z = kWindowMax / (plane * 4) - 4 * kR;
-  return (int)std::min<int64_t>(z, 1 << 30);
+  return (int)std::min<int64_t>(z, kMaxZc2);
 }
 
 bool sweep2_sources_fit(const int32_t* ijk, int n) {
   // first-step region of tile (tx, ty): x in [56 tx - 4, 56 tx + 60),
-  // y in [16 ty - 4, 16 ty + 20); each point lies in at most 2 x 2 tiles
+  // y in [24 ty - 4, 24 ty + 28); each point lies in at most 2 x 2 tiles
   std::unordered_map<int64_t, int> count;
   for (int s = 0; s < n; ++s) {
     const int i = ijk[3 * s], j = ijk[3 * s + 1];
@@ -524,7 +490,7 @@ int auto_zchunk2(int nx, int ny, int nz) {
   const int64_t chunks = (4096 + tiles - 1) / tiles;
   int zc = (int)std::min<int64_t>(nz / 8, (nz + chunks - 1) / chunks);
   zc = std::max(zc, 64);
-  return std::min(zc, nz);
+  return std::min(std::min(zc, nz), kMaxZc2);
 }
 
 hipError_t launch_sweep2(const Sweep2Args& g, int storage, int zchunk, hipStream_t s) {

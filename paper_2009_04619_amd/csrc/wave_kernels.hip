@@ -72,7 +72,14 @@ struct Slots {
   int ls[RY];        // LDS index of the point in the staged plane
   bool valid[RY];    // inside the grid (else the clamped ghost row/column)
   bool lay[RY];      // a damping-layer point
+  bool phl[RY];      // phi is read and written back here: a layer point, or an
+                     // inner point sharing a 128-byte line with an x-wall one
 };
+
+// Read-only tables in the constant address space (scalar loads when the
+// index is wave-uniform).
+typedef const double __attribute__((address_space(4))) CDouble;
+typedef const float __attribute__((address_space(4))) CFloat;
 
 // The streaming loop over planes [zb, ze) for one wavefront's slots.
 // EM = 0: no layer point.  EM = 1, 2: the wavefront owns at least one layer
@@ -124,23 +131,29 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
   }
 #pragma unroll
   for (int k = 0; k < HPT; ++k) hoe[k] = ho[k] * ES;
-  uint32_t eo[RY];  // eta/phi lane offset; out of range for non-layer points
+  uint32_t eo[RY];  // eta lane offset; out of range for non-layer points
+  uint32_t fo[RY];  // phi lane offset; out of range where phi is not touched
   if (LAYER) {
 #pragma unroll
-    for (int r = 0; r < RY; ++r) eo[r] = sl.lay[r] ? vo4[r] : kOOB;
+    for (int r = 0; r < RY; ++r) {
+      eo[r] = sl.lay[r] ? vo4[r] : kOOB;
+      fo[r] = sl.phl[r] ? vo4[r] : kOOB;
+    }
   }
   // EM = 2: the z-independent part of the profile sum, tx + ty, and the x and
   // y difference products of the point; per plane tz(z) and dq_z(z), which
-  // are the same for every lane, travel in operand rings
+  // are the same for every lane, travel in operand rings (read through the
+  // constant address space, so they are scalar loads that do not queue
+  // behind the vector loads)
   double tsc[RY];
   float dqx[RY], dqy[RY];
-  const double* tzt = nullptr;
-  const float* dqzt = nullptr;
+  const CDouble* tzt = nullptr;
+  const CFloat* dqzt = nullptr;
   if (EM == 2) {
     const double* tx = a.etab + 1;
     const double* ty = tx + a.nx + 2;
-    tzt = ty + a.ny + 2;
-    dqzt = a.etq + a.nx + a.ny;
+    tzt = (const CDouble*)(ty + a.ny + 2);
+    dqzt = (const CFloat*)(a.etq + a.nx + a.ny);
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       const int x = sl.x[r], y = sl.y[r];
@@ -182,7 +195,7 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
     for (int k = 0; k < HPT; ++k) hh[j][k] = S::bld(ru, hoe[k], se);
     if (LAYER) {
 #pragma unroll
-      for (int r = 0; r < RY; ++r) ph[j][r] = bld1_f32(rph, eo[r], s4);
+      for (int r = 0; r < RY; ++r) ph[j][r] = bld1_f32(rph, fo[r], s4);
     }
     if (EM == 2) {
       const int zt = zb - kR + (int)kp;
@@ -231,7 +244,7 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
       for (int k = 0; k < HPT; ++k) hh[BP][k] = S::bld(ru, hoe[k], se);
       if (LAYER) {
 #pragma unroll
-        for (int r = 0; r < RY; ++r) ph[BP][r] = bld1_f32(rph, eo[r], s4);
+        for (int r = 0; r < RY; ++r) ph[BP][r] = bld1_f32(rph, fo[r], s4);
       }
       if (EM == 2) {
         const int zt = zb - kR + (int)kp;
@@ -291,12 +304,15 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
           gy = dqy[r];
           gz = dzr[B];
         }
-        res = upd_layer(c, pu, vp, lap, e, ph[B][r]);
-        const float nph = upd_phi(ph[B][r], e, gx, row[1] - row[-1], gy, row[LW] - row[-LW], gz,
+        // phi of a point outside the layer counts as 0 (the loaded value is
+        // only written back)
+        const float phv = sl.lay[r] ? ph[B][r] : 0.0f;
+        res = upd_layer(c, pu, vp, lap, e, phv);
+        const float nph = upd_phi(phv, e, gx, row[1] - row[-1], gy, row[LW] - row[-LW], gz,
                                   q[(Sl + kR + 1) % L][r] - q[(Sl + kR - 1) % L][r]);
-        // stored for every point; points outside the layer have an out-of-
-        // range offset, so their store is dropped
-        bst_f32(rph, eo[r], sz4, nph);
+        // stored for every point; points where phi is not touched have an
+        // out-of-range offset, so their store is dropped
+        bst_f32(rph, fo[r], sz4, sl.lay[r] ? nph : ph[B][r]);
       } else {
         res = upd_inner(c, pu, vp, lap);
       }
@@ -352,6 +368,11 @@ __device__ __forceinline__ void stream_tile(const SweepArgs& a,
     sl.ls[r] = (kR + row) * LW + kR + col;
     sl.lay[r] = damp && sl.valid[r] &&
                 (cap || y < a.w || y >= a.ny - a.w || x < a.w || x >= a.nx - a.w);
+    // the x walls' phi rows are widened to whole 128-byte lines (32 floats
+    // from x = 0, which is line-aligned): full-line writes instead of
+    // partial ones, which the memory would have to merge
+    sl.phl[r] = sl.lay[r] || (damp && sl.valid[r] && a.w > 0 &&
+                              (x < ((a.w + 31) & ~31) || x >= ((a.nx - a.w) & ~31)));
     any_lay = any_lay || sl.lay[r];
   }
 

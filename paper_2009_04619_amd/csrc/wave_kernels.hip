@@ -427,31 +427,23 @@ __global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) 
   constexpr int LSZ = (TY + 2 * kR) * (kTX + 2 * kR) + 64;  // + a dump row
   __shared__ float sm[2][LSZ];
 
-  // XCD-aware tile order: dispatch sends block b to XCD b % 8.
-  const int nb = gridDim.x, bid = blockIdx.x;
+  // XCD-aware tile order: dispatch sends block b to XCD b % 8.  The tile
+  // rows are padded to 8 slabs of sh = ceil(tiles_y / 8) rows (workgroups
+  // of padding rows exit at once), so every XCD gets the same number of
+  // workgroups.  Each XCD owns a slab of tile rows for every z chunk and
+  // walks it chunk by chunk: the tiles it runs at once are x and y
+  // neighbours, so halos come from its L2.  The slab an XCD owns moves on
+  // by 3 (coprime to 8) from one chunk to the next, so the slabs holding the
+  // y walls of the damping layer, which cost more, are spread over all XCDs
+  // instead of loading the first and the last.
+  const int bid = blockIdx.x;
   const int xcd = bid & 7, slot = bid >> 3;
-  int tx, ty, ch;
-  if ((tiles_y & 7) == 0) {
-    // each XCD owns a slab of tile rows for every z chunk and walks it chunk
-    // by chunk: the tiles it runs at once are x and y neighbours, and the
-    // planes a chunk shares with the one below were read just before, so
-    // halos and chunk warm-ups come from its L2 rather than HBM (the
-    // workgroup count is tiles_x * tiles_y * chunks, a multiple of 8, so
-    // every XCD gets the same share)
-    const int sh = tiles_y >> 3;
-    tx = slot % tiles_x;
-    const int t2 = slot / tiles_x;
-    ty = xcd * sh + t2 % sh;
-    ch = t2 / sh;
-  } else {
-    // each XCD gets a contiguous range of logical tiles
-    const int per = nb >> 3, rem = nb & 7;
-    const int logical = (xcd < rem) ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
-    tx = logical % tiles_x;
-    const int t2 = logical / tiles_x;
-    ty = t2 % tiles_y;
-    ch = t2 / tiles_y;
-  }
+  const int sh = (tiles_y + 7) >> 3;
+  const int tx = slot % tiles_x;
+  const int t2 = slot / tiles_x;
+  const int ch = t2 / sh;
+  const int ty = ((xcd + 3 * ch) & 7) * sh + t2 % sh;
+  if (ty >= tiles_y) return;
   const int x0 = tx * kTX, y0 = ty * TY;
   const bool damp = a.damping != 0;
   const ChunkInfo c = chunk_of(ch, a.nz, a.w, zchunk, damp);
@@ -663,7 +655,8 @@ hipError_t sweep_stream_t(const SweepArgs& a, int zchunk, hipStream_t st) {
   const int tiles_y = (a.ny + TY - 1) / TY;
   if (zchunk > stream_zchunk_limit(a.plane)) return hipErrorInvalidValue;
   const int chunks = chunk_count(a.nz, a.w, zchunk, a.damping != 0);
-  const int64_t blocks = (int64_t)tiles_x * tiles_y * chunks;
+  // tile rows padded to a multiple of 8 (see k_sweep_stream)
+  const int64_t blocks = (int64_t)tiles_x * 8 * ((tiles_y + 7) / 8) * chunks;
   if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_sweep_stream<S, RY, NW>), dim3((unsigned)blocks), dim3(64 * NW), 0, st, a,
                      tiles_x, tiles_y, zchunk);

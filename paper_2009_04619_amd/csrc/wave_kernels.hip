@@ -452,10 +452,9 @@ __global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) 
 }
 
 // ---- many shots per launch ---------------------------------------------------
-// One workgroup grid covers every member of a batch: the workgroup index (after
-// the same XCD-aware remap) is located in the members' block ranges, the
-// member's parity picks u^n and u^{n-1}, and the tile is swept exactly as in
-// a single-shot launch.  Members that have taken their steps for this run exit
+// One workgroup grid covers every member of a batch: the workgroup index is
+// located in the members' block ranges, the member's parity picks u^n and
+// u^{n-1}, and the tile is swept exactly as in a single-shot launch.  Members that have taken their steps for this run exit
 // at once, so a captured sequence of launches stays valid as members finish.
 template <class S, int RY, int NW>
 __global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) void k_sweep_batch(
@@ -463,14 +462,12 @@ __global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) 
   constexpr int TY = RY * NW;
   constexpr int LSZ = (TY + 2 * kR) * (kTX + 2 * kR) + 64;
   __shared__ float sm[2][LSZ];
-  const int nb = gridDim.x, bid = blockIdx.x;
-  const int per = nb >> 3, rem = nb & 7, xcd = bid & 7, slot = bid >> 3;
-  const int64_t logical = (xcd < rem) ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
-  // member of this workgroup: last member whose first block is <= logical
+  const int64_t bid = blockIdx.x;
+  // member of this workgroup: last member whose first block is <= bid
   int lo = 0, hi = nshots - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (shots[mid].block_begin <= logical) lo = mid; else hi = mid - 1;
+    if (shots[mid].block_begin <= bid) lo = mid; else hi = mid - 1;
   }
   const BatchShot& b = shots[lo];
   const BatchState st = state[lo];
@@ -478,11 +475,18 @@ __global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) 
   SweepArgs a = b.sa;
   a.cur = b.u[st.cur];
   a.nxt = b.u[st.cur ^ 1];
-  const int64_t local = logical - b.block_begin;
-  const int tx = (int)(local % b.tiles_x);
-  const int64_t t2 = local / b.tiles_x;
-  const int ty = (int)(t2 % b.tiles_y);
-  const int ch = (int)(t2 / b.tiles_y);
+  // each member's range starts at a multiple of 8 blocks, so the member-local
+  // index keeps the XCD in its low 3 bits; tiles follow k_sweep_stream's
+  // order (padded slabs of tile rows, rotated over the XCDs per z chunk)
+  const int64_t local = bid - b.block_begin;
+  const int xcd = (int)(local & 7);
+  const int64_t slot = local >> 3;
+  const int sh = (b.tiles_y + 7) >> 3;
+  const int tx = (int)(slot % b.tiles_x);
+  const int64_t t2 = slot / b.tiles_x;
+  const int ch = (int)(t2 / sh);
+  const int ty = ((xcd + 3 * ch) & 7) * sh + (int)(t2 % sh);
+  if (ty >= b.tiles_y) return;
   const int x0 = tx * kTX, y0 = ty * TY;
   const bool damp = a.damping != 0;
   const ChunkInfo c = chunk_of(ch, a.nz, a.w, b.zchunk, damp);

@@ -494,7 +494,8 @@ void batch_layout(wave_batch* b) {
     e.zchunk = stream_zchunk(c, b->ry, b->nw, c->zchunk);
     const int chunks = wave::stream_chunk_count(c->L.nz, c->d.w, e.zchunk, c->damp);
     e.block_begin = begin;
-    begin += (int64_t)e.tiles_x * e.tiles_y * chunks;
+    // tile rows padded to 8 slabs: a multiple of 8 blocks per member
+    begin += (int64_t)e.tiles_x * 8 * ((e.tiles_y + 7) / 8) * chunks;
     b->prefix_blocks.push_back(begin);
     e.target = 0;
     e.inj = inject_args(c);

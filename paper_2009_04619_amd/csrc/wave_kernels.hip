@@ -76,6 +76,9 @@ struct Slots {
                      // inner point sharing a 128-byte line with an x-wall one
 };
 
+// Halo offset marking a ghost cell (never a real in-plane offset).
+constexpr uint32_t kHaloGhost = 0xffffffffu;
+
 // Read-only tables in the constant address space (scalar loads when the
 // index is wave-uniform).
 typedef const double __attribute__((address_space(4))) CDouble;
@@ -116,7 +119,9 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
   const int64_t w0 = (int64_t)(zb - kR) * Q - (int64_t)kR * P;
   const uint32_t wlen = (uint32_t)(ze - zb + 2 * kR) * p4;
   const int zlast = ze - zb + kR - 1;  // window index of plane ze-1
-  const auto ru = rsrc_at(static_cast<const T*>(a.cur) + w0, 0xffffffffu);
+  // u^n: limited to the window, so a halo load of a ghost cell (kOOB)
+  // fetches nothing and reads 0, the ghost's value
+  const auto ru = rsrc_at(static_cast<const T*>(a.cur) + w0, (uint32_t)(ze - zb + 2 * kR) * pe);
   const auto rn = rsrc_at(static_cast<T*>(a.nxt) + w0, 0xffffffffu);
   const auto rv = rsrc_at(a.vp + w0, 0xffffffffu);
   const auto rph = rsrc_at(LAYER ? (const void*)(a.phi + w0) : nullptr, LAYER ? wlen : 0u);
@@ -130,7 +135,7 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
     vo4[r] = sl.ro[r] * 4u;
   }
 #pragma unroll
-  for (int k = 0; k < HPT; ++k) hoe[k] = ho[k] * ES;
+  for (int k = 0; k < HPT; ++k) hoe[k] = ho[k] == kHaloGhost ? kOOB : ho[k] * ES;
   uint32_t eo[RY];  // eta lane offset; out of range for non-layer points
   uint32_t fo[RY];  // phi lane offset; out of range where phi is not touched
   if (LAYER) {
@@ -402,9 +407,12 @@ __device__ __forceinline__ void stream_tile(const SweepArgs& a,
       gy = ylast;
       gx = x0 + lane;
     }
+    // ghost cells (outside the grid) and the dump row are zero or unused:
+    // no load (a line of row padding would be fetched for 16 bytes)
+    const bool ghost = h >= NHALO || gx < 0 || gx >= a.nx || gy < 0 || gy >= a.ny;
     gy = min(gy, ylast);
     hl[k] = rl * LW + cl;
-    ho[k] = (uint32_t)((gy + kR) * P + gx);
+    ho[k] = ghost ? kHaloGhost : (uint32_t)((gy + kR) * P + gx);
   }
 
   // wavefront-uniform choice of the loop

@@ -62,9 +62,11 @@ def describe(cfg) -> str:
     return f"stream rows_per_wave={ry} waves_per_group={nw} zchunk={zc}"
 
 
-def measured_traffic(workload: str, launches_bytes: float, variant: int = 1):
+def measured_traffic(workload: str, launches_bytes: float, variant: int = 1, tile=None):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source; else None."""
+    if it was taken on the current kernel source; else None.  `tile`
+    (rows_per_wave, waves_per_group) selects the kernel instance the run used
+    when the summary lists it."""
     name, prefix, _ = KERNELS[variant]
     p = os.path.join(ROOT, "profiles", f"traffic_{prefix}_{workload}.json")
     if not os.path.exists(p):
@@ -75,6 +77,9 @@ def measured_traffic(workload: str, launches_bytes: float, variant: int = 1):
         return None
     if t.get("kernel_sha") != kernel_source_sha(variant):
         return None
+    inst = t.get("instances", {}).get(f"{tile[0]},{tile[1]}") if tile else None
+    if inst:
+        return float(inst["hbm_bytes_per_launch"])
     return float(t["hbm_bytes_per_launch"])
 
 
@@ -343,7 +348,8 @@ def main():
     achieved = alg_bytes / (avg_ms / 1e3) / 1e9
     workload = f"{args.n}cube_w{args.w}_{args.storage}"
     variant = cfg[0] if cfg[0] in KERNELS else 1
-    traffic = measured_traffic(workload, alg_bytes, variant)
+    traffic = measured_traffic(workload, alg_bytes, variant,
+                               tile=(cfg[1], cfg[2]) if variant == 1 else None)
     log(f"[bench] sweep kernel avg {avg_ms:.4f} ms over {launches} launches, "
         f"{alg_bytes / pts:.2f} B/pt algorithmic -> {achieved:.0f} GB/s")
     r0 = time.perf_counter()

@@ -186,14 +186,54 @@ def test_energy_conserved_with_damping_off(W):
     sh.close()
 
 
+def random_state(shot, seed):
+    """u^n, u^{n-1} random everywhere and phi random in the layer (zero
+    elsewhere): every point of the grid then carries a nonzero value, so a
+    tile that is skipped, doubled or misplaced shows up."""
+    rng = np.random.default_rng(seed)
+    shape = (shot.nz, shot.ny, shot.nx)
+    u = (rng.standard_normal(shape, dtype=np.float32) * np.float32(1e-2))
+    up = (rng.standard_normal(shape, dtype=np.float32) * np.float32(1e-2))
+    w = shot.w
+    k = np.arange(shot.nz)[:, None, None]
+    j = np.arange(shot.ny)[None, :, None]
+    i = np.arange(shot.nx)[None, None, :]
+    lay = ((i < w) | (i >= shot.nx - w) | (j < w) | (j >= shot.ny - w) | (k < w) | (k >= shot.nz - w))
+    phi = np.where(lay, rng.standard_normal(shape, dtype=np.float32) * np.float32(1e-3),
+                   np.float32(0)).astype(np.float32)
+    return {"u": u, "u_prev": up, "phi": phi}
+
+
 def test_c2_full_size_few_steps_bitwise(W):
-    """512^3, 20-cell layer, layered model: the benchmark's launch
-    configuration, 3 steps against the float32 oracle on every point."""
+    """512^3, 20-cell layer, layered model: every launch configuration the
+    benchmark's tuner can pick (tile instance and z-chunk length), 3 steps
+    against the float32 oracle on every point."""
     shot = synth.config_c2(steps=3)
-    say("case c2 512^3 3 steps")
-    g = gpu_run(W, shot, 3)
-    o = oracle.run_shot(shot, precision="f32")
-    assert_same(g, o, "c2 512^3")
+    st = random_state(shot, 11)
+    o = oracle.run_shot(shot, precision="f32", state=st)
+    for k in [(1, 1, 16, 64), (1, 1, 16, 128), (1, 1, 8, 32), (1, 2, 8, 64), (1, 2, 4, 32)]:
+        say(f"case c2 512^3 3 steps kernel {k}")
+        assert_same(gpu_run(W, shot, 3, kernel=k, state=st), o, f"c2 512^3 {k}")
+
+
+def test_c3_size_few_steps_bitwise(W):
+    """1024^3 with a 32-cell layer (the large-domain configuration's grid and
+    layer; constant velocity so that the model is quick to build), from a
+    random state: 2 steps of the default launch against the float32 oracle
+    on every point."""
+    n, w = 1024, 32
+    vel = synth.constant_velocity(n, n, n, 3000.0)
+    dt = synth._dt_for(3000.0)
+    c = n // 2
+    shot = synth.Shot("c3_size", n, n, n, w, synth.H, synth.H, synth.H, dt, vel, 2,
+                      src=[(c, c, w + 5), (w + 2, 9, n - 3)],
+                      wavelet=np.stack([synth.ricker(2, dt, t0=0.0), synth.ricker(2, dt, t0=0.0)]),
+                      rec=synth.receiver_line(n, c, w + 5), seed=0)
+    say("case c3-size 1024^3 2 steps")
+    st = random_state(shot, 12)
+    g = gpu_run(W, shot, 2, state=st)
+    o = oracle.run_shot(shot, precision="f32", state=st)
+    assert_same(g, o, "1024^3")
 
 
 def test_long_run_medium_grid_vs_oracles(W):

@@ -68,6 +68,8 @@ GRIDS = [  # nx, ny, nz, w, steps, storage, damping
     (130, 19, 22, 3, 9, "bf16", True),
     (65, 33, 17, 4, 8, "f16", True),
     (45, 70, 30, 6, 10, "f32", False),
+    (3, 2, 5, 1, 6, "f32", True),       # smaller than every tile and chunk
+    (1, 1, 1, 0, 4, "bf16", True),      # one point, no layer
 ]
 
 

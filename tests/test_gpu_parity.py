@@ -211,7 +211,7 @@ def test_c2_full_size_few_steps_bitwise(W):
     shot = synth.config_c2(steps=3)
     st = random_state(shot, 11)
     o = oracle.run_shot(shot, precision="f32", state=st)
-    for k in [(1, 1, 16, 64), (1, 1, 16, 128), (1, 1, 8, 32), (1, 2, 8, 64), (1, 2, 4, 32)]:
+    for k in [(1, 1, 16, 64), (1, 1, 8, 32), (1, 2, 8, 128), (1, 2, 4, 32)]:
         say(f"case c2 512^3 3 steps kernel {k}")
         assert_same(gpu_run(W, shot, 3, kernel=k, state=st), o, f"c2 512^3 {k}")
 
@@ -219,20 +219,23 @@ def test_c2_full_size_few_steps_bitwise(W):
 def test_c3_size_few_steps_bitwise(W):
     """1024^3 with a 32-cell layer (the large-domain configuration's grid and
     layer; constant velocity so that the model is quick to build), from a
-    random state: 2 steps of the default launch against the float32 oracle
+    random state: one step of the default launch against the float32 oracle
     on every point."""
     n, w = 1024, 32
     vel = synth.constant_velocity(n, n, n, 3000.0)
     dt = synth._dt_for(3000.0)
     c = n // 2
-    shot = synth.Shot("c3_size", n, n, n, w, synth.H, synth.H, synth.H, dt, vel, 2,
+    shot = synth.Shot("c3_size", n, n, n, w, synth.H, synth.H, synth.H, dt, vel, 1,
                       src=[(c, c, w + 5), (w + 2, 9, n - 3)],
-                      wavelet=np.stack([synth.ricker(2, dt, t0=0.0), synth.ricker(2, dt, t0=0.0)]),
+                      wavelet=np.stack([synth.ricker(1, dt, t0=0.0), synth.ricker(1, dt, t0=0.0)]),
                       rec=synth.receiver_line(n, c, w + 5), seed=0)
-    say("case c3-size 1024^3 2 steps")
+    say("case c3-size 1024^3 1 step: random state")
     st = random_state(shot, 12)
-    g = gpu_run(W, shot, 2, state=st)
-    o = oracle.run_shot(shot, precision="f32", state=st)
+    say("case c3-size 1024^3 1 step: GPU")
+    g = gpu_run(W, shot, 1, state=st)
+    say("case c3-size 1024^3 1 step: oracle")
+    o = oracle.run_shot(shot, steps=1, precision="f32", state=st)
+    say("case c3-size 1024^3 1 step: compare")
     assert_same(g, o, "1024^3")
 
 

@@ -38,7 +38,8 @@ KERNELS = {0: ("k_sweep_direct", "direct", ("wave_kernels.hip", "wave_direct.h",
            2: ("k_sweep2", "sweep2", ("wave_kernels2.hip", "wave_point.h")),
            3: ("k_sweep_gmem", "gmem", ("wave_shapes.hip", "wave_direct.h", "wave_point.h")),
            4: ("k_sweep_ring", "ring", ("wave_shapes.hip", "wave_direct.h", "wave_point.h")),
-           5: ("k_sweep_shift", "shift", ("wave_shapes.hip", "wave_direct.h", "wave_point.h"))}
+           5: ("k_sweep_shift", "shift", ("wave_shapes.hip", "wave_direct.h", "wave_point.h")),
+           6: ("k_sweep_pair", "pair", ("wave_kernels_pair.hip", "wave_point.h"))}
 
 
 def kernel_source_sha(variant: int = 1) -> str:
@@ -56,6 +57,8 @@ def describe(cfg) -> str:
         return "direct"
     if v == 3:
         return f"3-D tile {ry}x{nw}x{zc}, all operands from memory"
+    if v == 6:
+        return f"stream, two points per lane, 128x{nw} zchunk={zc}"
     if v in (4, 5):
         return f"2.5-D {'ring of 9 LDS planes' if v == 4 else 'LDS plane + shifted registers'} " \
                f"64x{nw} zchunk={zc}"

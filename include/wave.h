@@ -233,6 +233,12 @@ int wave_energy(wave_ctx *ctx, double *out);
 #define WAVE_KERNEL_SHIFT 5  /* 2.5-D: one staged plane in LDS for the x/y
                                 neighbours, the z neighbours in 9 registers
                                 shifted each plane; parameters as RING     */
+#define WAVE_KERNEL_PAIR 6   /* the streaming kernel with two x-adjacent
+                                points per lane (128 x ty tiles, paired
+                                loads and stores); rows_per_wave = 1,
+                                waves_per_group = ty in {8, 16}, zchunk as
+                                for WAVE_KERNEL_STREAM; not with an eta
+                                array (EINVAL)                            */
 
 /* Select the sweep kernel and its tile: rows_per_wave (RY) and
  * waves_per_group (NW) give a 64 x (RY*NW) xy tile; zchunk is the number of
@@ -253,8 +259,10 @@ int wave_set_kernel(wave_ctx *ctx, int32_t variant, int32_t rows_per_wave,
 /* Autotuner: advance the simulation by `trial_steps` real steps under each
  * compiled tile shape and a few z-chunk lengths, and, with WAVE_TWO_STEP,
  * under the two-step kernel with a few z-chunk lengths (trial_steps rounded
- * up to even there), then under four of the paper's other code shapes
- * (WAVE_KERNEL_GMEM 8x8x8 and 64x4x4, RING and SHIFT with 16 rows).  Every
+ * up to even there), under the two-points-per-lane kernel (both tile
+ * heights, two z-chunk lengths; not with an eta array), then under four of
+ * the paper's other code shapes (WAVE_KERNEL_GMEM 8x8x8 and 64x4x4, RING
+ * and SHIFT with 16 rows).  Every
  * candidate computes identical results, so the trials are ordinary steps of
  * the run.  Each is timed with HIP events; the fastest per step is kept (a
  * candidate later in the list must be at least 1.5 % faster to replace an

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libwave.so")
-SOURCES = ["wave_kernels.hip", "wave_kernels2.hip", "wave_shapes.hip", "wave_runtime.hip"]
+SOURCES = ["wave_kernels.hip", "wave_kernels2.hip", "wave_kernels_pair.hip", "wave_shapes.hip",
+           "wave_runtime.hip"]
 
 # -ffp-contract=off: the kernels fuse multiply-adds only where the source
 # says so (results must not depend on the compiler's choices);

@@ -157,6 +157,10 @@ hipError_t launch_sweep_gmem(const SweepArgs& a, int storage, int bx, int by, in
 hipError_t launch_sweep_25d(const SweepArgs& a, int storage, int shape, int ty, int zchunk,
                             hipStream_t s);
 int auto_zchunk25(int nx, int ny, int nz, int ty);
+// Streaming sweep with two x-adjacent points per lane (wave_kernels_pair.hip):
+// 128 x ty tiles, ty in {8, 16}; the default profile's tables only (no eta
+// array); zchunk <= stream_zchunk_limit(plane).
+hipError_t launch_sweep_pair(const SweepArgs& a, int storage, int ty, int zchunk, hipStream_t s);
 hipError_t launch_energy(const EnergyArgs& a, int storage, hipStream_t s);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 // Scatter a compact [nz][ny][nx] float field into a padded array whose

@@ -471,6 +471,18 @@ int stream_zchunk(const wave_ctx* c, int ry, int nw, int zchunk) {
   return std::min(zc, lim);
 }
 
+// z-chunk length of the pair kernel (128 x ty tiles): as stream_zchunk, the
+// automatic length chosen for the tile count of 128-wide tiles; 0 when the
+// context holds an eta array (the kernel reads the default profile's tables
+// only) or one plane is too large to stream.
+int pair_zchunk(const wave_ctx* c, int ty, int zchunk) {
+  if (eta_array(&c->d)) return 0;
+  const int lim = wave::stream_zchunk_limit(c->L.plane);
+  if (lim < 1) return 0;
+  const int zc = zchunk > 0 ? zchunk : wave::auto_zchunk((c->L.nx + 1) / 2, c->L.ny, c->L.nz, 1, ty);
+  return std::min(zc, lim);
+}
+
 void batch_drop_graphs(wave_batch* b) {
   for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.second);
   b->graphs.clear();
@@ -860,6 +872,7 @@ int wave_step(wave_ctx* c, int32_t n) {
   const int zc = stream_zchunk(c, c->ry, c->nw, c->zchunk);
   const bool direct = c->variant == WAVE_KERNEL_DIRECT || zc < 1;
   const bool shape25 = c->variant == WAVE_KERNEL_RING || c->variant == WAVE_KERNEL_SHIFT;
+  const int zcp = c->variant != WAVE_KERNEL_PAIR ? 0 : pair_zchunk(c, c->shp[1], c->shp[2]);
   const int zc25 = !shape25 ? 0
                    : c->shp[2] > 0 ? std::min(c->shp[2], c->L.nz)
                                    : wave::auto_zchunk25(c->L.nx, c->L.ny, c->L.nz, c->shp[1]);
@@ -869,6 +882,8 @@ int wave_step(wave_ctx* c, int32_t n) {
     if (shape25)
       return wave::launch_sweep_25d(s, c->d.storage, c->variant == WAVE_KERNEL_RING ? 0 : 1,
                                     c->shp[1], zc25, c->stream);
+    if (c->variant == WAVE_KERNEL_PAIR)
+      return wave::launch_sweep_pair(s, c->d.storage, c->shp[1], zcp, c->stream);
     return direct ? wave::launch_sweep_direct(s, c->d.storage, c->stream)
                   : wave::launch_sweep_stream(s, c->d.storage, c->ry, c->nw, zc, c->stream);
   };
@@ -1027,6 +1042,17 @@ int wave_set_kernel(wave_ctx* c, int32_t variant, int32_t ry, int32_t nw, int32_
     c->shp[2] = zchunk;
     return WAVE_OK;
   }
+  if (variant == WAVE_KERNEL_PAIR) {
+    if (ry != 1 || (nw != 8 && nw != 16)) return fail(WAVE_EINVAL, "pair kernel needs rows_per_wave 1, 8 or 16 rows");
+    if (zchunk < 0) return fail(WAVE_EINVAL, "zchunk < 0");
+    if (pair_zchunk(c, nw, zchunk) < 1)
+      return fail(WAVE_EINVAL, "pair kernel: no eta array, and planes small enough to stream");
+    c->variant = variant;
+    c->shp[0] = 1;
+    c->shp[1] = nw;
+    c->shp[2] = zchunk;
+    return WAVE_OK;
+  }
   if (variant == WAVE_KERNEL_RING || variant == WAVE_KERNEL_SHIFT) {
     if (ry != 1 || (nw != 8 && nw != 16)) return fail(WAVE_EINVAL, "2.5-D shape needs rows_per_wave 1, 8 or 16 rows");
     if (zchunk < 0) return fail(WAVE_EINVAL, "zchunk < 0");
@@ -1077,6 +1103,14 @@ int wave_tune(wave_ctx* c, int32_t trial_steps, int32_t chosen[4]) {
       if (zc >= 1) add({WAVE_KERNEL_STREAM2, c->ry, c->nw, zc});
     }
   }
+  // two points per lane, at the automatic and the doubled chunk length
+  for (int ty : {16, 8}) {
+    const int za = pair_zchunk(c, ty, 0);
+    if (za < 1) continue;
+    add({WAVE_KERNEL_PAIR, 1, ty, za});
+    const int z2 = pair_zchunk(c, ty, std::min(nz, 2 * za));
+    if (z2 != za) add({WAVE_KERNEL_PAIR, 1, ty, z2});
+  }
   // the paper's other code shapes, last (they must beat the streaming kernel
   // by the margin below to be picked)
   if (!cand.empty()) {
@@ -1103,7 +1137,8 @@ int wave_tune(wave_ctx* c, int32_t trial_steps, int32_t chosen[4]) {
   const int variant = c->variant, ry0 = c->ry, nw0 = c->nw, zc0 = c->zchunk, zc20 = c->zchunk2;
   const int shp0[3] = {c->shp[0], c->shp[1], c->shp[2]};
   auto is_shape = [](int v) {
-    return v == WAVE_KERNEL_GMEM || v == WAVE_KERNEL_RING || v == WAVE_KERNEL_SHIFT;
+    return v == WAVE_KERNEL_GMEM || v == WAVE_KERNEL_RING || v == WAVE_KERNEL_SHIFT ||
+           v == WAVE_KERNEL_PAIR;
   };
   float best = 0.0f;
   std::array<int, 4> pick = {variant, ry0, nw0, zc0};

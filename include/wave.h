@@ -338,13 +338,18 @@ int wave_batch_run(wave_batch *b, int32_t n);
 /* Steps ctx still has to take in this batch. */
 int wave_batch_remaining(const wave_batch *b, const wave_ctx *ctx, int32_t *remaining);
 
-/* Tile shape of the batch sweep (same combinations as wave_set_kernel) and
- * the number of steps captured into one graph (0 = plain launches). */
+/* Tile shape of the batch sweep (same combinations as wave_set_kernel, or
+ * rows_per_wave = 0 for the two-points-per-lane kernel with 128 x
+ * waves_per_group tiles, waves_per_group in {8, 16}; EINVAL while a member
+ * holds an eta array, and such a member cannot join then) and the number of
+ * steps captured into one graph (0 = plain launches). */
 int wave_batch_set_kernel(wave_batch *b, int32_t rows_per_wave, int32_t waves_per_group);
 int wave_batch_set_graph(wave_batch *b, int32_t steps_per_graph);
 
 /* Autotuner for a batch: runs trial_steps steps under each compiled tile
- * shape and keeps the fastest; *chosen = {rows_per_wave, waves_per_group}. */
+ * shape (and the two-points-per-lane tiles when no member holds an eta
+ * array) and keeps the fastest; *chosen = {rows_per_wave, waves_per_group}
+ * as wave_batch_set_kernel takes them. */
 int wave_batch_tune(wave_batch *b, int32_t trial_steps, int32_t chosen[2]);
 
 /* Wait for the batch's work, release it (members stay valid contexts). */

@@ -161,6 +161,9 @@ int auto_zchunk25(int nx, int ny, int nz, int ty);
 // 128 x ty tiles, ty in {8, 16}; the default profile's tables only (no eta
 // array); zchunk <= stream_zchunk_limit(plane).
 hipError_t launch_sweep_pair(const SweepArgs& a, int storage, int ty, int zchunk, hipStream_t s);
+// Batched form: the members' block ranges laid out for 128 x ty tiles.
+hipError_t launch_sweep_batch_pair(const BatchShot* shots, BatchState* state, int nshots,
+                                   int64_t total_blocks, int storage, int ty, hipStream_t s);
 hipError_t launch_energy(const EnergyArgs& a, int storage, hipStream_t s);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 // Scatter a compact [nz][ny][nx] float field into a padded array whose

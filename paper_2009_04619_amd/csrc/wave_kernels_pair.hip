@@ -276,33 +276,16 @@ __device__ __forceinline__ void pair_loop(const SweepArgs& a, float (*sm)[(TY + 
   }
 }
 
+// Sweep of the 128 x TY tile at (x0, y0) through planes [zb, ze); `cap`: the
+// chunk is a z cap of the damping layer.
 template <class S, int TY>
-__global__ __launch_bounds__(64 * TY) void k_sweep_pair(SweepArgs a, int tiles_x, int tiles_y,
-                                                      int zchunk) {
+__device__ __forceinline__ void pair_tile(const SweepArgs& a, float (*sm)[(TY + 2 * kR) * kPW + 128],
+                                          int x0, int y0, int zb, int ze, bool cap) {
   constexpr int LR = TY + 2 * kR;
   constexpr int NT = 64 * TY;
   constexpr int NHP = (2 * kR * kPX + 2 * kR * TY) / 2;
   constexpr int HPT = (NHP + NT - 1) / NT;
-  // staged plane plus a dump area of 128 floats for the threads without a
-  // halo pair
-  __shared__ __attribute__((aligned(16))) float sm[2][LR * kPW + 128];
-
-  // tile order as in k_sweep_stream: 8 slabs of tile rows rotating over the
-  // XCDs per z chunk
-  const int bid = blockIdx.x;
-  const int xcd = bid & 7, slot = bid >> 3;
-  const int sh = (tiles_y + 7) >> 3;
-  const int tx = slot % tiles_x;
-  const int t2 = slot / tiles_x;
-  const int ch = t2 / sh;
-  const int ty = ((xcd + 3 * ch) & 7) * sh + t2 % sh;
-  if (ty >= tiles_y) return;
-  const int x0 = tx * kPX, y0 = ty * TY;
   const bool damp = a.damping != 0;
-  const ChunkInfo c = chunk_of(ch, a.nz, a.w, zchunk, damp);
-  if (c.zb >= c.ze) return;
-  const bool cap = damp && c.cap;
-
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int P = a.pitch;
@@ -363,9 +346,69 @@ __global__ __launch_bounds__(64 * TY) void k_sweep_pair(SweepArgs a, int tiles_x
   }
 
   if (!__any(any_lay))
-    pair_loop<S, TY, 0>(a, sm, sl, hl, ho, c.zb, c.ze);
+    pair_loop<S, TY, 0>(a, sm, sl, hl, ho, zb, ze);
   else
-    pair_loop<S, TY, 2>(a, sm, sl, hl, ho, c.zb, c.ze);
+    pair_loop<S, TY, 2>(a, sm, sl, hl, ho, zb, ze);
+}
+
+
+template <class S, int TY>
+__global__ __launch_bounds__(64 * TY) void k_sweep_pair(SweepArgs a, int tiles_x, int tiles_y,
+                                                      int zchunk) {
+  constexpr int LR = TY + 2 * kR;
+  // staged plane plus a dump area of 128 floats for the threads without a
+  // halo pair
+  __shared__ __attribute__((aligned(16))) float sm[2][LR * kPW + 128];
+
+  // tile order as in k_sweep_stream: 8 slabs of tile rows rotating over the
+  // XCDs per z chunk
+  const int bid = blockIdx.x;
+  const int xcd = bid & 7, slot = bid >> 3;
+  const int sh = (tiles_y + 7) >> 3;
+  const int tx = slot % tiles_x;
+  const int t2 = slot / tiles_x;
+  const int ch = t2 / sh;
+  const int ty = ((xcd + 3 * ch) & 7) * sh + t2 % sh;
+  if (ty >= tiles_y) return;
+  const bool damp = a.damping != 0;
+  const ChunkInfo c = chunk_of(ch, a.nz, a.w, zchunk, damp);
+  if (c.zb >= c.ze) return;
+  pair_tile<S, TY>(a, sm, tx * kPX, ty * TY, c.zb, c.ze, damp && c.cap);
+}
+
+// Batch: one grid over the members' block ranges (each a multiple of 8
+// blocks, padded slabs of 128 x TY tiles), as k_sweep_batch.
+template <class S, int TY>
+__global__ __launch_bounds__(64 * TY) void k_sweep_batch_pair(const BatchShot* __restrict__ shots,
+                                                            const BatchState* __restrict__ state,
+                                                            int nshots) {
+  constexpr int LR = TY + 2 * kR;
+  __shared__ __attribute__((aligned(16))) float sm[2][LR * kPW + 128];
+  const int64_t bid = blockIdx.x;
+  int lo = 0, hi = nshots - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (shots[mid].block_begin <= bid) lo = mid; else hi = mid - 1;
+  }
+  const BatchShot& b = shots[lo];
+  const BatchState st = state[lo];
+  if (st.done >= b.target) return;
+  SweepArgs a = b.sa;
+  a.cur = b.u[st.cur];
+  a.nxt = b.u[st.cur ^ 1];
+  const int64_t local = bid - b.block_begin;
+  const int xcd = (int)(local & 7);
+  const int64_t slot = local >> 3;
+  const int sh = (b.tiles_y + 7) >> 3;
+  const int tx = (int)(slot % b.tiles_x);
+  const int64_t t2 = slot / b.tiles_x;
+  const int ch = (int)(t2 / sh);
+  const int ty = ((xcd + 3 * ch) & 7) * sh + (int)(t2 % sh);
+  if (ty >= b.tiles_y) return;
+  const bool damp = a.damping != 0;
+  const ChunkInfo c = chunk_of(ch, a.nz, a.w, b.zchunk, damp);
+  if (c.zb >= c.ze) return;
+  pair_tile<S, TY>(a, sm, tx * kPX, ty * TY, c.zb, c.ze, damp && c.cap);
 }
 
 template <class S, int TY>
@@ -389,6 +432,23 @@ hipError_t pair_s(const SweepArgs& a, int ty, int zchunk, hipStream_t st) {
 }
 
 }  // namespace
+
+hipError_t launch_sweep_batch_pair(const BatchShot* shots, BatchState* state, int nshots,
+                                   int64_t total_blocks, int storage, int ty, hipStream_t s) {
+  if (total_blocks <= 0 || total_blocks > 0x7fffffff || (ty != 8 && ty != 16))
+    return hipErrorInvalidValue;
+  const dim3 g((unsigned)total_blocks);
+#define WAVE_BATCH_PAIR(S_, T_)                                                                \
+  hipLaunchKernelGGL((k_sweep_batch_pair<S_, T_>), g, dim3(64 * T_), 0, s, shots, state, nshots); \
+  return hipGetLastError();
+  switch (storage) {
+    case 0: if (ty == 8) { WAVE_BATCH_PAIR(StF32, 8) } else { WAVE_BATCH_PAIR(StF32, 16) }
+    case 1: if (ty == 8) { WAVE_BATCH_PAIR(StBF16, 8) } else { WAVE_BATCH_PAIR(StBF16, 16) }
+    case 2: if (ty == 8) { WAVE_BATCH_PAIR(StF16, 8) } else { WAVE_BATCH_PAIR(StF16, 16) }
+  }
+#undef WAVE_BATCH_PAIR
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_sweep_pair(const SweepArgs& a, int storage, int ty, int zchunk, hipStream_t s) {
   if (a.damping && !a.etab) return hipErrorInvalidValue;   // eta arrays: not in this kernel

@@ -493,7 +493,9 @@ void batch_layout(wave_batch* b) {
   b->h_shots.resize(b->members.size());
   b->prefix_blocks.assign(1, 0);
   int64_t begin = 0;
-  const int ty = b->ry * b->nw;
+  // rows_per_wave 0: two points per lane, 128 x nw tiles
+  const bool pair = b->ry == 0;
+  const int ty = pair ? b->nw : b->ry * b->nw;
   for (size_t i = 0; i < b->members.size(); ++i) {
     wave_ctx* c = b->members[i];
     wave::BatchShot& e = b->h_shots[i];
@@ -501,9 +503,9 @@ void batch_layout(wave_batch* b) {
     e.sa = sweep_args(c);
     e.u[0] = c->u_origin(std::min(c->icur, c->iprev));
     e.u[1] = c->u_origin(std::max(c->icur, c->iprev));
-    e.tiles_x = (c->L.nx + wave::kTX - 1) / wave::kTX;
+    e.tiles_x = (c->L.nx + (pair ? 2 : 1) * wave::kTX - 1) / ((pair ? 2 : 1) * wave::kTX);
     e.tiles_y = (c->L.ny + ty - 1) / ty;
-    e.zchunk = stream_zchunk(c, b->ry, b->nw, c->zchunk);
+    e.zchunk = pair ? pair_zchunk(c, b->nw, c->zchunk) : stream_zchunk(c, b->ry, b->nw, c->zchunk);
     const int chunks = wave::stream_chunk_count(c->L.nz, c->d.w, e.zchunk, c->damp);
     e.block_begin = begin;
     // tile rows padded to 8 slabs: a multiple of 8 blocks per member
@@ -519,8 +521,11 @@ void batch_layout(wave_batch* b) {
 
 // One step of the first k members (those still taking steps in this run).
 hipError_t batch_launch_step(wave_batch* b, int k) {
-  hipError_t e = wave::launch_sweep_batch(b->d_shots, b->d_state, k, b->prefix_blocks[k],
-                                          b->storage, b->ry, b->nw, b->stream);
+  hipError_t e = b->ry == 0
+                     ? wave::launch_sweep_batch_pair(b->d_shots, b->d_state, k, b->prefix_blocks[k],
+                                                     b->storage, b->nw, b->stream)
+                     : wave::launch_sweep_batch(b->d_shots, b->d_state, k, b->prefix_blocks[k],
+                                                b->storage, b->ry, b->nw, b->stream);
   if (e != hipSuccess) return e;
   return wave::launch_inject_batch(b->d_shots, b->d_state, k, b->storage, b->stream);
 }
@@ -1330,6 +1335,8 @@ int wave_batch_add(wave_batch* b, wave_ctx* c, int32_t nsteps) {
   if (c->step + nsteps > 0x7fffffff) return fail(WAVE_EINVAL, "step counter overflow");
   if (wave::stream_zchunk_limit(c->L.plane) < 1)
     return fail(WAVE_EINVAL, "z planes too large for the batched streaming kernel");
+  if (b->ry == 0 && eta_array(&c->d))
+    return fail(WAVE_EINVAL, "the batch runs the two-points-per-lane kernel, which takes no eta array");
   // the batch's launches come after everything queued so far on the member's stream
   JOIN_CTX(c);
   if (c->stream != b->user_stream) {
@@ -1377,7 +1384,13 @@ int wave_batch_remaining(const wave_batch* b, const wave_ctx* c, int32_t* remain
 
 int wave_batch_set_kernel(wave_batch* b, int32_t ry, int32_t nw) {
   CHECK_BATCH(b);
-  if (!wave::stream_config_supported(ry, nw)) return fail(WAVE_EINVAL, "tile (rows_per_wave, waves) not compiled");
+  if (ry == 0) {   // two points per lane
+    if (nw != 8 && nw != 16) return fail(WAVE_EINVAL, "two points per lane: 8 or 16 rows");
+    for (wave_ctx* c : b->members)
+      if (eta_array(&c->d)) return fail(WAVE_EINVAL, "a member holds an eta array (two points per lane takes none)");
+  } else if (!wave::stream_config_supported(ry, nw)) {
+    return fail(WAVE_EINVAL, "tile (rows_per_wave, waves) not compiled");
+  }
   b->ry = ry;
   b->nw = nw;
   b->layout_dirty = true;
@@ -1500,9 +1513,19 @@ int wave_batch_tune(wave_batch* b, int32_t trial_steps, int32_t chosen[2]) {
   const int ry0 = b->ry, nw0 = b->nw;
   float best = 0.0f;
   int pr = ry0, pn = nw0;
-  for (int k = 0; k < nshape; ++k) {
-    b->ry = kShapes[k][0];
-    b->nw = kShapes[k][1];
+  // the compiled one-point tiles, then two points per lane (128 x 16, 128 x 8)
+  // when no member holds an eta array
+  std::vector<std::array<int, 2>> shapes;
+  for (int k = 0; k < nshape; ++k) shapes.push_back({kShapes[k][0], kShapes[k][1]});
+  bool pair_ok = true;
+  for (wave_ctx* c : b->members) pair_ok = pair_ok && !eta_array(&c->d);
+  if (pair_ok) {
+    shapes.push_back({0, 16});
+    shapes.push_back({0, 8});
+  }
+  for (const auto& sh : shapes) {
+    b->ry = sh[0];
+    b->nw = sh[1];
     b->layout_dirty = true;
     hipEvent_t e0, e1;
     BCHK(b, hipEventCreate(&e0), "hipEventCreate");
@@ -1522,8 +1545,8 @@ int wave_batch_tune(wave_batch* b, int32_t trial_steps, int32_t chosen[2]) {
     (void)hipEventDestroy(e1);
     if (best == 0.0f || ms < best * 0.985f) {   // as in wave_tune
       best = ms;
-      pr = kShapes[k][0];
-      pn = kShapes[k][1];
+      pr = sh[0];
+      pn = sh[1];
     }
   }
   b->ry = pr;

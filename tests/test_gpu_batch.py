@@ -225,3 +225,35 @@ def test_members_on_another_stream(W):
     b.close()
     for x in m:
         x.close()
+
+
+@pytest.mark.parametrize("storage,tile", [("bf16", (0, 8)), ("f32", (0, 16))])
+def test_batch_two_points_per_lane(W, storage, tile):
+    """The batch on the two-points-per-lane kernel (rows_per_wave 0): members
+    equal solo runs bit for bit, plain launches and captured blocks; the
+    mode refuses members with an eta array."""
+    shots = shots_for(SHAPES)
+    say(f"case batch two points per lane storage={storage} tile={tile}")
+    ref = [solo(W, s, storage) for s in shots]
+    b = W.Batch(storage=storage, max_shots=8)
+    assert W.wave_batch_set_kernel(b.b, 0, 12) == W.WAVE_EINVAL
+    b.set_kernel(*tile)
+    b.set_graph(4)
+    members = []
+    for s in shots:
+        sh = W.shot_from_synth(s, storage=storage)
+        b.add(sh, s.steps)
+        members.append(sh)
+    for n in (7, 1, 30):
+        b.run(n)
+    for q, (sh, r) in enumerate(zip(members, ref)):
+        same(read_all(W, sh), r, f"pair member {q}")
+    s0 = shots[0]
+    _, e32 = oracle.eta_default(s0.nx, s0.ny, s0.nz, s0.w, s0.dx, s0.dy, s0.dz, s0.dt,
+                                float(s0.vel.max()))
+    with_eta = W.shot_from_synth(s0, storage=storage, eta=e32)
+    assert W.wave_batch_add(b.b, with_eta.ctx, 5) == W.WAVE_EINVAL
+    with_eta.close()
+    b.close()
+    for sh in members:
+        sh.close()

@@ -87,14 +87,22 @@ class GpuExecutor(Executor):
     """Batches per storage type on the caller's stream; set-up and read-out
     of requests on a stream of their own, so that they overlap with the
     blocks the batches are running (the library orders the two with
-    events)."""
+    events).
 
-    def __init__(self, device="cuda:0", graph_steps=0, max_shots=128):
+    `tiles` gives each storage type's batch sweep tile as
+    wave_batch_set_kernel takes it; the defaults are what the batch tuner
+    picked for mixed 128-384^3 shots on MI355X (one point per lane, 64 x 8,
+    for float32; two points per lane, 128 x 8, for 16-bit storage)."""
+
+    TILES = {"f32": (1, 8), "bf16": (0, 8), "f16": (0, 8)}
+
+    def __init__(self, device="cuda:0", graph_steps=0, max_shots=128, tiles=None):
         import torch
         self.torch = torch
         self.device = device
         self.graph_steps = graph_steps
         self.max_shots = max_shots
+        self.tiles = dict(self.TILES, **(tiles or {}))
         self.batches: Dict[str, W.Batch] = {}
         self.shots: Dict[int, W.Shot] = {}
         self.run_stream = torch.cuda.current_stream(device)
@@ -113,6 +121,7 @@ class GpuExecutor(Executor):
             b = W.Batch(storage=storage, max_shots=self.max_shots, device=self.device,
                         stream=self.run_stream)
             b.set_graph(self.graph_steps)
+            b.set_kernel(*self.tiles[storage])
             self.batches[storage] = b
         return b
 

@@ -256,21 +256,21 @@ int wave_energy(wave_ctx *ctx, double *out);
 int wave_set_kernel(wave_ctx *ctx, int32_t variant, int32_t rows_per_wave,
                     int32_t waves_per_group, int32_t zchunk);
 
-/* Autotuner: advance the simulation by `trial_steps` real steps under each
- * compiled tile shape and a few z-chunk lengths, and, with WAVE_TWO_STEP,
- * under the two-step kernel with a few z-chunk lengths (trial_steps rounded
- * up to even there), under the two-points-per-lane kernel (both tile
- * heights, two z-chunk lengths; not with an eta array), then under four of
- * the paper's other code shapes (WAVE_KERNEL_GMEM 8x8x8 and 64x4x4, RING
- * and SHIFT with 16 rows).  Every
- * candidate computes identical results, so the trials are ordinary steps of
- * the run.  Each is timed with HIP events; the fastest per step is kept (a
- * candidate later in the list must be at least 1.5 % faster to replace an
- * earlier one, so near-ties pick stably).  *chosen (may be NULL) receives
- * the wave_set_kernel arguments {variant, rows_per_wave, waves_per_group,
- * zchunk} of the pick; {0, 0, 0, 0} when the planes are
- * too large to stream and the direct kernel is kept.  Synchronises.  EINVAL
- * if the steps would overflow the trace buffer. */
+/* Autotuner: advance the simulation by one untimed and `trial_steps` timed
+ * real steps under each compiled tile shape and a few z-chunk lengths, and,
+ * with WAVE_TWO_STEP, under the two-step kernel with a few z-chunk lengths
+ * (trial_steps rounded up to even there), under the two-points-per-lane
+ * kernel (both tile heights, two z-chunk lengths; not with an eta array),
+ * then under four of the paper's other code shapes (WAVE_KERNEL_GMEM 8x8x8
+ * and 64x4x4, RING and SHIFT with 16 rows).  Every candidate computes
+ * identical results, so the trials are ordinary steps of the run.  Each is
+ * timed with HIP events; the fastest per step is kept (a candidate later in
+ * the list must be at least 1.5 % faster to replace an earlier one, so
+ * near-ties pick stably).  *chosen (may be NULL) receives the
+ * wave_set_kernel arguments {variant, rows_per_wave, waves_per_group,
+ * zchunk} of the pick; {0, 0, 0, 0} when the planes are too large to stream
+ * and the direct kernel is kept.  Synchronises.  EINVAL if the steps would
+ * overflow the trace buffer. */
 int wave_tune(wave_ctx *ctx, int32_t trial_steps, int32_t chosen[4]);
 
 /* When on, wave_step brackets every sweep-kernel launch with HIP events on

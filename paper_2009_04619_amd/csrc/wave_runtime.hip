@@ -1132,7 +1132,9 @@ int wave_tune(wave_ctx* c, int32_t trial_steps, int32_t chosen[4]) {
   // a two-step candidate runs an even number of steps
   const int32_t trial2 = trial_steps + (trial_steps & 1);
   int64_t total = 0;
-  for (const auto& e : cand) total += e[0] == WAVE_KERNEL_STREAM2 ? trial2 : trial_steps;
+  // each candidate first takes one untimed step (the first launch after a
+  // kernel switch runs cold), then its timed trial
+  for (const auto& e : cand) total += 1 + (e[0] == WAVE_KERNEL_STREAM2 ? trial2 : trial_steps);
   if (c->nrec > 0 && (int64_t)c->trace_count + total > c->d.max_steps)
     return fail(WAVE_EINVAL, "tuning steps would overflow the trace buffer");
   if (c->step + total > 0x7fffffff) return fail(WAVE_EINVAL, "step counter overflow");
@@ -1158,6 +1160,8 @@ int wave_tune(wave_ctx* c, int32_t trial_steps, int32_t chosen[4]) {
       if (e[0] == WAVE_KERNEL_STREAM2) c->zchunk2 = e[3]; else c->zchunk = e[3];
     }
     const int32_t steps = e[0] == WAVE_KERNEL_STREAM2 ? trial2 : trial_steps;
+    rc = wave_step(c, 1);
+    if (rc != WAVE_OK) break;
     hipError_t he = hipEventRecord(e0, c->stream);
     if (he == hipSuccess) rc = wave_step(c, steps);
     if (he == hipSuccess && rc == WAVE_OK) he = hipEventRecord(e1, c->stream);

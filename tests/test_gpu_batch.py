@@ -178,24 +178,25 @@ def test_tuned_runs_stay_exact(W):
     """Tuning trials are ordinary steps: a tuned shot and a tuned batch end
     exactly where untuned runs end."""
     shots = shots_for(SHAPES[:3], seed0=400)
+    n = 100                           # room for every candidate's trial steps
     for s in shots:
-        s.steps = 60
-        s.wavelet = np.ascontiguousarray(np.pad(s.wavelet, ((0, 0), (0, 60))))[:, :60]
+        s.steps = n
+        s.wavelet = np.ascontiguousarray(np.pad(s.wavelet, ((0, 0), (0, n))))[:, :n]
     say("case tuned runs")
     ref = [solo(W, s) for s in shots]
     sh = W.shot_from_synth(shots[0])
-    cfg = sh.tune(2)                  # <= 12 candidates x 2 steps
-    assert len(cfg) == 4
-    sh.step(60 - sh.step_count)
+    cfg = sh.tune(2)                  # ~20 candidates x (1 + 2) steps
+    assert len(cfg) == 4 and sh.step_count < n
+    sh.step(n - sh.step_count)
     same(read_all(W, sh), ref[0], "tuned shot")
     sh.close()
     b = W.Batch(max_shots=4)
     m = [W.shot_from_synth(s) for s in shots]
     for s, x in zip(shots, m):
-        b.add(x, 60)
-    bc = b.tune(3)                    # 4 shapes x 3 steps
+        b.add(x, n)
+    bc = b.tune(3)                    # 6 shapes x 3 steps
     assert len(bc) == 2
-    b.run(100)
+    b.run(2 * n)
     for q in range(3):
         same(read_all(W, m[q]), ref[q], f"tuned batch member {q}")
     b.close()

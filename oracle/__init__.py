@@ -75,6 +75,8 @@ def _load():
         lib.ora_round_bf16.restype = C.c_float
         lib.ora_round_f16.argtypes = [C.c_float]
         lib.ora_round_f16.restype = C.c_float
+        lib.ora_round_array.argtypes = [P, C.c_longlong, i32]
+        lib.ora_round_array.restype = None
         lib.ora_run_f64.argtypes = [i32, i32, i32, i32, f64, f64, f64, P, P, P, f64,
                                     i32, P, P, i32, i32, P, P, i32, i32, P, P, P]
         lib.ora_run_f64.restype = i32
@@ -229,8 +231,8 @@ def run(nx, ny, nz, w, dx, dy, dz, dt, vel, steps, *,
         vpo, eo = vp64, e64
     elif precision == "f32":
         if storage != "f32" and state is not None:
-            r = np.vectorize(round_bf16 if storage == "bf16" else round_f16, otypes=[np.float32])
-            u, up = r(u), r(up)
+            for arr in (u, up):   # the state as stored (each element rounded)
+                lib.ora_round_array(_ptr(arr), arr.size, STORAGE[storage])
         rc = lib.ora_run_f32(nx, ny, nz, w, dx, dy, dz, _ptr(vp32), _ptr(e32), _ptr(etab), dt,
                              STORAGE[storage],
                              nsrc, _ptr(src_a), _ptr(wav), nsamp, nrec, _ptr(rec_a),

@@ -231,6 +231,14 @@ static inline float store16(float x, int storage)
     return x;
 }
 
+/* store16 over an array in place (storage 1 bf16, 2 binary16): the rounding
+ * of an initial state to the storage type, one element at a time. */
+void ora_round_array(float *a, long long n, int storage)
+{
+    #pragma omp parallel for schedule(static)
+    for (long long i = 0; i < n; ++i) a[i] = store16(a[i], storage);
+}
+
 /* ---- the recurrence ----------------------------------------------------- */
 
 typedef struct {

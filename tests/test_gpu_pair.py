@@ -88,3 +88,41 @@ def test_pair_refuses_eta_array_and_bad_tiles(W):
         assert W.wave_set_kernel(sh.ctx, *bad) == W.WAVE_EINVAL, bad
     assert W.wave_set_kernel(sh.ctx, W.WAVE_KERNEL_PAIR, 1, 8, 0) == W.WAVE_OK
     sh.close()
+
+
+def test_pair_full_size_bf16_bitwise(W):
+    """512^3, 20-cell layer, layered model, bf16 storage, from a random
+    state: the launches the benchmark's bf16 leg can pick (two points per
+    lane, both tile heights), 2 steps against the oracle's bf16 mode on
+    every point."""
+    shot = synth.config_c2(steps=2)
+    rng = np.random.default_rng(21)
+    shape = (shot.nz, shot.ny, shot.nx)
+    w = shot.w
+    k = np.arange(shot.nz)[:, None, None]
+    j = np.arange(shot.ny)[None, :, None]
+    i = np.arange(shot.nx)[None, None, :]
+    lay = (i < w) | (i >= shot.nx - w) | (j < w) | (j >= shot.ny - w) | (k < w) | (k >= shot.nz - w)
+    # u values representable in bf16 (the state is stored in the storage type)
+    def bf16(a):
+        b = a.astype(np.float32).view(np.uint32)
+        b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+        return b.view(np.float32)
+    st = {"u": bf16(rng.standard_normal(shape, dtype=np.float32) * np.float32(1e-2)),
+          "u_prev": bf16(rng.standard_normal(shape, dtype=np.float32) * np.float32(1e-2)),
+          "phi": np.where(lay, rng.standard_normal(shape, dtype=np.float32) * np.float32(1e-3),
+                          np.float32(0)).astype(np.float32)}
+    say("case pair 512^3 bf16: oracle")
+    o = oracle.run_shot(shot, precision="f32", storage="bf16", state=st)
+    for kern in [(6, 1, 8, 128), (6, 1, 16, 64)]:
+        say(f"case pair 512^3 bf16 kernel {kern}")
+        sh = W.shot_from_synth(shot, storage="bf16", max_steps=2)
+        sh.write(W.WAVE_FIELD_U, st["u"])
+        sh.write(W.WAVE_FIELD_UPREV, st["u_prev"])
+        sh.write(W.WAVE_FIELD_PHI, st["phi"])
+        sh.set_kernel(*kern)
+        sh.step(2)
+        g = dict(u=sh.read(W.WAVE_FIELD_U), u_prev=sh.read(W.WAVE_FIELD_UPREV),
+                 phi=sh.read(W.WAVE_FIELD_PHI), traces=sh.traces())
+        sh.close()
+        assert_same(g, o, f"pair 512^3 bf16 {kern}")

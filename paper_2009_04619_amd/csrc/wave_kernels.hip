@@ -25,7 +25,8 @@ __global__ __launch_bounds__(256) void k_sweep_direct(SweepArgs a) {
 
 // ---- variant 1: 2.5-D streaming ------------------------------------------------
 // A workgroup of NW wavefronts owns a 64 x TY xy tile (TY = RY * NW; each
-// wavefront owns RY rows, one x column per lane) and streams it through the
+// wavefront owns RY rows, one x column per lane, or, in a tile that holds an
+// x wall of the layer, 2 RY half rows of 32 columns) and streams it through the
 // planes [zb, ze) of one z chunk.  Per plane z:
 //  * the values u(z-4..z+4) of every owned column sit in registers, in a ring
 //    that also holds the kPD planes of u already requested beyond z+4;
@@ -360,11 +361,23 @@ __device__ __forceinline__ void stream_tile(const SweepArgs& a,
   const int ylast = a.ny + kR - 1;
   const bool damp = a.damping != 0;
 
+  // Lanes of a tile that holds an x wall of the layer are laid out as 32
+  // columns x 2 rows per wavefront: the first half of the wavefronts takes
+  // the tile's left 32 columns, the second half its right 32, so a wall of
+  // up to 32 cells lands in half the wavefronts and the other half run the
+  // inner loop (with 64 x 1 every wavefront of such a tile would take the
+  // layer loop).  The halves are the first and the last NW/2 wavefronts, so
+  // SIMDs that take a workgroup's wavefronts in turn get as many of either.
+  // Other tiles keep one row per wavefront.
+  const bool split = (NW % 2 == 0) && damp && !cap && a.w > 0 &&
+                     (x0 < a.w || x0 + kTX > a.nx - a.w);
+  const int hw = NW / 2;
   Slots<RY> sl;
   bool any_lay = false;
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    const int col = lane, row = wv * RY + r;
+    const int col = split ? (wv / hw) * 32 + (lane & 31) : lane;
+    const int row = split ? (wv % hw) * 2 * RY + 2 * r + (lane >> 5) : wv * RY + r;
     const int x = x0 + col, y = y0 + row;
     sl.x[r] = min(x, a.nx - 1);
     sl.y[r] = min(y, a.ny - 1);

@@ -10,7 +10,8 @@
 // matters where the one-point loop runs short of instruction issue rather
 // than of bandwidth (16-bit storage moves fewer bytes per instruction).
 //
-// Structure as in k_sweep_stream: a 128 x TY tile (one row per wavefront)
+// Structure as in k_sweep_stream: a 128 x TY tile (one row per wavefront, or
+// two half rows where the tile holds an x wall of the layer)
 // streamed through a z chunk, u(z-4..z+4) of the own pair in a register ring
 // with 3 more planes requested ahead, the centre plane and its 4-cell halo
 // staged in double-buffered LDS (one barrier per plane), operands of plane
@@ -291,15 +292,25 @@ __device__ __forceinline__ void pair_tile(const SweepArgs& a, float (*sm)[(TY + 
   const int P = a.pitch;
   const int ylast = a.ny + kR - 1;
 
+  // A tile that holds an x wall of the layer lays its lanes out as 64
+  // columns (32 pairs) x 2 rows per wavefront, the first TY/2 wavefronts on
+  // the left half of the tile and the others on the right half, so a wall of
+  // up to 64 cells lands in half the wavefronts and the rest run the inner
+  // loop; other tiles keep one 128-column row per wavefront.
+  const bool split = (TY % 2 == 0) && damp && !cap && a.w > 0 &&
+                     (x0 < a.w || x0 + kPX > a.nx - a.w);
+  constexpr int HW = TY / 2;
+  const int col = split ? (wv / HW) * (kPX / 2) + 2 * (lane & 31) : 2 * lane;
+  const int row = split ? (wv % HW) * 2 + (lane >> 5) : wv;
   PairSlot sl;
   bool any_lay = false;
   {
-    const int x = x0 + 2 * lane, y = y0 + wv;
+    const int x = x0 + col, y = y0 + row;
     sl.x = min(x, a.nx - 1);
     sl.y = min(y, a.ny - 1);
     sl.inrow = x + 1 < P;
     sl.ro = (uint32_t)((min(y, ylast) + kR) * P + min(x, P - 2));
-    sl.ls = (kR + wv) * kPW + kR + 2 * lane;
+    sl.ls = (kR + row) * kPW + kR + col;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int xi = x + i;

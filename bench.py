@@ -352,7 +352,7 @@ def main():
     workload = f"{args.n}cube_w{args.w}_{args.storage}"
     variant = cfg[0] if cfg[0] in KERNELS else 1
     traffic = measured_traffic(workload, alg_bytes, variant,
-                               tile=(cfg[1], cfg[2]) if variant == 1 else None)
+                               tile=(cfg[1], cfg[2]) if variant in (1, 6) else None)
     log(f"[bench] sweep kernel avg {avg_ms:.4f} ms over {launches} launches, "
         f"{alg_bytes / pts:.2f} B/pt algorithmic -> {achieved:.0f} GB/s")
     r0 = time.perf_counter()

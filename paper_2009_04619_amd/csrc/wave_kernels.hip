@@ -120,20 +120,24 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
   const int64_t w0 = (int64_t)(zb - kR) * Q - (int64_t)kR * P;
   const uint32_t wlen = (uint32_t)(ze - zb + 2 * kR) * p4;
   const int zlast = ze - zb + kR - 1;  // window index of plane ze-1
-  // u^n: limited to the window, so a halo load of a ghost cell (kOOB)
-  // fetches nothing and reads 0, the ghost's value
+  // every resource is limited to the window, so a load at kOOB (a ghost
+  // halo cell, a lane past the grid) fetches nothing and reads 0, the
+  // ghost's value, and a store there is dropped
   const auto ru = rsrc_at(static_cast<const T*>(a.cur) + w0, (uint32_t)(ze - zb + 2 * kR) * pe);
-  const auto rn = rsrc_at(static_cast<T*>(a.nxt) + w0, 0xffffffffu);
-  const auto rv = rsrc_at(a.vp + w0, 0xffffffffu);
+  const auto rn = rsrc_at(static_cast<T*>(a.nxt) + w0, (uint32_t)(ze - zb + 2 * kR) * pe);
+  const auto rv = rsrc_at(a.vp + w0, wlen);
   const auto rph = rsrc_at(LAYER ? (const void*)(a.phi + w0) : nullptr, LAYER ? wlen : 0u);
   const auto ret = rsrc_at(EARR ? (const void*)(a.eta + w0) : nullptr, EARR ? wlen : 0u);
 
-  uint32_t vo[RY], vo4[RY];  // lane byte offsets in a plane
+  // lane byte offsets in a plane; a lane past the grid (its column in the
+  // row padding, or its row clamped to the ghost row) reads zeros and
+  // stores nothing: padding and ghosts are zero from the set-up on
+  uint32_t vo[RY], vo4[RY];
   uint32_t hoe[HPT];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    vo[r] = sl.ro[r] * ES;
-    vo4[r] = sl.ro[r] * 4u;
+    vo[r] = sl.valid[r] ? sl.ro[r] * ES : kOOB;
+    vo4[r] = sl.valid[r] ? sl.ro[r] * 4u : kOOB;
   }
 #pragma unroll
   for (int k = 0; k < HPT; ++k) hoe[k] = ho[k] == kHaloGhost ? kOOB : ho[k] * ES;
@@ -322,9 +326,9 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
       } else {
         res = upd_inner(c, pu, vp, lap);
       }
-      // points past the grid (clamped to ghost cells) write zero there: no
-      // branch around the store
-      S::bst(rn, vo[r], sz, sl.valid[r] ? res : 0.0f);
+      // points past the grid have an out-of-range offset: no branch around
+      // the store
+      S::bst(rn, vo[r], sz, res);
     }
   };
 

@@ -138,9 +138,13 @@ __device__ __forceinline__ void pair_loop(const SweepArgs& a, float (*sm)[(TY + 
   const auto rv = rsrc_at(a.vp + w0, wlen);
   const auto rph = rsrc_at(LAYER ? (const void*)(a.phi + w0) : nullptr, LAYER ? wlen : 0u);
 
-  // a pair past the padded row (the last tile may reach beyond it) touches
-  // nothing: its offsets are out of range
-  const uint32_t vo = sl.inrow ? sl.ro * ES : kOOB, vo4 = sl.inrow ? sl.ro * 4u : kOOB;
+  // a pair past the grid (in the row padding, beyond the padded row, or on
+  // a row clamped to the ghost row) touches nothing: its offsets are out of
+  // range, so it reads zeros, the ghost values, and stores nothing (padding
+  // and ghosts stay as the set-up zeroed them).  A pair whose second point
+  // is the first ghost column still stores that point's 0.
+  const bool live = sl.inrow && sl.valid[0];
+  const uint32_t vo = live ? sl.ro * ES : kOOB, vo4 = live ? sl.ro * 4u : kOOB;
   uint32_t hoe[HPT];
 #pragma unroll
   for (int k = 0; k < HPT; ++k) hoe[k] = ho[k] == kPairGhost ? kOOB : ho[k] * ES;

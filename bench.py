@@ -292,8 +292,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "z-slab decomposition is a design, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no "
+              "multi-GPU path (a z-slab decomposition is described, not implemented)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

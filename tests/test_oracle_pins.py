@@ -154,6 +154,41 @@ def test_p3_nyquist_mode_growth(courant, grows):
         assert amp < 10.0
 
 
+def test_p3_layer_update_growth_factor_bound():
+    """Without the Laplacian the damped update of one point has the growth
+    factors lam of (1 + 2 eta) lam^2 - (2 + 2 eta - eta^2) lam + 1 = 0; a
+    root leaves the unit circle through -1 at eta = 2 + 2 sqrt(2)."""
+    bound = 2.0 + 2.0 * math.sqrt(2.0)
+    for eta, unstable in [(bound - 1e-6, False), (bound + 1e-6, True), (1.0, False), (8.0, True)]:
+        lam = np.roots([1.0 + 2.0 * eta, -(2.0 + 2.0 * eta - eta * eta), 1.0])
+        assert (np.abs(lam).max() > 1.0) == unstable, (eta, lam)
+    # at the bound -1 is a root exactly
+    assert abs((1 + 2 * bound) + (2 + 2 * bound - bound * bound) + 1) < 1e-12
+
+
+@pytest.mark.parametrize("w", [1, 2, 3, 4])
+def test_p3_thin_layers_amplify_where_eta_exceeds_the_bound(w):
+    """The oracle's layer update against that bound: the default profile's
+    largest eta (a corner cell, three axis terms) lies above 2 + 2 sqrt(2)
+    for 1- and 2-cell layers, and a random state then grows; from 3 cells
+    it lies below and the state stays bounded."""
+    n = 24
+    shot = synth.config_small_layered(n, n, n, w, 12, seed=5, nsrc=1)
+    e64, _ = oracle.eta_default(n, n, n, w, shot.dx, shot.dy, shot.dz, shot.dt,
+                                float(shot.vel.max()))
+    above = float(e64.max()) > 2.0 + 2.0 * math.sqrt(2.0)
+    assert above == (w <= 2)
+    rng = np.random.default_rng(9)
+    st = {"u": rng.standard_normal((n, n, n)) * 1e-2,
+          "u_prev": rng.standard_normal((n, n, n)) * 1e-2}
+    out = oracle.run_shot(shot, steps=12, precision="f64", state=st)
+    amp = float(np.abs(out["u"]).max())
+    if above:
+        assert amp > 10.0, amp
+    else:
+        assert amp < 1.0, amp
+
+
 # ---------------------------------------------------------------- P4 ------
 def test_p4_energy_conserved_with_damping_off():
     nx, ny, nz = 30, 26, 34

@@ -88,6 +88,16 @@ typedef struct wave_ctx wave_ctx;
  * and reduction tables).  Returns 0 if `d` is invalid. */
 size_t wave_bytes_required(const wave_desc *d);
 
+/* Admission of a request under a device-memory budget (serving; not in
+ * the paper).  *need_out = wave_bytes_required(d); *fits_now = 1 when that
+ * many bytes fit beside in_use_bytes (need + in_use <= budget_bytes), else
+ * 0.  Returns OK when the request fits the budget now or once enough of
+ * in_use_bytes is released, EBUDGET when it needs more than the whole
+ * budget (it can never be admitted), EINVAL for an invalid descriptor.
+ * Either pointer may be NULL. */
+int wave_admit(const wave_desc *d, size_t budget_bytes, size_t in_use_bytes, size_t *need_out,
+               int32_t *fits_now);
+
 /* The 13 float32 stencil weights of Eq. 3 used by the kernels:
  * out[0] = c_xyz, out[1..4] = c_x1..4, out[5..8] = c_y1..4,
  * out[9..12] = c_z1..4.  Weights are the standard 8th-order central
@@ -130,7 +140,14 @@ int wave_eta_default(const wave_desc *d, double vmax, float *out);
  *              vp and the padded layout) and waited for once before return.
  * Errors: EINVAL (descriptor, pointers, alignment, non-finite input, eta
  * given without WAVE_ETA_ARRAY or missing with it), ENOMEM (arena too
- * small), EUNSTABLE (wave_stability > 1), EDEVICE. */
+ * small), EUNSTABLE (wave_stability > 1, or, with damping on, a largest
+ * eta at or above 2 + sqrt(8 - 4 s^2), s = wave_stability: there the damped
+ * layer update of one point, (1 + 2 eta) u' = (2 + 2 eta - eta^2 - vp K) u
+ * - u_prev for a mode with Laplacian symbol -K, has a growth factor below -1;
+ * the default profile reaches it with 1- or 2-cell layers at Courant
+ * number 0.4), EDEVICE.  The inputs are checked before the arena, so a
+ * NULL arena validates a descriptor and its arrays without device work
+ * (EINVAL naming the arena when they are valid). */
 int wave_alloc(const wave_desc *d, const float *vel_host, const float *eta_host,
                void *dev_arena, size_t arena_bytes, void *hip_stream, wave_ctx **out);
 
@@ -145,7 +162,8 @@ int wave_free(wave_ctx *ctx);
  * vp(s) * w[n] into u^{n+1}(s) (Alg. 1 source add, scaled per Eq. 2).
  * Several sources at one cell are added in the order they were given.
  * Errors: EINVAL (index outside the grid, nsamples > max_steps, table
- * full). */
+ * full, the context is a batch member: a batch copies its members' source
+ * tables when they join). */
 int wave_inject(wave_ctx *ctx, int32_t i, int32_t j, int32_t k,
                 const float *samples_host, int32_t nsamples);
 
@@ -153,7 +171,7 @@ int wave_inject(wave_ctx *ctx, int32_t i, int32_t j, int32_t k,
  * After each step n the library records u^{n+1}(rec_r) (after the source
  * add) as float64 into traces[t][r], t counting steps since this call.
  * ijk_host is int32 [nrec][3] = (i, j, k).  Errors: EINVAL (index outside
- * the grid, nrec > max_rec). */
+ * the grid, nrec > max_rec, the context is a batch member). */
 int wave_record(wave_ctx *ctx, const int32_t *ijk_host, int32_t nrec);
 
 /* ---- time stepping ------------------------------------------------------ */

@@ -186,6 +186,19 @@ void eta_tables(const wave_desc* d, double vmax, const float q[3], std::vector<u
   memcpy(out.data() + t.size() * 8, dq.data(), dq.size() * 4);
 }
 
+// Largest eta of the default profile: at a corner of the grid, where the
+// depth into the layer is w on every axis, eta = fl32(dt * sum_a d0_a).
+double max_default_eta(const wave_desc* d, double vmax) {
+  const double h[3] = {d->dx, d->dy, d->dz};
+  double s = 0.0;
+  for (int a = 0; a < 3; ++a) s += 3.0 * vmax * log(1.0 / d->refl) / (2.0 * ((double)d->w * h[a]));
+  return (double)(float)(d->dt * s);
+}
+
+// Largest eta the damped update tolerates at stability number stab <= 1:
+// 2 + sqrt(8 - 4 stab^2) (2 + 2 sqrt 2 without the Laplacian, 4 at stab 1).
+double eta_limit(double stab) { return 2.0 + sqrt(8.0 - 4.0 * stab * stab); }
+
 uint16_t host_bf16(float f) {
   uint32_t u;
   memcpy(&u, &f, 4);
@@ -562,6 +575,22 @@ size_t wave_bytes_required(const wave_desc* d) {
   return plan_arena(d).total;
 }
 
+int wave_admit(const wave_desc* d, size_t budget_bytes, size_t in_use_bytes, size_t* need_out,
+               int32_t* fits_now) {
+  std::string why;
+  if (need_out) *need_out = 0;
+  if (fits_now) *fits_now = 0;
+  if (!desc_ok(d, &why)) return fail(WAVE_EINVAL, why);
+  const size_t need = plan_arena(d).total;
+  if (need_out) *need_out = need;
+  if (need > budget_bytes)
+    return fail(WAVE_EBUDGET, "request needs " + std::to_string(need) +
+                                  " bytes of arena, more than the whole budget of " +
+                                  std::to_string(budget_bytes));
+  if (fits_now) *fits_now = in_use_bytes <= budget_bytes && need <= budget_bytes - in_use_bytes;
+  return WAVE_OK;
+}
+
 int wave_coefficients(const wave_desc* d, float out[13]) {
   std::string why;
   if (!desc_ok(d, &why)) return fail(WAVE_EINVAL, why);
@@ -606,11 +635,6 @@ int wave_alloc(const wave_desc* d, const float* vel, const float* eta, void* dev
   *out = nullptr;
   if (!desc_ok(d, &why)) return fail(WAVE_EINVAL, why);
   if (!vel) return fail(WAVE_EINVAL, "velocity is NULL");
-  if (!dev_arena || ((uintptr_t)dev_arena & 255)) return fail(WAVE_EINVAL, "arena NULL or not 256-byte aligned");
-  const ArenaPlan plan = plan_arena(d);
-  if (arena_bytes < plan.total)
-    return fail(WAVE_ENOMEM, "arena of " + std::to_string(arena_bytes) + " bytes < required " +
-                                 std::to_string(plan.total));
   const size_t n = (size_t)d->nx * d->ny * d->nz;
   double vmax = 0.0;
   for (size_t p = 0; p < n; ++p) {
@@ -629,6 +653,32 @@ int wave_alloc(const wave_desc* d, const float* vel, const float* eta, void* dev
   const double stab = wave_stability(d, vmax);
   if (stab > 1.0)
     return fail(WAVE_EUNSTABLE, "stability number " + std::to_string(stab) + " > 1 (reduce dt)");
+  if (damp) {
+    // the damped layer update amplifies where eta is too large: frozen at
+    // one point, with s = vp K its share of the Laplacian's symbol, its
+    // growth factor solves (1 + 2 eta) l^2 - (2 + 2 eta - eta^2 - s) l + 1 = 0,
+    // whose root leaves [-1, 1] through -1 once eta^2 - 4 eta - (4 - s) >= 0,
+    // i.e. eta >= 2 + sqrt(8 - s); s is at most 4 stab^2 (the leapfrog
+    // bound), so the bound is taken there
+    double emax = 0.0;
+    if (eta) {
+      for (size_t p = 0; p < n; ++p) emax = std::max(emax, (double)eta[p]);
+    } else {
+      emax = max_default_eta(d, vmax);
+    }
+    const double lim = eta_limit(stab);
+    if (emax >= lim)
+      return fail(WAVE_EUNSTABLE, "largest damping eta " + std::to_string(emax) +
+                                      " reaches the layer update's bound " + std::to_string(lim) +
+                                      " (widen the layer or reduce dt)");
+  }
+  // the inputs are checked first, so a host without a device can validate a
+  // descriptor and its arrays by passing a NULL arena
+  if (!dev_arena || ((uintptr_t)dev_arena & 255)) return fail(WAVE_EINVAL, "arena NULL or not 256-byte aligned");
+  const ArenaPlan plan = plan_arena(d);
+  if (arena_bytes < plan.total)
+    return fail(WAVE_ENOMEM, "arena of " + std::to_string(arena_bytes) + " bytes < required " +
+                                 std::to_string(plan.total));
 
   wave_ctx* c = new wave_ctx();
   c->batch = nullptr;
@@ -726,6 +776,8 @@ int wave_free(wave_ctx* c) {
 int wave_inject(wave_ctx* c, int32_t i, int32_t j, int32_t k, const float* samples,
                 int32_t nsamples) {
   CHECK_CTX(c);
+  // a batch copies its members' source and receiver tables when they join
+  if (c->batch) return fail(WAVE_EINVAL, "context is a batch member (remove it to add sources)");
   JOIN_CTX(c);
   if (!in_grid(c, i, j, k)) return fail(WAVE_EINVAL, "source index outside the grid");
   if (nsamples < 0 || nsamples > c->d.max_steps) return fail(WAVE_EINVAL, "nsamples outside [0, max_steps]");
@@ -752,6 +804,7 @@ int wave_inject(wave_ctx* c, int32_t i, int32_t j, int32_t k, const float* sampl
 
 int wave_record(wave_ctx* c, const int32_t* ijk, int32_t nrec) {
   CHECK_CTX(c);
+  if (c->batch) return fail(WAVE_EINVAL, "context is a batch member (remove it to set receivers)");
   JOIN_CTX(c);
   if (nrec < 0 || nrec > c->d.max_rec) return fail(WAVE_EINVAL, "nrec outside [0, max_rec]");
   if (nrec > 0 && !ijk) return fail(WAVE_EINVAL, "receiver list is NULL");

@@ -64,6 +64,17 @@ class Executor:
     def bytes_for(self, req: Request) -> int:
         raise NotImplementedError
 
+    def admit(self, req: Request, in_use: int, budget: int):
+        """(status, bytes, fits now) under the budget, with the library's
+        status codes: WAVE_OK (admissible; `fits now` says whether beside
+        `in_use`), WAVE_EBUDGET (larger than the whole budget), WAVE_EINVAL."""
+        nb = int(self.bytes_for(req))
+        if nb <= 0:
+            return W.WAVE_EINVAL, 0, False
+        if nb > budget:
+            return W.WAVE_EBUDGET, nb, False
+        return W.WAVE_OK, nb, in_use + nb <= budget
+
     def start(self, req: Request) -> None:
         raise NotImplementedError
 
@@ -108,12 +119,17 @@ class GpuExecutor(Executor):
         self.run_stream = torch.cuda.current_stream(device)
         self.io_stream = torch.cuda.Stream(device=device)
 
-    def bytes_for(self, req: Request) -> int:
+    def _desc(self, req: Request):
         s = req.shot
         nrec = 0 if s.rec is None else len(s.rec)
-        d = W.make_desc(s.nx, s.ny, s.nz, s.w, s.dx, s.dy, s.dz, s.dt, req.storage,
-                        max_src=max(1, len(s.src)), max_rec=nrec, max_steps=int(s.steps))
-        return W.wave_bytes_required(d)
+        return W.make_desc(s.nx, s.ny, s.nz, s.w, s.dx, s.dy, s.dz, s.dt, req.storage,
+                           max_src=max(1, len(s.src)), max_rec=nrec, max_steps=int(s.steps))
+
+    def bytes_for(self, req: Request) -> int:
+        return W.wave_bytes_required(self._desc(req))
+
+    def admit(self, req: Request, in_use: int, budget: int):
+        return W.wave_admit(self._desc(req), budget, in_use)
 
     def _batch(self, storage: str) -> W.Batch:
         b = self.batches.get(storage)
@@ -168,7 +184,8 @@ class Server:
 
     run(requests) replays the requests' arrival times against the wall clock
     (time_scale < 1 compresses them) and returns the requests with their
-    latencies.  A request larger than the whole budget is rejected.
+    latencies.  A request larger than the whole budget is rejected
+    (WAVE_EBUDGET from the executor's admission check).
 
     The loop keeps one block in flight: it admits what has arrived, enqueues
     the next block, takes the requests that this block completes out of
@@ -205,14 +222,14 @@ class Server:
             # admit in arrival order while the budget allows (no overtaking)
             while waiting:
                 r = waiting[0]
-                nb = self.ex.bytes_for(r)
-                if nb == 0 or nb > self.budget:
+                rc, nb, fits = self.ex.admit(r, self.in_use, self.budget)
+                if rc != W.WAVE_OK:
                     waiting.popleft()
-                    r.error = "rejected: larger than the memory budget"
+                    r.error = f"rejected: {W.wave_strerror(rc)}"
                     r.finished = now()
                     done.append(r)
                     continue
-                if self.in_use + nb > self.budget:
+                if not fits:
                     break
                 waiting.popleft()
                 self.ex.start(r)

@@ -34,7 +34,7 @@ WAVE_KERNEL_GMEM, WAVE_KERNEL_RING, WAVE_KERNEL_SHIFT, WAVE_KERNEL_PAIR = 3, 4, 
 STORAGE = {"f32": WAVE_F32, "bf16": WAVE_BF16, "f16": WAVE_F16}
 
 EXPORTED = [
-    "wave_bytes_required", "wave_coefficients", "wave_stability", "wave_eta_default",
+    "wave_bytes_required", "wave_admit", "wave_coefficients", "wave_stability", "wave_eta_default",
     "wave_alloc", "wave_free", "wave_inject", "wave_record", "wave_step", "wave_sync",
     "wave_step_count", "wave_read_field", "wave_write_field", "wave_read_traces",
     "wave_energy", "wave_set_kernel", "wave_set_timing", "wave_read_timing",
@@ -71,6 +71,7 @@ def _load():
     D = C.POINTER(wave_desc)
     sig = {
         "wave_bytes_required": (sz, [D]),
+        "wave_admit": (C.c_int, [D, sz, sz, C.POINTER(sz), C.POINTER(i32)]),
         "wave_coefficients": (C.c_int, [D, P]),
         "wave_stability": (f64, [D, f64]),
         "wave_eta_default": (C.c_int, [D, f64, P]),
@@ -121,6 +122,15 @@ def _p(a: Optional[np.ndarray]):
 # ---- the C functions under their own names ---------------------------------
 def wave_bytes_required(d: wave_desc) -> int:
     return int(_lib.wave_bytes_required(C.byref(d)))
+
+
+def wave_admit(d: wave_desc, budget_bytes: int, in_use_bytes: int):
+    """(status, bytes needed, fits now) of a request under a memory budget."""
+    need = C.c_size_t(0)
+    fits = C.c_int32(0)
+    rc = _lib.wave_admit(C.byref(d), C.c_size_t(int(budget_bytes)), C.c_size_t(int(in_use_bytes)),
+                         C.byref(need), C.byref(fits))
+    return int(rc), int(need.value), bool(fits.value)
 
 
 def wave_coefficients(d: wave_desc):

@@ -124,3 +124,63 @@ def test_null_context_is_rejected(W):
 def test_stream_copy_rejects_misaligned(W):
     assert W.wave_stream_copy(16, 32, 17, 0) == W.WAVE_EINVAL
     assert W.wave_stream_copy(8, 32, 16, 0) == W.WAVE_EINVAL
+
+
+def _eta_limit(stab):
+    return 2.0 + math.sqrt(8.0 - 4.0 * stab * stab)
+
+
+@pytest.mark.parametrize("w,ok", [(1, False), (2, False), (3, True), (4, True), (20, True)])
+def test_alloc_rejects_layers_whose_damped_update_amplifies(W, w, ok):
+    """Courant number 0.4 with the default profile (refl 1e-3): the largest
+    eta, 3 * 4.145 / w at a grid corner, reaches the damped update's bound
+    2 + sqrt(8 - 4 s^2) (s the stability number) for 1- and 2-cell layers
+    only; the check runs on the host before any device work."""
+    n = 48
+    vmax = 3000.0
+    dt = 0.4 * 10.0 / vmax
+    d = _desc(W, nx=n, ny=n, nz=n, w=w, dx=10.0, dy=10.0, dz=10.0, dt=dt)
+    vel = np.full((n, n, n), vmax, np.float32)
+    e64, _ = oracle.eta_default(n, n, n, w, 10.0, 10.0, 10.0, dt, vmax)
+    lim = _eta_limit(oracle.stability(10.0, 10.0, 10.0, dt, vmax))
+    assert (float(e64.max()) < lim) == ok
+    # inputs are validated before the arena: a stable descriptor passes every
+    # check and stops at the NULL arena (EINVAL) without touching a device
+    rc, _ = W.wave_alloc(d, vel, None, 0, W.wave_bytes_required(d), 0)
+    if ok:
+        assert rc == W.WAVE_EINVAL and "arena" in W.wave_last_error()
+    else:
+        assert rc == W.WAVE_EUNSTABLE
+        assert "eta" in W.wave_last_error()
+
+
+def test_alloc_rejects_eta_arrays_at_the_bound(W):
+    n = 24
+    vmax = 2500.0
+    dt = 0.3 * 10.0 / vmax
+    de = _desc(W, nx=n, ny=n, nz=n, w=6, dx=10.0, dy=10.0, dz=10.0, dt=dt, eta_array=True)
+    vel = np.full((n, n, n), vmax, np.float32)
+    lim = _eta_limit(oracle.stability(10.0, 10.0, 10.0, dt, vmax))
+    need = W.wave_bytes_required(de)
+    for val, code in [(lim * 1.001, W.WAVE_EUNSTABLE), (lim * 0.999, W.WAVE_EINVAL)]:
+        eta = np.zeros((n, n, n), np.float32)
+        eta[0, 5, 7] = val
+        # a stable input gets past every host check and stops at the NULL
+        # arena (EINVAL) without touching a device
+        rc, _ = W.wave_alloc(de, vel, eta, 0, need, 0)
+        assert rc == code, (val, lim)
+        if code == W.WAVE_EINVAL:
+            assert "arena" in W.wave_last_error()
+
+
+def test_admission_under_a_budget(W):
+    d = _desc(W)
+    need = W.wave_bytes_required(d)
+    assert W.wave_admit(d, need, 0) == (W.WAVE_OK, need, True)
+    assert W.wave_admit(d, 3 * need, 2 * need) == (W.WAVE_OK, need, True)
+    assert W.wave_admit(d, 3 * need, 2 * need + 1) == (W.WAVE_OK, need, False)   # defer
+    assert W.wave_admit(d, 3 * need, 5 * need) == (W.WAVE_OK, need, False)
+    rc, n, fits = W.wave_admit(d, need - 1, 0)
+    assert (rc, n, fits) == (W.WAVE_EBUDGET, need, False)                        # never fits
+    assert "budget" in W.wave_last_error()
+    assert W.wave_admit(_desc(W, nx=0), 10 ** 12, 0)[0] == W.WAVE_EINVAL

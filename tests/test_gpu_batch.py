@@ -258,3 +258,36 @@ def test_batch_two_points_per_lane(W, storage, tile):
     b.close()
     for sh in members:
         sh.close()
+
+
+def test_member_sources_and_receivers_are_fixed_while_in_a_batch(W):
+    """A batch copies its members' source and receiver tables when they
+    join, so adding a source or replacing the receivers of a member is
+    refused (EINVAL) until it leaves; after leaving, the context takes both
+    and ends where the oracle does."""
+    say("case member source/receiver guard")
+    s = synth.config_small_layered(70, 45, 37, 5, 12, seed=301, nsrc=1)
+    sh = W.Shot(s.nx, s.ny, s.nz, s.w, s.dx, s.dy, s.dz, s.dt, s.vel, max_src=2,
+                max_rec=len(s.rec), max_steps=s.steps)
+    sh.inject(*s.src[0], s.wavelet[0])
+    sh.record(s.rec)
+    b = W.Batch(storage="f32", max_shots=2)
+    b.add(sh, 6)
+    b.run(6)
+    extra = synth.ricker(s.steps, s.dt, t0=0.25 / 15.0)
+    assert W.wave_inject(sh.ctx, 10, 11, 12, extra) == W.WAVE_EINVAL
+    assert W.wave_record(sh.ctx, s.rec[:3]) == W.WAVE_EINVAL
+    b.remove(sh)
+    assert W.wave_inject(sh.ctx, 10, 11, 12, extra) == W.WAVE_OK
+    sh.step(6)
+    got = read_all(W, sh)
+    b.close()
+    sh.close()
+    ref6 = oracle.run_shot(s, steps=6, precision="f32")
+    s2 = synth.config_small_layered(70, 45, 37, 5, 12, seed=301, nsrc=1)
+    s2.src = list(s.src) + [(10, 11, 12)]
+    s2.wavelet = np.stack([s.wavelet[0], extra])
+    ref = oracle.run_shot(s2, steps=6, precision="f32", n0=6,
+                          state=dict(u=ref6["u"], u_prev=ref6["u_prev"], phi=ref6["phi"]))
+    assert np.array_equal(got["u"], ref["u"])
+    assert np.array_equal(got["traces"][6:], ref["traces"])

@@ -56,7 +56,7 @@ GRIDS = [  # nx, ny, nz, w, steps, storage, damping
     (257, 40, 22, 9, 9, "f32", True),
     (130, 70, 30, 6, 10, "f32", False),
     (200, 48, 44, 20, 8, "bf16", True),      # layer wider than half a tile row
-    (3, 2, 5, 1, 6, "f32", True),
+    (6, 6, 7, 3, 6, "f32", True),        # all layer, smaller than every tile
     (1, 1, 1, 0, 4, "f16", True),
 ]
 KERNELS = [(6, 1, 16, 0), (6, 1, 8, 0), (6, 1, 16, 5), (6, 1, 8, 3)]

@@ -89,7 +89,7 @@ RAGGED = [
     (70, 45, 37, 5, 2),     # partial x tile, partial y tiles
     (65, 17, 130, 3, 1),    # 1 lane in the last x tile; long z
     (130, 33, 11, 4, 3),
-    (9, 200, 21, 2, 1),     # narrow x
+    (9, 200, 21, 3, 1),     # narrow x (3 inner columns)
     (1, 1, 1, 0, 1),        # a single point
     (64, 16, 8, 0, 1),      # no layer
     (40, 40, 40, 20, 1),    # all layer (2w = n)

@@ -68,7 +68,7 @@ GRIDS = [  # nx, ny, nz, w, steps, storage, damping
     (130, 19, 22, 3, 9, "bf16", True),
     (65, 33, 17, 4, 8, "f16", True),
     (45, 70, 30, 6, 10, "f32", False),
-    (3, 2, 5, 1, 6, "f32", True),       # smaller than every tile and chunk
+    (6, 6, 7, 3, 6, "f32", True),       # smaller than every tile and chunk, all layer
     (1, 1, 1, 0, 4, "bf16", True),      # one point, no layer
 ]
 
@@ -98,7 +98,7 @@ def test_shapes_with_eta_array(W):
 
 
 def test_shape_arguments_are_checked(W):
-    shot = synth.config_small_layered(20, 20, 20, 2, 4, seed=3)
+    shot = synth.config_small_layered(20, 20, 20, 3, 4, seed=3)
     sh = W.shot_from_synth(shot)
     for bad in [(3, 8, 8, 4), (3, 2, 2, 2), (4, 2, 8, 0), (4, 1, 12, 0), (5, 1, 16, -1)]:
         assert W.wave_set_kernel(sh.ctx, *bad) == W.WAVE_EINVAL, bad

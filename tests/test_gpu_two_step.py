@@ -71,7 +71,7 @@ CASES = [  # nx, ny, nz, w, steps, storage, damping, two-step zchunk
     (130, 33, 11, 4, 10, "f32", True, 64),      # 2 (w + 4) >= nz: every plane a cap plane
     (65, 17, 130, 3, 12, "f16", True, 16),
     (113, 65, 60, 9, 14, "f32", False, 16),
-    (9, 200, 21, 2, 9, "f32", True, 64),
+    (9, 200, 21, 3, 9, "f32", True, 64),
     (64, 64, 64, 16, 30, "f32", True, 0),
     (120, 40, 90, 6, 16, "bf16", True, 32),
     (1, 1, 1, 0, 6, "f32", True, 64),

@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E nameplate
+GOLD = os.path.join(ROOT, "tests", "golden")
 
 
 def log(*a):
@@ -39,7 +40,9 @@ KERNELS = {0: ("k_sweep_direct", "direct", ("wave_kernels.hip", "wave_direct.h",
            3: ("k_sweep_gmem", "gmem", ("wave_shapes.hip", "wave_direct.h", "wave_point.h")),
            4: ("k_sweep_ring", "ring", ("wave_shapes.hip", "wave_direct.h", "wave_point.h")),
            5: ("k_sweep_shift", "shift", ("wave_shapes.hip", "wave_direct.h", "wave_point.h")),
-           6: ("k_sweep_pair", "pair", ("wave_kernels_pair.hip", "wave_point.h"))}
+           6: ("k_sweep_pair", "pair", ("wave_kernels_pair.hip", "wave_point.h")),
+           7: ("k_sweep_stream", "semi", ("wave_kernels.hip", "wave_point.h")),
+           8: ("k_sweep_persist", "persist", ("wave_kernels.hip", "wave_point.h"))}
 
 
 def kernel_source_sha(variant: int = 1) -> str:
@@ -59,6 +62,10 @@ def describe(cfg) -> str:
         return f"3-D tile {ry}x{nw}x{zc}, all operands from memory"
     if v == 6:
         return f"stream, two points per lane, 128x{nw} zchunk={zc}"
+    if v == 7:
+        return f"stream, z semi-stencil, 64x{nw} zchunk={zc}"
+    if v == 8:
+        return f"stream, persistent (one workgroup per CU), 64x{nw} zchunk={zc}"
     if v in (4, 5):
         return f"2.5-D {'ring of 9 LDS planes' if v == 4 else 'LDS plane + shifted registers'} " \
                f"64x{nw} zchunk={zc}"
@@ -86,6 +93,89 @@ def measured_traffic(workload: str, launches_bytes: float, variant: int = 1, til
     return float(t["hbm_bytes_per_launch"])
 
 
+# ---- error against float64 ------------------------------------------------------
+# The float64 results come from goldens written by tests/golden/make_fp64_gap.py
+# (the CPU oracle's float64 mode on the same seeded shots); the GPU results are
+# compared on the samples stored there: an xz plane through the source (every
+# few points) and the traces of every few receivers.
+
+def load_golden(name):
+    base = os.path.join(GOLD, f"{name}_fp64_gap")
+    if not (os.path.exists(base + ".json") and os.path.exists(base + ".npz")):
+        return None
+    import numpy as np
+    return json.load(open(base + ".json")), np.load(base + ".npz")
+
+
+def rel_l2(a, b) -> float:
+    import numpy as np
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float("nan")
+
+
+def c2_accuracy(W, shot, storage, kernel):
+    """The benchmark shot run for the golden's step count (1000, the paper's
+    protocol) on the GPU with the given launch, against the float64 oracle on
+    the golden's samples, and whether it equals the oracle's own
+    float32-arithmetic mode there bit for bit."""
+    import dataclasses
+    import numpy as np
+    import synth
+    base = {(512, 20): "c2", (1024, 32): "c3"}.get((shot.nx, shot.w))
+    if base is None:
+        return None
+    g = load_golden(base if storage == "f32" else f"{base}_{storage}")
+    if g is None or [shot.nx, shot.ny, shot.nz] != g[0]["grid"] or shot.w != g[0]["layer"] \
+            or shot.seed != g[0]["seed"]:
+        return None
+    meta, arr = g
+    steps = meta["steps"]
+    s = dataclasses.replace(shot, steps=steps, wavelet=synth.ricker(steps, shot.dt)[None, :])
+    sh = W.shot_from_synth(s, storage=storage, max_steps=steps)
+    sh.set_kernel(*kernel)
+    sh.step(steps)
+    u = sh.read(W.WAVE_FIELD_U)
+    tr = sh.traces()
+    sh.close()
+    sm = meta["sample"]
+    plane = np.ascontiguousarray(u[::sm["plane_stride"], sm["plane_j"], ::sm["plane_stride"]])
+    trs = np.ascontiguousarray(tr[:, ::sm["receiver_stride"]])
+    same = bool(np.array_equal(plane, arr["plane_f32"]) and
+                np.array_equal(trs.astype(np.float32), arr["traces_f32"]))
+    out = {"steps": steps,
+           "rel_l2_vs_fp64": {"field_sample": round(rel_l2(plane, arr["plane_f64"]), 10),
+                              "traces_sample": round(rel_l2(trs, arr["traces_f64"]), 10)},
+           "equals_oracle_same_arithmetic_on_sample": same,
+           "oracle_whole_field_rel_l2_vs_fp64": meta["field_rel_l2"],
+           "oracle_traces_rel_l2_vs_fp64": meta["traces_rel_l2"],
+           "sample": f"xz plane j={sm['plane_j']} every {sm['plane_stride']}th point, "
+                     f"every {sm['receiver_stride']}th receiver trace"}
+    log(f"[bench] {storage} {shot.nx}^3 x {steps} steps vs fp64: {out['rel_l2_vs_fp64']} "
+        f"(equals oracle: {same})")
+    return out
+
+
+def sampled_error(golden_entry, arr, u, traces):
+    """rel L2 of a GPU result against a float64 golden entry's samples
+    (plane through the source, traces of every few receivers)."""
+    import numpy as np
+    key = golden_entry["key"]
+    ps = 8
+    plane = u[::ps, golden_entry["plane_j"], ::ps]
+    return max(rel_l2(plane, arr[f"{key}_plane"]), rel_l2(traces[:, ::8], arr[f"{key}_traces"]))
+
+
+def build_shots(specs, threads=8):
+    """synth shots for (nx, ny, nz, steps, seed) on a thread pool (the
+    velocity models are the bulk of the host time)."""
+    import synth
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(lambda t: synth.shot_from_shape(*t), specs))
+
+
 def copy_bandwidth(W, torch, nbytes=2 << 30, reps=10):
     """Plain streaming copy (the measured-bandwidth reference)."""
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
@@ -105,11 +195,12 @@ def copy_bandwidth(W, torch, nbytes=2 << 30, reps=10):
     return 2.0 * nbytes / (ms / 1e3) / 1e9
 
 
-def plain_rate(W, torch, n, w, storage, steps):
-    """One shot, plain launches, given storage: Gpoints/s and the sweep
-    kernel's algorithmic GB/s."""
+def plain_rate(W, torch, n, w, storage, steps, seed=1002, accuracy=True):
+    """One shot, plain launches, given storage: Gpoints/s, the sweep
+    kernel's algorithmic GB/s, and (with a golden for the grid) the error of
+    a 1000-step run against float64."""
     import synth
-    shot = synth.config_c2(steps=steps + 20 + 64, n=n, w=w)
+    shot = synth.config_c2(steps=steps + 20 + 64, n=n, w=w, seed=seed)
     sh = W.shot_from_synth(shot, storage=storage, max_steps=steps + 20 + 50 + 64, two_step=True)
     cfg = sh.tune(2)
     sh.step(max(0, 20 - sh.step_count))
@@ -126,9 +217,13 @@ def plain_rate(W, torch, n, w, storage, steps):
     gbs = sh.sweep_bytes() / (kms / k / 1e3) / 1e9
     sh.close()
     log(f"[bench] {storage} {n}^3: {shot.points * steps / ms / 1e6:.1f} Gpt/s, sweep {gbs:.0f} GB/s")
-    return {"value": round(shot.points * steps / ms / 1e6, 3), "unit": "Gpoints/s",
-            "storage": storage, "steps": steps, "kernel": describe(cfg),
-            "sweep_gbps_algorithmic": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    out = {"value": round(shot.points * steps / ms / 1e6, 3), "unit": "Gpoints/s",
+           "storage": storage, "steps": steps, "kernel": describe(cfg),
+           "sweep_ms": round(kms / k, 5),
+           "sweep_gbps_algorithmic": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    if accuracy:
+        out["accuracy"] = c2_accuracy(W, shot, storage, cfg)
+    return out
 
 
 # the paper's code shapes (Sec. IV, Table II) on this GPU: wave_set_kernel
@@ -170,14 +265,16 @@ def shapes_rate(W, torch, n, w, steps=20):
 
 def batched_rate(W, torch, count):
     """`count` seeded shots (each axis uniform in {128, 144, .., 384}, 200-1000
-    steps, 20-cell layer) advanced together with captured step blocks and a
-    tuned tile, against the same shots run one at a time."""
+    steps, 20-cell layer, 5 % perturbed layered models) advanced together with
+    captured step blocks and a tuned tile, against the same shots run one at
+    a time; the error against float64 of the shots the batch golden holds."""
     import synth
     shapes = synth.batch_shapes(count=count)
     log(f"[bench] batched: building {count} shots")
-    shots = [synth.shot_from_shape(nx, ny, nz, st, seed, pert=0.0)
-             for (nx, ny, nz, st, seed) in shapes]
+    shots = build_shots([(nx, ny, nz, st, seed) for (nx, ny, nz, st, seed) in shapes])
     work = sum(s.points * s.steps for s in shots)
+    gold = load_golden("batch")
+    check = [e for e in gold[0]["members"] if e["index"] < count] if gold else []
     out = {"shots": count, "points_x_steps": work}
     for storage in ("f32", "bf16"):
         members = [W.shot_from_synth(s, storage=storage) for s in shots]
@@ -192,11 +289,18 @@ def batched_rate(W, torch, count):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         b.close()
+        errs = {}
+        for e in check:
+            m = members[e["index"]]
+            errs[e["key"]] = round(sampled_error(e, gold[1], m.read(W.WAVE_FIELD_U), m.traces()), 9)
         for m in members:
             m.close()
         out[f"batched_{storage}"] = {"value": round(work / dt / 1e9, 3), "unit": "Gpoints/s",
                                      "seconds": round(dt, 3), "tile": list(cfg)}
-        log(f"[bench] batched {storage}: {work / dt / 1e9:.1f} Gpt/s ({dt:.2f} s)")
+        if errs:
+            out[f"batched_{storage}"]["max_rel_l2_vs_fp64"] = max(errs.values())
+            out[f"batched_{storage}"]["rel_l2_vs_fp64_per_shot"] = errs
+        log(f"[bench] batched {storage}: {work / dt / 1e9:.1f} Gpt/s ({dt:.2f} s), errors {errs}")
     # the same shots one at a time, plain float32 launches (set-up untimed,
     # like the batched leg's)
     solo = 0.0
@@ -211,33 +315,50 @@ def batched_rate(W, torch, count):
     solo = max(solo, 1e-9)
     out["one_at_a_time_f32"] = {"value": round(work / solo / 1e9, 3), "unit": "Gpoints/s",
                                 "seconds": round(solo, 3)}
+    out["batched_f32_over_one_at_a_time"] = round(out["batched_f32"]["value"] /
+                                                  out["one_at_a_time_f32"]["value"], 4)
+    if gold:
+        out["error_sample"] = (f"max over shots {[e['index'] for e in check]} of rel L2 vs the "
+                               "float64 oracle on an xz plane through the source (every 8th "
+                               "point) and every 8th receiver trace")
     log(f"[bench] one at a time f32: {work / solo / 1e9:.1f} Gpt/s ({solo:.2f} s)")
     return out
 
 
-def serve_run(W, torch, count):
-    """Seeded Poisson stream (20 requests/s; 256 requests by default) of shots
-    96-512 per axis, 200-2000 steps, storage uniform over f32/bf16/f16,
-    240 GB budget.  The offered load exceeds one GPU's capacity, so latency
-    includes queueing; offered and served load are both reported."""
+def serve_run(W, torch, count, rate=20.0, check_errors=True):
+    """Seeded Poisson stream (20 requests/s and 256 requests by default) of
+    shots 96-512 per axis, 200-2000 steps, storage uniform over
+    f32/bf16/f16, 5 % perturbed layered models, 240 GB budget.  Offered and
+    served load are both reported: above capacity, latency includes
+    queueing.  The requests the serve golden holds keep their wavefield and
+    are compared with float64 (max rel L2 per storage type)."""
     import synth
     from paper_2009_04619_amd.serve import GpuExecutor, Request, Server, summarize
-    reqs = []
+    specs = synth.serve_requests(count=count, rate=rate)
     log(f"[bench] serve: building {count} requests")
-    for q, r in enumerate(synth.serve_requests(count=count)):
-        shot = synth.shot_from_shape(r["nx"], r["ny"], r["nz"], r["steps"], r["seed"], pert=0.0)
-        reqs.append(Request(rid=q, arrival=r["t"], shot=shot,
-                            storage=["f32", "bf16", "f16"][r["storage"]]))
+    shots = build_shots([(r["nx"], r["ny"], r["nz"], r["steps"], r["seed"]) for r in specs])
+    reqs = [Request(rid=q, arrival=r["t"], shot=shot, storage=["f32", "bf16", "f16"][r["storage"]])
+            for q, (r, shot) in enumerate(zip(specs, shots))]
     offered = sum(r.points * r.shot.steps for r in reqs) / max(reqs[-1].arrival, 1e-9)
+    gold = load_golden("serve") if check_errors else None
+    check = {e["index"]: e for e in gold[0]["members"] if e["index"] < count} if gold else {}
     ex = GpuExecutor(graph_steps=10)
     srv = Server(ex, budget_bytes=240 * 10 ** 9, block_steps=50)
     t0 = time.perf_counter()
-    done = srv.run(reqs)
+    done = srv.run(reqs, keep_fields=set(check))
     wall = time.perf_counter() - t0
     ex.close()
     out = summarize(done, wall)
     out["offered_gpoints_per_s"] = round(offered / 1e9, 3)
-    out["arrival_rate_per_s"] = 20.0
+    out["arrival_rate_per_s"] = rate
+    if check:
+        errs = {}
+        for r in done:
+            if r.rid in check and r.error is None:
+                e = sampled_error(check[r.rid], gold[1], r.field, r.traces)
+                errs.setdefault(r.storage, []).append(e)
+        out["max_rel_l2_vs_fp64"] = {k: round(max(v), 9) for k, v in errs.items()}
+        out["checked_requests"] = {k: len(v) for k, v in errs.items()}
     log(f"[bench] serve: {out}")
     return out
 
@@ -289,6 +410,9 @@ def main():
                     help="skip the bf16, batched and serving measurements")
     ap.add_argument("--batch-shots", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 extras entry")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the 1000-step runs compared with the float64 goldens")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -353,7 +477,7 @@ def main():
     workload = f"{args.n}cube_w{args.w}_{args.storage}"
     variant = cfg[0] if cfg[0] in KERNELS else 1
     traffic = measured_traffic(workload, alg_bytes, variant,
-                               tile=(cfg[1], cfg[2]) if variant in (1, 6) else None)
+                               tile=(cfg[1], cfg[2]) if variant in (1, 6, 8) else None)
     log(f"[bench] sweep kernel avg {avg_ms:.4f} ms over {launches} launches, "
         f"{alg_bytes / pts:.2f} B/pt algorithmic -> {achieved:.0f} GB/s")
     r0 = time.perf_counter()
@@ -363,13 +487,23 @@ def main():
     log(f"[bench] set-up {setup_s * 1e3:.1f} ms, trace read-out {readout_s * 1e3:.1f} ms")
     sh.close()
     del sh
+    # the same launch run for the paper's 1000 steps, against float64
+    accuracy = None if args.no_accuracy else c2_accuracy(W, shot, args.storage, cfg)
 
     extras = None
     if not args.no_extras:
         extras = {"bf16_plain": plain_rate(W, torch, args.n, args.w, "bf16", 200),
                   "batched": batched_rate(W, torch, args.batch_shots),
                   "serve": serve_run(W, torch, args.serve_requests),
+                  # the same stream at a quarter of the arrival rate, below
+                  # capacity: latency is then service time, not backlog
+                  "serve_below_capacity": serve_run(W, torch, args.serve_requests // 4,
+                                                    rate=5.0, check_errors=False),
                   "code_shapes": shapes_rate(W, torch, args.n, args.w)}
+        if args.n == 512 and args.w == 20 and not args.no_large:
+            # the large-domain configuration: 1024^3 with a 32-cell layer
+            extras["large_1024cube_w32_f32"] = plain_rate(W, torch, 1024, 32, "f32", 100,
+                                                          seed=1003)
 
     copy_gbs = None if args.no_copy else copy_bandwidth(W, torch)
     if copy_gbs:
@@ -403,6 +537,7 @@ def main():
                      "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "kernel": KERNELS[variant][0], "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_kernel_ms": round(avg_ms, 5)},
+        "accuracy": accuracy,
         "copy_gbps": None if copy_gbs is None else round(copy_gbs, 1),
         "host_io": {"setup_s": round(setup_s, 4), "trace_readout_s": round(readout_s, 4),
                     "value_incl_host_io": round(pts * args.steps / (ms / 1e3 + setup_s + readout_s) / 1e9, 3),

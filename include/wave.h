@@ -257,6 +257,31 @@ int wave_energy(wave_ctx *ctx, double *out);
                                 waves_per_group = ty in {8, 16}, zchunk as
                                 for WAVE_KERNEL_STREAM; not with an eta
                                 array (EINVAL)                            */
+#define WAVE_KERNEL_PERSIST 8 /* the streaming kernel (the same tile code,
+                                so the same results bit for bit) as one
+                                persistent launch: one workgroup per CU,
+                                each sweeping a fixed, rotated share of the
+                                (tile, z chunk) items one after the other,
+                                so no CU waits for a new workgroup to be
+                                dispatched; rows_per_wave = 1,
+                                waves_per_group in {8, 16}, zchunk as for
+                                WAVE_KERNEL_STREAM                        */
+#define WAVE_KERNEL_SEMI 7   /* the streaming kernel with the z terms of
+                                Eq. 3 summed by the semi-stencil (Sec. IV,
+                                "Semi-stencil"), along the streaming axis:
+                                each staged plane adds c_zm u to the sums of
+                                its z neighbours in a forward phase (outputs
+                                ahead) and a backward phase (outputs behind,
+                                the fourth of which it completes), so an
+                                output is written 4 planes after it was
+                                staged.  The same Laplacian summed in
+                                another order: results differ from the
+                                other variants by float32 rounding only (a
+                                per-point bound is tested), which is why the
+                                autotuner never picks it.  rows_per_wave = 1,
+                                waves_per_group in {8, 16}, zchunk as for
+                                WAVE_KERNEL_STREAM; not with an eta array
+                                (EINVAL)                                 */
 
 /* Select the sweep kernel and its tile: rows_per_wave (RY) and
  * waves_per_group (NW) give a 64 x (RY*NW) xy tile; zchunk is the number of
@@ -269,8 +294,8 @@ int wave_energy(wave_ctx *ctx, double *out);
  * WAVE_KERNEL_STREAM2 (needs WAVE_TWO_STEP) rows_per_wave and
  * waves_per_group are ignored and zchunk is the two-step chunk (0 =
  * automatic; a window of zchunk + 16 planes).  Results do not depend on the
- * choice: every variant evaluates each point with the same operations in
- * the same order. */
+ * choice: every variant but WAVE_KERNEL_SEMI evaluates each point with the
+ * same operations in the same order. */
 int wave_set_kernel(wave_ctx *ctx, int32_t variant, int32_t rows_per_wave,
                     int32_t waves_per_group, int32_t zchunk);
 

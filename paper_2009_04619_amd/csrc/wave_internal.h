@@ -133,6 +133,14 @@ hipError_t launch_sweep_direct(const SweepArgs& a, int storage, hipStream_t s);
 hipError_t launch_sweep_stream(const SweepArgs& a, int storage, int ry, int nw,
                                int zchunk, hipStream_t s);
 bool stream_config_supported(int ry, int nw);
+// The streaming kernel as one persistent launch of `groups` workgroups (a
+// multiple of 8; one per CU), each sweeping its share of the tiles in turn.
+// Tiles 64 x nw, ry = 1, nw in {8, 16}.
+hipError_t launch_sweep_persist(const SweepArgs& a, int storage, int ry, int nw, int zchunk,
+                                int groups, hipStream_t s);
+// The streaming kernel with the z terms summed by the semi-stencil (64 x nw
+// tiles, nw in {8, 16}; default-profile tables or damping off only).
+hipError_t launch_sweep_semi(const SweepArgs& a, int storage, int nw, int zchunk, hipStream_t s);
 int auto_zchunk(int nx, int ny, int nz, int ry, int nw);
 // Largest z chunk the streaming kernels accept for planes of `plane`
 // elements (their float arrays are addressed with 32-bit offsets inside a

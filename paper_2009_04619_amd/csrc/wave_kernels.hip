@@ -91,7 +91,23 @@ typedef const float __attribute__((address_space(4))) CFloat;
 // as 0 and phi' dropped for the others, which gives the inner update
 // exactly); eta comes from the per-point array (EM = 1) or from the default
 // profile's tables (EM = 2, no eta traffic).
-template <class S, int RY, int NW, int EM>
+//
+// ZS: the z terms of the Laplacian by the semi-stencil (Sec. IV,
+// "Semi-stencil"): each u plane enters the sums of its 8 z neighbours the
+// plane it becomes the staged one, in two phases.  Forward: u(p) is the -m
+// neighbour of the outputs p+m, whose partial sums F collect
+// c_z4 u(p+m-4) + .. + c_z1 u(p+m-1) before their own plane is staged.
+// Backward: u(p) is the +m neighbour of the outputs p-m, whose sums A
+// (centre, x and y terms, plus F, formed when their plane was staged) it
+// completes in the order m = 1..4; the output p-4 is then final and is
+// written.  So an output trails the staged plane by 4 planes, its operands
+// (u^{n-1}, vp, phi, the profile's z term) are requested for that plane, and
+// each z term is c_zm u rather than c_zm (u(+m) + u(-m)): the same
+// Laplacian summed in another order, so results differ from the other
+// kernels by rounding only.  The phi update is unchanged (its gradient
+// keeps the x, y, z order: the z difference u(p+1) - u(p-1) is added the
+// plane after p was staged).  Default-profile tables only (no eta array).
+template <class S, int RY, int NW, int EM, bool ZS = false>
 __device__ __forceinline__ void stream_loop(const SweepArgs& a,
                                             float (*sm)[(RY * NW + 2 * kR) * (kTX + 2 * kR) + 64],
                                             const Slots<RY>& sl, const int* hl, const uint32_t* ho,
@@ -110,6 +126,8 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
   static_assert(L % NR == 0 && L % NE == 0 && L % 2 == 0, "ring lengths must divide the unroll");
   constexpr bool LAYER = EM != 0;
   constexpr bool EARR = EM == 1;
+  static_assert(!ZS || EM != 1, "the z semi-stencil takes the default profile's tables only");
+  constexpr int ZD = ZS ? kR : 0;  // planes an output trails the staged plane
 
   const int64_t Q = a.plane;
   const int P = a.pitch;
@@ -182,6 +200,10 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
   float ex0[NR][RY], ex1[NR][RY], ey0[NR][RY], ey1[NR][RY], ph[NR][RY];
   double tzr[NR];
   float dzr[NR];
+  // ZS: sums of the outputs in flight (A: planes z-3..z, F: z+1..z+4, G: the
+  // phi gradient of z-3..z), and dq_z of the staged planes
+  float A[ZS ? 4 : 1][RY], F[ZS ? 4 : 1][RY], G[ZS && LAYER ? 4 : 1][RY];
+  float dzs[ZS ? NR : 1] = {};
 
   // prologue: u(zb-4 .. zb+3+PD) into ring slots 0 .. L-2, operands of planes
   // zb .. zb+PD-1 into operand slots 0 .. PD-1, eta(zb-1 .. zb+PD) into eta
@@ -194,15 +216,18 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
   }
 #pragma unroll
   for (int j = 0; j < PD; ++j) {
-    const uint32_t kp = (uint32_t)min(j + kR, zlast);
+    // operands of the output plane zb - ZD + j, halo of the staged plane zb + j
+    const uint32_t kp = (uint32_t)min(j + kR - ZD, zlast);
     const uint32_t se = kp * pe, s4 = kp * p4;
+    const uint32_t sh = (uint32_t)min(j + kR, zlast) * pe;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       pv[j][r] = S::bld1(rn, vo[r], se);
       vv[j][r] = bld1_f32(rv, vo4[r], s4);
     }
 #pragma unroll
-    for (int k = 0; k < HPT; ++k) hh[j][k] = S::bld(ru, hoe[k], se);
+    for (int k = 0; k < HPT; ++k) hh[j][k] = S::bld(ru, hoe[k], sh);
+    if (ZS && LAYER) dzs[j] = dqzt[min(zb + j, a.nz - 1)];
     if (LAYER) {
 #pragma unroll
       for (int r = 0; r < RY; ++r) ph[j][r] = bld1_f32(rph, fo[r], s4);
@@ -230,28 +255,49 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
       for (int r = 0; r < RY; ++r) er[j][r] = bld_f32(ret, eo[r], s4);
     }
   }
+  if constexpr (ZS) {
+    // forward phase of the planes zb-4 .. zb-1 (ring slots 0..3): F(zb+i)
+    // starts with c_z4 u(zb+i-4) and gathers the nearer planes in turn
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        A[i][r] = 0.0f;
+        if (LAYER) G[i][r] = 0.0f;
+        float f = a.c[12] * q[i][r];
+#pragma unroll
+        for (int m = 3; m >= 1; --m)
+          if (i + 4 - m < 4) f = __builtin_fmaf(a.c[8 + m], q[i + 4 - m][r], f);
+        F[i][r] = f;
+      }
+    }
+  }
 
   auto body = [&](auto SC, const int z) {
     constexpr int Sl = decltype(SC)::value;
-    constexpr int B = Sl % NR;          // operand slot of plane z
-    constexpr int BP = (Sl + PD) % NR;  // operand slot of plane z + PD
+    constexpr int B = Sl % NR;          // operand slot of plane z - ZD
+    constexpr int BP = (Sl + PD) % NR;  // operand slot of plane z - ZD + PD
     constexpr int LB = Sl & 1;          // LDS buffer
     const int kz = z - zb + kR;         // window index of plane z
-    // request the operands of plane zp = min(z + PD, ze - 1) and u(zp + 4),
-    // unconditionally so that the number of loads in flight is the same on
-    // every path (past the chunk's end the loads repeat its last planes,
-    // which are in cache, and are never used)
+    // ZS: dq_z of plane z - 1 (its slot is refilled below)
+    const float dz1 = ZS && LAYER ? dzs[(Sl + NR - 1) % NR] : 0.0f;
+    // request the halo of plane zh = min(z + PD, ze - 1), u(zh + 4) and the
+    // operands of output plane zh - ZD, unconditionally so that the number
+    // of loads in flight is the same on every path (past the chunk's end the
+    // loads repeat its last planes, which are in cache, and are never used)
     {
-      const uint32_t kp = (uint32_t)min(kz + PD, zlast);
-      const uint32_t se = kp * pe, s4 = kp * p4;
+      const uint32_t kh = (uint32_t)min(kz + PD, zlast);
+      const uint32_t kp = (uint32_t)min(kz - ZD + PD, zlast);
+      const uint32_t se = kp * pe, s4 = kp * p4, sh = kh * pe;
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
-        q[(Sl + L - 1) % L][r] = S::bld(ru, vo[r], se + 4u * pe);
+        q[(Sl + L - 1) % L][r] = S::bld(ru, vo[r], sh + 4u * pe);
         pv[BP][r] = S::bld1(rn, vo[r], se);
         vv[BP][r] = bld1_f32(rv, vo4[r], s4);
       }
 #pragma unroll
-      for (int k = 0; k < HPT; ++k) hh[BP][k] = S::bld(ru, hoe[k], se);
+      for (int k = 0; k < HPT; ++k) hh[BP][k] = S::bld(ru, hoe[k], sh);
+      if (ZS && LAYER) dzs[BP] = dqzt[min(zb - kR + (int)kh, a.nz - 1)];
       if (LAYER) {
 #pragma unroll
         for (int r = 0; r < RY; ++r) ph[BP][r] = bld1_f32(rph, fo[r], s4);
@@ -272,72 +318,138 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
         }
       }
     }
-    // stage the centre plane and its halo
-    float* s = sm[LB];
+    if constexpr (ZS) {
+      const bool stage = z < ze;        // plane z is an output plane of the chunk
+      const bool emit = z - ZD >= zb;   // output plane z - 4 is complete
+      float* s = sm[LB];
+      if (stage) {
 #pragma unroll
-    for (int r = 0; r < RY; ++r) s[sl.ls[r]] = q[(Sl + kR) % L][r];
+        for (int r = 0; r < RY; ++r) s[sl.ls[r]] = q[(Sl + kR) % L][r];
 #pragma unroll
-    for (int k = 0; k < HPT; ++k) s[hl[k]] = hh[B][k];
-    __syncthreads();
-
-    const uint32_t sz = (uint32_t)kz * pe, sz4 = (uint32_t)kz * p4;
-#pragma unroll
-    for (int r = 0; r < RY; ++r) {
-      const float* row = s + sl.ls[r];
-      const float c = q[(Sl + kR) % L][r];
-      float lap = a.c[0] * c;
-#pragma unroll
-      for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(a.c[m], row[m] + row[-m], lap);
-#pragma unroll
-      for (int m = 1; m <= kR; ++m)
-        lap = __builtin_fmaf(a.c[4 + m], row[m * LW] + row[-m * LW], lap);
-#pragma unroll
-      for (int m = 1; m <= kR; ++m)
-        lap = __builtin_fmaf(a.c[8 + m], q[(Sl + kR + m) % L][r] + q[(Sl + kR - m) % L][r], lap);
-      lap = __builtin_fmaf(a.ce, c, lap);
-      const float pu = pv[B][r];
-      const float vp = vv[B][r];
-      float res;
-      if (LAYER) {
-        float e, gx, gy, gz;
-        if (EARR) {
-          e = er[(Sl + 1) % NE][r];
-          gx = (ex1[B][r] - ex0[B][r]) * a.q[0];
-          gy = (ey1[B][r] - ey0[B][r]) * a.q[1];
-          gz = (er[(Sl + 2) % NE][r] - er[Sl % NE][r]) * a.q[2];
-        } else {
-          // table mode: non-layer points take eta = 0 like the array mode's
-          // out-of-range loads (their phi' is dropped, so gx..gz do not
-          // matter there)
-          e = sl.lay[r] ? (float)(a.dt * (tsc[r] + tzr[B])) : 0.0f;
-          gx = dqx[r];
-          gy = dqy[r];
-          gz = dzr[B];
-        }
-        // phi of a point outside the layer counts as 0 (the loaded value is
-        // only written back)
-        const float phv = sl.lay[r] ? ph[B][r] : 0.0f;
-        res = upd_layer(c, pu, vp, lap, e, phv);
-        const float nph = upd_phi(phv, e, gx, row[1] - row[-1], gy, row[LW] - row[-LW], gz,
-                                  q[(Sl + kR + 1) % L][r] - q[(Sl + kR - 1) % L][r]);
-        // stored for every point; points where phi is not touched have an
-        // out-of-range offset, so their store is dropped
-        bst_f32(rph, fo[r], sz4, sl.lay[r] ? nph : ph[B][r]);
-      } else {
-        res = upd_inner(c, pu, vp, lap);
+        for (int k = 0; k < HPT; ++k) s[hl[k]] = hh[Sl % NR][k];
+        __syncthreads();
       }
-      // points past the grid have an out-of-range offset: no branch around
-      // the store
-      S::bst(rn, vo[r], sz, res);
+      const uint32_t so = (uint32_t)(kz - ZD) * pe, so4 = (uint32_t)(kz - ZD) * p4;
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        const float c = q[(Sl + kR) % L][r];  // u(z)
+        float xy = 0.0f, gxy = 0.0f;
+        if (stage) {
+          const float* row = s + sl.ls[r];
+          xy = a.c[0] * c;
+#pragma unroll
+          for (int m = 1; m <= kR; ++m) xy = __builtin_fmaf(a.c[m], row[m] + row[-m], xy);
+#pragma unroll
+          for (int m = 1; m <= kR; ++m)
+            xy = __builtin_fmaf(a.c[4 + m], row[m * LW] + row[-m * LW], xy);
+          if (LAYER) {
+            gxy = dqx[r] * (row[1] - row[-1]);
+            gxy = __builtin_fmaf(dqy[r], row[LW] - row[-LW], gxy);
+          }
+        }
+        // backward phase: u(z) is the +m neighbour of the outputs z - m
+        A[(Sl + 3) % 4][r] = __builtin_fmaf(a.c[9], c, A[(Sl + 3) % 4][r]);
+        A[(Sl + 2) % 4][r] = __builtin_fmaf(a.c[10], c, A[(Sl + 2) % 4][r]);
+        A[(Sl + 1) % 4][r] = __builtin_fmaf(a.c[11], c, A[(Sl + 1) % 4][r]);
+        A[Sl % 4][r] = __builtin_fmaf(a.c[12], c, A[Sl % 4][r]);
+        if (LAYER)  // z part of the phi gradient of plane z - 1
+          G[(Sl + 3) % 4][r] =
+              __builtin_fmaf(dz1, c - q[(Sl + kR - 2) % L][r], G[(Sl + 3) % 4][r]);
+        if (emit) {
+          const float cz = q[Sl % L][r];  // u(z - 4)
+          const float lap = __builtin_fmaf(a.ce, cz, A[Sl % 4][r]);
+          const float pu = pv[B][r];
+          const float vp = vv[B][r];
+          float res;
+          if (LAYER) {
+            const float e = sl.lay[r] ? (float)(a.dt * (tsc[r] + tzr[B])) : 0.0f;
+            const float phv = sl.lay[r] ? ph[B][r] : 0.0f;
+            res = upd_layer(cz, pu, vp, lap, e, phv);
+            const float nph = (phv - G[Sl % 4][r]) / (1.0f + e);
+            bst_f32(rph, fo[r], so4, sl.lay[r] ? nph : ph[B][r]);
+          } else {
+            res = upd_inner(cz, pu, vp, lap);
+          }
+          S::bst(rn, vo[r], so, res);
+        }
+        if (stage) {
+          A[Sl % 4][r] = xy + F[Sl % 4][r];
+          if (LAYER) G[Sl % 4][r] = gxy;
+        }
+        // forward phase: u(z) is the -m neighbour of the outputs z + m
+        F[Sl % 4][r] = a.c[12] * c;
+        F[(Sl + 3) % 4][r] = __builtin_fmaf(a.c[11], c, F[(Sl + 3) % 4][r]);
+        F[(Sl + 2) % 4][r] = __builtin_fmaf(a.c[10], c, F[(Sl + 2) % 4][r]);
+        F[(Sl + 1) % 4][r] = __builtin_fmaf(a.c[9], c, F[(Sl + 1) % 4][r]);
+      }
+    } else {
+      // stage the centre plane and its halo
+      float* s = sm[LB];
+  #pragma unroll
+      for (int r = 0; r < RY; ++r) s[sl.ls[r]] = q[(Sl + kR) % L][r];
+  #pragma unroll
+      for (int k = 0; k < HPT; ++k) s[hl[k]] = hh[B][k];
+      __syncthreads();
+
+      const uint32_t sz = (uint32_t)kz * pe, sz4 = (uint32_t)kz * p4;
+  #pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        const float* row = s + sl.ls[r];
+        const float c = q[(Sl + kR) % L][r];
+        float lap = a.c[0] * c;
+  #pragma unroll
+        for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(a.c[m], row[m] + row[-m], lap);
+  #pragma unroll
+        for (int m = 1; m <= kR; ++m)
+          lap = __builtin_fmaf(a.c[4 + m], row[m * LW] + row[-m * LW], lap);
+  #pragma unroll
+        for (int m = 1; m <= kR; ++m)
+          lap = __builtin_fmaf(a.c[8 + m], q[(Sl + kR + m) % L][r] + q[(Sl + kR - m) % L][r], lap);
+        lap = __builtin_fmaf(a.ce, c, lap);
+        const float pu = pv[B][r];
+        const float vp = vv[B][r];
+        float res;
+        if (LAYER) {
+          float e, gx, gy, gz;
+          if (EARR) {
+            e = er[(Sl + 1) % NE][r];
+            gx = (ex1[B][r] - ex0[B][r]) * a.q[0];
+            gy = (ey1[B][r] - ey0[B][r]) * a.q[1];
+            gz = (er[(Sl + 2) % NE][r] - er[Sl % NE][r]) * a.q[2];
+          } else {
+            // table mode: non-layer points take eta = 0 like the array mode's
+            // out-of-range loads (their phi' is dropped, so gx..gz do not
+            // matter there)
+            e = sl.lay[r] ? (float)(a.dt * (tsc[r] + tzr[B])) : 0.0f;
+            gx = dqx[r];
+            gy = dqy[r];
+            gz = dzr[B];
+          }
+          // phi of a point outside the layer counts as 0 (the loaded value is
+          // only written back)
+          const float phv = sl.lay[r] ? ph[B][r] : 0.0f;
+          res = upd_layer(c, pu, vp, lap, e, phv);
+          const float nph = upd_phi(phv, e, gx, row[1] - row[-1], gy, row[LW] - row[-LW], gz,
+                                    q[(Sl + kR + 1) % L][r] - q[(Sl + kR - 1) % L][r]);
+          // stored for every point; points where phi is not touched have an
+          // out-of-range offset, so their store is dropped
+          bst_f32(rph, fo[r], sz4, sl.lay[r] ? nph : ph[B][r]);
+        } else {
+          res = upd_inner(c, pu, vp, lap);
+        }
+        // points past the grid have an out-of-range offset: no branch around
+        // the store
+        S::bst(rn, vo[r], sz, res);
+      }
     }
   };
 
   using std::integral_constant;
   static_assert(L == 10 || L == 12 || L == 16, "unrolled loop below covers ring lengths 10, 12, 16");
-  for (int z = zb; z < ze; z += L) {
+  for (int z = zb; z < ze + ZD; z += L) {
 #define WAVE_BODY(J)                                   \
   if constexpr ((J) < L) {                             \
-    if ((J) > 0 && z + (J) >= ze) break;               \
+    if ((J) > 0 && z + (J) >= ze + ZD) break;          \
     body(integral_constant<int, (J) % L>{}, z + (J));  \
   }
     WAVE_BODY(0) WAVE_BODY(1) WAVE_BODY(2) WAVE_BODY(3) WAVE_BODY(4) WAVE_BODY(5)
@@ -347,7 +459,7 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
   }
 }
 
-template <class S, int RY, int NW>
+template <class S, int RY, int NW, bool ZS = false>
 __device__ __forceinline__ void stream_tile(const SweepArgs& a,
                                             float (*sm)[(RY * NW + 2 * kR) * (kTX + 2 * kR) + 64],
                                             int x0, int y0, int zb, int ze, bool cap) {
@@ -434,18 +546,18 @@ __device__ __forceinline__ void stream_tile(const SweepArgs& a,
 
   // wavefront-uniform choice of the loop
   if (!__any(any_lay))
-    stream_loop<S, RY, NW, 0>(a, sm, sl, hl, ho, zb, ze);
-  else if (a.etab)
-    stream_loop<S, RY, NW, 2>(a, sm, sl, hl, ho, zb, ze);
+    stream_loop<S, RY, NW, 0, ZS>(a, sm, sl, hl, ho, zb, ze);
+  else if (ZS || a.etab)
+    stream_loop<S, RY, NW, 2, ZS>(a, sm, sl, hl, ho, zb, ze);
   else
-    stream_loop<S, RY, NW, 1>(a, sm, sl, hl, ho, zb, ze);
+    stream_loop<S, RY, NW, ZS ? 2 : 1, ZS>(a, sm, sl, hl, ho, zb, ze);
 }
 
 // Occupancy target in wavefronts per SIMD for one-row tiles.
 #ifndef WAVE_STREAM_WAVES_PER_SIMD
 #define WAVE_STREAM_WAVES_PER_SIMD 4
 #endif
-template <class S, int RY, int NW>
+template <class S, int RY, int NW, bool ZS = false>
 __global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) void k_sweep_stream(
     SweepArgs a, int tiles_x, int tiles_y, int zchunk) {
   constexpr int TY = RY * NW;
@@ -473,7 +585,45 @@ __global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) 
   const bool damp = a.damping != 0;
   const ChunkInfo c = chunk_of(ch, a.nz, a.w, zchunk, damp);
   if (c.zb >= c.ze) return;
-  stream_tile<S, RY, NW>(a, sm, x0, y0, c.zb, c.ze, damp && c.cap);
+  stream_tile<S, RY, NW, ZS>(a, sm, x0, y0, c.zb, c.ze, damp && c.cap);
+}
+
+// The same sweep as one persistent launch: 8 G workgroups (G per XCD, one
+// per CU), each sweeping a fixed list of work items -- the (tile, z chunk)
+// pairs that k_sweep_stream runs as workgroups -- one after the other.
+// Items keep k_sweep_stream's order and XCD: the items of workgroup b's XCD
+// (b mod 8) are the blocks 8 s + b mod 8, s = 0, 1, ..  They are dealt out
+// in rounds of G: in round k, workgroup g = b / 8 takes s = k G +
+// (g + 5 k) mod G, so that over the rounds every workgroup meets every tile
+// position of a row (5 is coprime to the 8 of a tile row of a 512-wide
+// grid): wall tiles, which take longer, do not all land on the same
+// workgroups.  Each tile is swept by the same code as in k_sweep_stream, so
+// results are the same bit for bit.  No workgroup waits for the end of
+// another to start its next tile, and no atomics are needed.
+template <class S, int RY, int NW>
+__global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) void k_sweep_persist(
+    SweepArgs a, int tiles_x, int tiles_y, int zchunk) {
+  constexpr int TY = RY * NW;
+  constexpr int LSZ = (TY + 2 * kR) * (kTX + 2 * kR) + 64;
+  __shared__ float sm[2][LSZ];
+  const int xcd = blockIdx.x & 7;
+  const int g = blockIdx.x >> 3;
+  const int G = gridDim.x >> 3;
+  const int sh = (tiles_y + 7) >> 3;
+  const bool damp = a.damping != 0;
+  const int items = tiles_x * sh * chunk_count(a.nz, a.w, zchunk, damp);
+  for (int k = 0; k * G < items; ++k) {
+    const int slot = k * G + (g + 5 * k) % G;
+    if (slot >= items) continue;
+    const int tx = slot % tiles_x;
+    const int t2 = slot / tiles_x;
+    const int ch = t2 / sh;
+    const int ty = ((xcd + 3 * ch) & 7) * sh + t2 % sh;
+    const ChunkInfo c = chunk_of(ch, a.nz, a.w, zchunk, damp);
+    if (ty >= tiles_y || c.zb >= c.ze) continue;
+    stream_tile<S, RY, NW, false>(a, sm, tx * kTX, ty * TY, c.zb, c.ze, damp && c.cap);
+    __syncthreads();  // the next tile's staging reuses the LDS planes
+  }
 }
 
 // ---- many shots per launch ---------------------------------------------------
@@ -677,7 +827,7 @@ hipError_t sweep_direct_t(const SweepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <class S, int RY, int NW>
+template <class S, int RY, int NW, bool ZS = false>
 hipError_t sweep_stream_t(const SweepArgs& a, int zchunk, hipStream_t st) {
   constexpr int TY = RY * NW;
   const int tiles_x = (a.nx + kTX - 1) / kTX;
@@ -687,7 +837,22 @@ hipError_t sweep_stream_t(const SweepArgs& a, int zchunk, hipStream_t st) {
   // tile rows padded to a multiple of 8 (see k_sweep_stream)
   const int64_t blocks = (int64_t)tiles_x * 8 * ((tiles_y + 7) / 8) * chunks;
   if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_sweep_stream<S, RY, NW>), dim3((unsigned)blocks), dim3(64 * NW), 0, st, a,
+  hipLaunchKernelGGL((k_sweep_stream<S, RY, NW, ZS>), dim3((unsigned)blocks), dim3(64 * NW), 0, st,
+                     a, tiles_x, tiles_y, zchunk);
+  return hipGetLastError();
+}
+
+template <class S, int RY, int NW>
+hipError_t sweep_persist_t(const SweepArgs& a, int zchunk, int groups, hipStream_t st) {
+  constexpr int TY = RY * NW;
+  const int tiles_x = (a.nx + kTX - 1) / kTX;
+  const int tiles_y = (a.ny + TY - 1) / TY;
+  if (zchunk > stream_zchunk_limit(a.plane) || groups < 8 || groups % 8 != 0)
+    return hipErrorInvalidValue;
+  const int chunks = chunk_count(a.nz, a.w, zchunk, a.damping != 0);
+  const int64_t blocks = (int64_t)tiles_x * 8 * ((tiles_y + 7) / 8) * chunks;
+  if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_sweep_persist<S, RY, NW>), dim3((unsigned)groups), dim3(64 * NW), 0, st, a,
                      tiles_x, tiles_y, zchunk);
   return hipGetLastError();
 }
@@ -741,6 +906,37 @@ hipError_t launch_sweep_stream(const SweepArgs& a, int storage, int ry, int nw, 
     case 1: return sweep_stream_s<StBF16>(a, ry, nw, zchunk, s);
     case 2: return sweep_stream_s<StF16>(a, ry, nw, zchunk, s);
   }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep_persist(const SweepArgs& a, int storage, int ry, int nw, int zchunk,
+                                int groups, hipStream_t s) {
+  if (zchunk <= 0) return hipErrorInvalidValue;
+#define WAVE_PERSIST_CASE(S_)                                                         \
+  if (ry == 1 && nw == 16) return sweep_persist_t<S_, 1, 16>(a, zchunk, groups, s); \
+  if (ry == 1 && nw == 8) return sweep_persist_t<S_, 1, 8>(a, zchunk, groups, s);   \
+  return hipErrorInvalidValue;
+  switch (storage) {
+    case 0: { WAVE_PERSIST_CASE(StF32) }
+    case 1: { WAVE_PERSIST_CASE(StBF16) }
+    case 2: { WAVE_PERSIST_CASE(StF16) }
+  }
+#undef WAVE_PERSIST_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep_semi(const SweepArgs& a, int storage, int nw, int zchunk, hipStream_t s) {
+  if (zchunk <= 0 || (nw != 8 && nw != 16)) return hipErrorInvalidValue;
+  if (a.damping && !a.etab) return hipErrorInvalidValue;  // eta arrays: not in this kernel
+#define WAVE_SEMI_CASE(S_)                                                      \
+  return nw == 16 ? sweep_stream_t<S_, 1, 16, true>(a, zchunk, s)               \
+                  : sweep_stream_t<S_, 1, 8, true>(a, zchunk, s);
+  switch (storage) {
+    case 0: WAVE_SEMI_CASE(StF32)
+    case 1: WAVE_SEMI_CASE(StBF16)
+    case 2: WAVE_SEMI_CASE(StF16)
+  }
+#undef WAVE_SEMI_CASE
   return hipErrorInvalidValue;
 }
 

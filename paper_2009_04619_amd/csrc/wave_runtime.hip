@@ -32,6 +32,15 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 int storage_bytes(int32_t storage) { return storage == WAVE_F32 ? 4 : 2; }
 
+// Workgroups of a persistent sweep on the current device: one per CU, a
+// multiple of 8 (the XCD count of the tile order); 0 if the count is unknown.
+int persistent_groups() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return n >= 8 ? n / 8 * 8 : 0;
+}
+
 bool desc_ok(const wave_desc* d, std::string* why) {
   auto bad = [&](const char* m) {
     if (why) *why = m;
@@ -239,6 +248,7 @@ struct wave_ctx {
   bool src_fit2;                   // the sources fit the two-step kernel's tiles
   int variant, ry, nw, zchunk;
   int shp[3];             // WAVE_KERNEL_GMEM: block (bx, by, bz); RING/SHIFT: (1, ty, zchunk)
+  int groups;             // workgroups of a persistent launch (one per CU)
   bool timing;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t events_used;
@@ -488,11 +498,16 @@ int stream_zchunk(const wave_ctx* c, int ry, int nw, int zchunk) {
 // automatic length chosen for the tile count of 128-wide tiles; 0 when the
 // context holds an eta array (the kernel reads the default profile's tables
 // only) or one plane is too large to stream.
-int pair_zchunk(const wave_ctx* c, int ty, int zchunk) {
+// z chunk of the kernels that take the default profile's tables only: the
+// two-points-per-lane tiles (128 x ty; semi_nw = 0) and the semi-stencil
+// tiles (64 x semi_nw); 0 with an eta array or planes too large to stream.
+int pair_zchunk(const wave_ctx* c, int ty, int zchunk, int semi_nw = 0) {
   if (eta_array(&c->d)) return 0;
   const int lim = wave::stream_zchunk_limit(c->L.plane);
   if (lim < 1) return 0;
-  const int zc = zchunk > 0 ? zchunk : wave::auto_zchunk((c->L.nx + 1) / 2, c->L.ny, c->L.nz, 1, ty);
+  const int zc = zchunk > 0  ? zchunk
+                 : semi_nw  ? wave::auto_zchunk(c->L.nx, c->L.ny, c->L.nz, 1, semi_nw)
+                            : wave::auto_zchunk((c->L.nx + 1) / 2, c->L.ny, c->L.nz, 1, ty);
   return std::min(zc, lim);
 }
 
@@ -706,6 +721,7 @@ int wave_alloc(const wave_desc* d, const float* vel, const float* eta, void* dev
   c->src_fit2 = true;
   c->variant = WAVE_KERNEL_STREAM;
   c->shp[0] = c->shp[1] = c->shp[2] = 0;
+  c->groups = persistent_groups();
   c->ry = 1;
   c->nw = 16;
   c->zchunk = 0;
@@ -930,7 +946,9 @@ int wave_step(wave_ctx* c, int32_t n) {
   const int zc = stream_zchunk(c, c->ry, c->nw, c->zchunk);
   const bool direct = c->variant == WAVE_KERNEL_DIRECT || zc < 1;
   const bool shape25 = c->variant == WAVE_KERNEL_RING || c->variant == WAVE_KERNEL_SHIFT;
-  const int zcp = c->variant != WAVE_KERNEL_PAIR ? 0 : pair_zchunk(c, c->shp[1], c->shp[2]);
+  const int zcp = c->variant == WAVE_KERNEL_PAIR   ? pair_zchunk(c, c->shp[1], c->shp[2])
+                  : c->variant == WAVE_KERNEL_SEMI ? pair_zchunk(c, 0, c->shp[2], c->shp[1])
+                                                   : 0;
   const int zc25 = !shape25 ? 0
                    : c->shp[2] > 0 ? std::min(c->shp[2], c->L.nz)
                                    : wave::auto_zchunk25(c->L.nx, c->L.ny, c->L.nz, c->shp[1]);
@@ -942,6 +960,10 @@ int wave_step(wave_ctx* c, int32_t n) {
                                     c->shp[1], zc25, c->stream);
     if (c->variant == WAVE_KERNEL_PAIR)
       return wave::launch_sweep_pair(s, c->d.storage, c->shp[1], zcp, c->stream);
+    if (c->variant == WAVE_KERNEL_SEMI)
+      return wave::launch_sweep_semi(s, c->d.storage, c->shp[1], zcp, c->stream);
+    if (c->variant == WAVE_KERNEL_PERSIST && !direct)
+      return wave::launch_sweep_persist(s, c->d.storage, c->ry, c->nw, zc, c->groups, c->stream);
     return direct ? wave::launch_sweep_direct(s, c->d.storage, c->stream)
                   : wave::launch_sweep_stream(s, c->d.storage, c->ry, c->nw, zc, c->stream);
   };
@@ -1111,6 +1133,17 @@ int wave_set_kernel(wave_ctx* c, int32_t variant, int32_t ry, int32_t nw, int32_
     c->shp[2] = zchunk;
     return WAVE_OK;
   }
+  if (variant == WAVE_KERNEL_SEMI) {
+    if (ry != 1 || (nw != 8 && nw != 16)) return fail(WAVE_EINVAL, "semi-stencil kernel needs rows_per_wave 1, 8 or 16 rows");
+    if (zchunk < 0) return fail(WAVE_EINVAL, "zchunk < 0");
+    if (pair_zchunk(c, 0, zchunk, nw) < 1)
+      return fail(WAVE_EINVAL, "semi-stencil kernel: no eta array, and planes small enough to stream");
+    c->variant = variant;
+    c->shp[0] = 1;
+    c->shp[1] = nw;
+    c->shp[2] = zchunk;
+    return WAVE_OK;
+  }
   if (variant == WAVE_KERNEL_RING || variant == WAVE_KERNEL_SHIFT) {
     if (ry != 1 || (nw != 8 && nw != 16)) return fail(WAVE_EINVAL, "2.5-D shape needs rows_per_wave 1, 8 or 16 rows");
     if (zchunk < 0) return fail(WAVE_EINVAL, "zchunk < 0");
@@ -1120,7 +1153,10 @@ int wave_set_kernel(wave_ctx* c, int32_t variant, int32_t ry, int32_t nw, int32_
     c->shp[2] = zchunk;
     return WAVE_OK;
   }
-  if (variant != WAVE_KERNEL_STREAM) return fail(WAVE_EINVAL, "unknown kernel variant");
+  if (variant == WAVE_KERNEL_PERSIST && (ry != 1 || (nw != 8 && nw != 16)))
+    return fail(WAVE_EINVAL, "persistent sweep needs rows_per_wave 1, 8 or 16 rows");
+  if (variant != WAVE_KERNEL_STREAM && variant != WAVE_KERNEL_PERSIST)
+    return fail(WAVE_EINVAL, "unknown kernel variant");
   if (!wave::stream_config_supported(ry, nw)) return fail(WAVE_EINVAL, "tile (rows_per_wave, waves) not compiled");
   if (zchunk < 0) return fail(WAVE_EINVAL, "zchunk < 0");
   c->variant = variant;
@@ -1152,6 +1188,14 @@ int wave_tune(wave_ctx* c, int32_t trial_steps, int32_t chosen[4]) {
     for (int z : {za, std::max(8, za / 2), std::min(nz, 2 * za)}) {
       const int zc = stream_zchunk(c, ry, nw, z);
       if (zc >= 1) add({WAVE_KERNEL_STREAM, ry, nw, zc});
+    }
+  }
+  // the same tiles as one persistent launch (one workgroup per CU)
+  for (int nw : {16, 8}) {
+    const int za = wave::auto_zchunk(c->L.nx, c->L.ny, nz, 1, nw);
+    for (int z : {za, std::max(8, za / 2)}) {
+      const int zc = stream_zchunk(c, 1, nw, z);
+      if (zc >= 1 && c->groups >= 8) add({WAVE_KERNEL_PERSIST, 1, nw, zc});
     }
   }
   if (stream2_zchunk(c, 0) >= 1) {
@@ -1198,7 +1242,7 @@ int wave_tune(wave_ctx* c, int32_t trial_steps, int32_t chosen[4]) {
   const int shp0[3] = {c->shp[0], c->shp[1], c->shp[2]};
   auto is_shape = [](int v) {
     return v == WAVE_KERNEL_GMEM || v == WAVE_KERNEL_RING || v == WAVE_KERNEL_SHIFT ||
-           v == WAVE_KERNEL_PAIR;
+           v == WAVE_KERNEL_PAIR || v == WAVE_KERNEL_SEMI;
   };
   float best = 0.0f;
   std::array<int, 4> pick = {variant, ry0, nw0, zc0};

@@ -31,6 +31,7 @@ WAVE_TWO_STEP = 4
 WAVE_FIELD_U, WAVE_FIELD_UPREV, WAVE_FIELD_PHI, WAVE_FIELD_VP, WAVE_FIELD_ETA = 0, 1, 2, 3, 4
 WAVE_KERNEL_DIRECT, WAVE_KERNEL_STREAM, WAVE_KERNEL_STREAM2 = 0, 1, 2
 WAVE_KERNEL_GMEM, WAVE_KERNEL_RING, WAVE_KERNEL_SHIFT, WAVE_KERNEL_PAIR = 3, 4, 5, 6
+WAVE_KERNEL_SEMI, WAVE_KERNEL_PERSIST = 7, 8
 STORAGE = {"f32": WAVE_F32, "bf16": WAVE_BF16, "f16": WAVE_F16}
 
 EXPORTED = [

@@ -1,0 +1,83 @@
+"""Float32 against float64 at the benchmark configurations (CPU, oracle only).
+
+The GPU path equals the oracle's float32 mode bit for bit (the GPU parity
+tests, at full size too), so the distance of that mode from the float64 truth
+is the distance of the GPU result.  Running both modes on the 512^3 grid for
+the paper's 1000 steps (Sec. V-B, Table II) takes about an hour on eight
+cores, so `tests/golden/make_fp64_gap.py` stores the measured distances and
+samples of both final fields; these tests check what it stored against the
+bar (1e-5 relative L2 after N steps, on the whole field and the traces), and
+`WAVE_SLOW=1` re-derives the first checkpoint from the oracle.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = 1e-5
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def load(name):
+    p = os.path.join(GOLD, f"{name}_fp64_gap.json")
+    if not os.path.exists(p):
+        pytest.skip(f"{p} not generated yet")
+    meta = json.load(open(p))
+    arr = np.load(os.path.join(GOLD, f"{name}_fp64_gap.npz"))
+    return meta, arr
+
+
+def test_c2_float32_within_tolerance_of_float64_after_1000_steps():
+    meta, arr = load("c2")
+    # the stored run is the benchmark shot: 512^3, 20-cell layer, seed 1002,
+    # 1000 steps (config_c2's defaults)
+    s = synth.config_c2.__defaults__
+    assert (meta["grid"], meta["layer"], meta["steps"], meta["seed"]) == \
+        ([s[1]] * 3, s[2], s[0], s[3])
+    cps = meta["checkpoints"]
+    assert [c["step"] for c in cps] == list(range(100, 1001, 100))
+    for c in cps:
+        assert c["field_rel_l2"] <= TOL, c
+        assert c["traces_rel_l2"] <= TOL, c
+        assert c["field_l2_f64"] > 0 and np.isfinite(c["field_l2_f64"])
+    # the samples agree with the whole-field figures (same order of size)
+    d_plane = rel_l2(arr["plane_f32"], arr["plane_f64"])
+    d_tr = rel_l2(arr["traces_f32"], arr["traces_f64"])
+    assert d_plane <= TOL and d_tr <= TOL
+    assert arr["traces_f64"].shape[0] == 1000
+
+
+def test_c2_16bit_storage_distance_is_stated_and_bounded():
+    for kind, unit in (("bf16", 2.0 ** -8), ("f16", 2.0 ** -11)):
+        p = os.path.join(GOLD, f"c2_{kind}_fp64_gap.json")
+        if not os.path.exists(p):
+            continue
+        meta, arr = load(f"c2_{kind}")
+        n = meta["steps"]
+        bound = 2.0 * np.sqrt(n) * unit
+        for c in meta["checkpoints"]:
+            assert c["field_rel_l2"] <= 2.0 * np.sqrt(c["step"]) * unit, c
+        assert meta["field_rel_l2"] <= bound
+        assert rel_l2(arr["plane_f32"], arr["plane_f64"]) <= bound
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(os.environ.get("WAVE_SLOW") != "1", reason="about 6 minutes on 8 cores")
+def test_c2_first_checkpoint_regenerates():
+    import sys
+    sys.path.insert(0, GOLD)
+    import make_fp64_gap as g
+    meta, _ = load("c2")
+    s = synth.config_c2(steps=100)
+    _, _, _, _, cps = g.side_by_side(s, 100, "f32", 100)
+    assert cps[0]["field_rel_l2"] == meta["checkpoints"][0]["field_rel_l2"]
+    assert cps[0]["traces_rel_l2"] == meta["checkpoints"][0]["traces_rel_l2"]

@@ -35,9 +35,10 @@ def say(*a):
     sys.stdout.flush()
 
 
-def gpu_run(W, shot, steps, storage="f32", damping=True, kernel=None, state=None, eta=None):
+def gpu_run(W, shot, steps, storage="f32", damping=True, kernel=None, state=None, eta=None,
+            two_step=False):
     sh = W.shot_from_synth(shot, storage=storage, damping=damping, max_steps=max(steps, 1),
-                           eta=eta)
+                           eta=eta, two_step=two_step)
     if kernel is not None:
         sh.set_kernel(*kernel)
     if state is not None:
@@ -97,7 +98,9 @@ RAGGED = [
 
 KERNELS = [(W_, ry, nw, zc) for (W_, ry, nw, zc) in [
     (0, 1, 16, 0), (1, 1, 16, 0), (1, 1, 8, 0), (1, 2, 8, 0), (1, 2, 4, 0),
-    (1, 1, 16, 5), (1, 2, 8, 7), (1, 1, 8, 1), (1, 2, 4, 3)]]
+    (1, 1, 16, 5), (1, 2, 8, 7), (1, 1, 8, 1), (1, 2, 4, 3),
+    # the persistent launch of the same tiles
+    (8, 1, 16, 0), (8, 1, 8, 0), (8, 1, 16, 5), (8, 1, 8, 1)]]
 
 
 @pytest.mark.parametrize("case", RAGGED, ids=lambda c: "x".join(map(str, c[:3])) + f"_w{c[3]}")
@@ -206,14 +209,27 @@ def random_state(shot, seed):
 
 def test_c2_full_size_few_steps_bitwise(W):
     """512^3, 20-cell layer, layered model: every launch configuration the
-    benchmark's tuner can pick (tile instance and z-chunk length), 3 steps
+    benchmark's tuner can pick at this size -- the streaming tiles at their
+    z-chunk lengths, the persistent launch, two steps per launch, two points
+    per lane, and the paper's other code shapes it times (3-D 8x8x8 and
+    64x4x4, the LDS plane ring, the shifted register queue) -- 4 steps
     against the float32 oracle on every point."""
-    shot = synth.config_c2(steps=3)
+    shot = synth.config_c2(steps=4)
     st = random_state(shot, 11)
     o = oracle.run_shot(shot, precision="f32", state=st)
-    for k in [(1, 1, 16, 64), (1, 1, 8, 32), (1, 2, 8, 128), (1, 2, 4, 32)]:
-        say(f"case c2 512^3 3 steps kernel {k}")
-        assert_same(gpu_run(W, shot, 3, kernel=k, state=st), o, f"c2 512^3 {k}")
+    # wave_tune's candidates at 512^3: every compiled tile at the automatic
+    # chunk (64 planes), half and double; the persistent launch at 64 and 32;
+    # two steps per launch at 64, 32, 128; two points per lane (16 rows: 32
+    # and 64 planes, 8 rows: 64 and 128); the four code shapes
+    stream = [(1, ry, nw, z) for (ry, nw) in [(1, 16), (1, 8), (2, 8), (2, 4)] for z in (64, 32, 128)]
+    others = [(8, 1, 16, 64), (8, 1, 16, 32), (8, 1, 8, 64), (8, 1, 8, 32),
+              (2, 1, 16, 64), (2, 1, 16, 32), (2, 1, 16, 128),
+              (6, 1, 16, 32), (6, 1, 16, 64), (6, 1, 8, 64), (6, 1, 8, 128),
+              (3, 8, 8, 8), (3, 64, 4, 4), (4, 1, 16, 0), (5, 1, 16, 0)]
+    for k in stream + others:
+        say(f"case c2 512^3 4 steps kernel {k}")
+        assert_same(gpu_run(W, shot, 4, kernel=k, state=st, two_step=k[0] == 2), o,
+                    f"c2 512^3 {k}")
 
 
 def test_c3_size_few_steps_bitwise(W):
@@ -231,12 +247,13 @@ def test_c3_size_few_steps_bitwise(W):
                       rec=synth.receiver_line(n, c, w + 5), seed=0)
     say("case c3-size 1024^3 1 step: random state")
     st = random_state(shot, 12)
-    say("case c3-size 1024^3 1 step: GPU")
-    g = gpu_run(W, shot, 1, state=st)
     say("case c3-size 1024^3 1 step: oracle")
     o = oracle.run_shot(shot, steps=1, precision="f32", state=st)
-    say("case c3-size 1024^3 1 step: compare")
-    assert_same(g, o, "1024^3")
+    for k in (None, (8, 1, 16, 64)):
+        say(f"case c3-size 1024^3 1 step: GPU kernel {k or 'default'}")
+        g = gpu_run(W, shot, 1, state=st, kernel=k)
+        assert_same(g, o, f"1024^3 {k}")
+        del g
 
 
 def test_long_run_medium_grid_vs_oracles(W):

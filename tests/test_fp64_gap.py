@@ -81,3 +81,28 @@ def test_c2_first_checkpoint_regenerates():
     _, _, _, _, cps = g.side_by_side(s, 100, "f32", 100)
     assert cps[0]["field_rel_l2"] == meta["checkpoints"][0]["field_rel_l2"]
     assert cps[0]["traces_rel_l2"] == meta["checkpoints"][0]["traces_rel_l2"]
+
+
+def test_batch_and_serve_goldens_match_their_workloads():
+    """The float64 samples the benchmark compares its batched and served
+    results with belong to the shots of those workloads (grid, steps, seed),
+    hold the stated samples, and are finite and nonzero."""
+    specs = {"batch": [dict(nx=a, ny=b, nz=c, steps=st, seed=sd)
+                       for (a, b, c, st, sd) in synth.batch_shapes()],
+             "serve": synth.serve_requests()}
+    for name, spec in specs.items():
+        p = os.path.join(GOLD, f"{name}_fp64_gap.json")
+        if not os.path.exists(p):
+            continue
+        meta, arr = load(name)
+        ps, rs = meta["sample"]["plane_stride"], meta["sample"]["receiver_stride"]
+        assert meta["members"]
+        for e in meta["members"]:
+            s = spec[e["index"]]
+            assert e["grid"] == [s["nx"], s["ny"], s["nz"]] and e["steps"] == s["steps"]
+            assert e["seed"] == s["seed"] and e["plane_j"] == s["ny"] // 2
+            plane, tr = arr[f"{e['key']}_plane"], arr[f"{e['key']}_traces"]
+            assert plane.shape == (-(-s["nz"] // ps), -(-s["nx"] // ps))
+            assert tr.shape == (s["steps"], -(-s["nx"] // rs))
+            assert np.isfinite(plane).all() and np.abs(plane).max() > 0
+            assert np.isfinite(tr).all() and np.abs(tr).max() > 0

@@ -42,7 +42,8 @@ KERNELS = {0: ("k_sweep_direct", "direct", ("wave_kernels.hip", "wave_direct.h",
            5: ("k_sweep_shift", "shift", ("wave_shapes.hip", "wave_direct.h", "wave_point.h")),
            6: ("k_sweep_pair", "pair", ("wave_kernels_pair.hip", "wave_point.h")),
            7: ("k_sweep_stream", "semi", ("wave_kernels.hip", "wave_point.h")),
-           8: ("k_sweep_persist", "persist", ("wave_kernels.hip", "wave_point.h"))}
+           8: ("k_sweep_persist", "persist", ("wave_kernels.hip", "wave_point.h")),
+           9: ("k_sweep_stream", "shuffle", ("wave_kernels.hip", "wave_point.h"))}
 
 
 def kernel_source_sha(variant: int = 1) -> str:
@@ -66,6 +67,8 @@ def describe(cfg) -> str:
         return f"stream, z semi-stencil, 64x{nw} zchunk={zc}"
     if v == 8:
         return f"stream, persistent (one workgroup per CU), 64x{nw} zchunk={zc}"
+    if v == 9:
+        return f"stream, x neighbours by wavefront shuffles, 64x{nw} zchunk={zc}"
     if v in (4, 5):
         return f"2.5-D {'ring of 9 LDS planes' if v == 4 else 'LDS plane + shifted registers'} " \
                f"64x{nw} zchunk={zc}"
@@ -177,22 +180,32 @@ def build_shots(specs, threads=8):
 
 
 def copy_bandwidth(W, torch, nbytes=2 << 30, reps=10):
-    """Plain streaming copy (the measured-bandwidth reference)."""
-    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
-    dst = torch.empty_like(src)
+    """Plain streams (the measured-bandwidth references): copy (1 read, 1
+    write), read only, and three reads with one write (the access mix of an
+    inner point of the sweep); GB/s moved."""
+    a = torch.zeros(nbytes, dtype=torch.uint8, device="cuda:0")
+    b, c, d = torch.zeros_like(a), torch.zeros_like(a), torch.zeros_like(a)
     s = torch.cuda.current_stream()
-    for _ in range(2):
-        W.wave_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, s.cuda_stream)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(reps):
-        W.wave_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, s.cuda_stream)
-    e1.record(s)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    del src, dst
+    P = (a.data_ptr(), b.data_ptr(), c.data_ptr(), d.data_ptr())
+    legs = {"copy": (lambda: W.wave_stream_copy(P[3], P[0], nbytes, s.cuda_stream), 2.0),
+            "read": (lambda: W.wave_stream_mix(0, P[3], P[0], 0, 0, nbytes, s.cuda_stream), 1.0),
+            "read3_write1": (lambda: W.wave_stream_mix(1, P[3], P[0], P[1], P[2], nbytes,
+                                                       s.cuda_stream), 4.0)}
+    out = {}
+    for name, (fn, moved) in legs.items():
+        for _ in range(2):
+            assert fn() == 0
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = round(moved * nbytes / (ms / 1e3) / 1e9, 1)
+    del a, b, c, d
     torch.cuda.empty_cache()
-    return 2.0 * nbytes / (ms / 1e3) / 1e9
+    return out
 
 
 def plain_rate(W, torch, n, w, storage, steps, seed=1002, accuracy=True):
@@ -200,8 +213,8 @@ def plain_rate(W, torch, n, w, storage, steps, seed=1002, accuracy=True):
     kernel's algorithmic GB/s, and (with a golden for the grid) the error of
     a 1000-step run against float64."""
     import synth
-    shot = synth.config_c2(steps=steps + 20 + 64, n=n, w=w, seed=seed)
-    sh = W.shot_from_synth(shot, storage=storage, max_steps=steps + 20 + 50 + 64, two_step=True)
+    shot = synth.config_c2(steps=steps + 20 + 256, n=n, w=w, seed=seed)
+    sh = W.shot_from_synth(shot, storage=storage, max_steps=steps + 20 + 50 + 256, two_step=True)
     cfg = sh.tune(2)
     sh.step(max(0, 20 - sh.step_count))
     sh.sync()
@@ -276,8 +289,9 @@ def batched_rate(W, torch, count):
     gold = load_golden("batch")
     check = [e for e in gold[0]["members"] if e["index"] < count] if gold else []
     out = {"shots": count, "points_x_steps": work}
-    for storage in ("f32", "bf16"):
+    for storage in ("f32", "bf16", "f16"):
         members = [W.shot_from_synth(s, storage=storage) for s in shots]
+        alg = sum(m.sweep_bytes() * s.steps for m, s in zip(members, shots))
         b = W.Batch(storage=storage, max_shots=count)
         for s, m in zip(shots, members):
             b.add(m, s.steps)
@@ -296,7 +310,9 @@ def batched_rate(W, torch, count):
         for m in members:
             m.close()
         out[f"batched_{storage}"] = {"value": round(work / dt / 1e9, 3), "unit": "Gpoints/s",
-                                     "seconds": round(dt, 3), "tile": list(cfg)}
+                                     "seconds": round(dt, 3), "tile": list(cfg),
+                                     "sweep_bytes_algorithmic": alg,
+                                     "gbps_algorithmic_incl_tuning": round(alg / dt / 1e9, 1)}
         if errs:
             out[f"batched_{storage}"]["max_rel_l2_vs_fp64"] = max(errs.values())
             out[f"batched_{storage}"]["rel_l2_vs_fp64_per_shot"] = errs
@@ -410,7 +426,9 @@ def main():
                     help="skip the bf16, batched and serving measurements")
     ap.add_argument("--batch-shots", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=256)
-    ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 extras entry")
+    ap.add_argument("--extras", default="bf16,batched,serve,serve_low,shapes,large",
+                    help="comma-separated measurements beside the headline: bf16, batched, "
+                         "serve, serve_low, shapes, large (1024^3)")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the 1000-step runs compared with the float64 goldens")
     args = ap.parse_args()
@@ -428,11 +446,11 @@ def main():
 
     log(f"[bench] building workload {args.n}^3 w{args.w}")
     total = args.warmup + args.steps
-    shot = synth.config_c2(steps=total + 64, n=args.n, w=args.w)
+    shot = synth.config_c2(steps=total + 256, n=args.n, w=args.w)
     torch.cuda.synchronize()
     s0 = time.perf_counter()
     sh = W.shot_from_synth(shot, storage=args.storage,
-                           max_steps=total + 64 + args.roofline_steps,
+                           max_steps=total + 256 + args.roofline_steps,
                            two_step=not args.single_step)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - s0          # host-to-device set-up (vel over PCIe)
@@ -491,23 +509,31 @@ def main():
     accuracy = None if args.no_accuracy else c2_accuracy(W, shot, args.storage, cfg)
 
     extras = None
-    if not args.no_extras:
-        extras = {"bf16_plain": plain_rate(W, torch, args.n, args.w, "bf16", 200),
-                  "batched": batched_rate(W, torch, args.batch_shots),
-                  "serve": serve_run(W, torch, args.serve_requests),
-                  # the same stream at a quarter of the arrival rate, below
-                  # capacity: latency is then service time, not backlog
-                  "serve_below_capacity": serve_run(W, torch, args.serve_requests // 4,
-                                                    rate=5.0, check_errors=False),
-                  "code_shapes": shapes_rate(W, torch, args.n, args.w)}
-        if args.n == 512 and args.w == 20 and not args.no_large:
+    legs = [] if args.no_extras else args.extras.split(",")
+    if legs:
+        extras = {}
+        if "bf16" in legs:
+            extras["bf16_plain"] = plain_rate(W, torch, args.n, args.w, "bf16", 200)
+        if "batched" in legs:
+            extras["batched"] = batched_rate(W, torch, args.batch_shots)
+        if "serve" in legs:
+            extras["serve"] = serve_run(W, torch, args.serve_requests)
+        if "serve_low" in legs:
+            # the same stream at a quarter of the arrival rate, below
+            # capacity: latency is then service time, not backlog
+            extras["serve_below_capacity"] = serve_run(W, torch, args.serve_requests // 4,
+                                                       rate=5.0, check_errors=False)
+        if "shapes" in legs:
+            extras["code_shapes"] = shapes_rate(W, torch, args.n, args.w)
+        if "large" in legs and args.n == 512 and args.w == 20:
             # the large-domain configuration: 1024^3 with a 32-cell layer
             extras["large_1024cube_w32_f32"] = plain_rate(W, torch, 1024, 32, "f32", 100,
                                                           seed=1003)
 
-    copy_gbs = None if args.no_copy else copy_bandwidth(W, torch)
-    if copy_gbs:
-        log(f"[bench] stream copy {copy_gbs:.0f} GB/s")
+    streams = None if args.no_copy else copy_bandwidth(W, torch)
+    copy_gbs = None if streams is None else streams["copy"]
+    if streams:
+        log(f"[bench] plain streams GB/s: {streams}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -538,7 +564,14 @@ def main():
                      "kernel": KERNELS[variant][0], "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_kernel_ms": round(avg_ms, 5)},
         "accuracy": accuracy,
-        "copy_gbps": None if copy_gbs is None else round(copy_gbs, 1),
+        "copy_gbps": copy_gbs,
+        "empirical_roofline": None if streams is None else {
+            "unit": "GB/s", **streams,
+            "sweep_traffic_gbps": None if traffic is None else round(traffic / (avg_ms / 1e3) / 1e9, 1),
+            "note": "plain streams on this GPU (copy; read only; three reads and one write, the "
+                    "mix of an inner point); sweep_traffic_gbps = the sweep's measured HBM "
+                    "bytes (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated) per launch over its "
+                    "average launch time"},
         "host_io": {"setup_s": round(setup_s, 4), "trace_readout_s": round(readout_s, 4),
                     "value_incl_host_io": round(pts * args.steps / (ms / 1e3 + setup_s + readout_s) / 1e9, 3),
                     "note": "value with the set-up (velocity upload, vp) and the trace read-out "

@@ -257,15 +257,6 @@ int wave_energy(wave_ctx *ctx, double *out);
                                 waves_per_group = ty in {8, 16}, zchunk as
                                 for WAVE_KERNEL_STREAM; not with an eta
                                 array (EINVAL)                            */
-#define WAVE_KERNEL_PERSIST 8 /* the streaming kernel (the same tile code,
-                                so the same results bit for bit) as one
-                                persistent launch: one workgroup per CU,
-                                each sweeping a fixed, rotated share of the
-                                (tile, z chunk) items one after the other,
-                                so no CU waits for a new workgroup to be
-                                dispatched; rows_per_wave = 1,
-                                waves_per_group in {8, 16}, zchunk as for
-                                WAVE_KERNEL_STREAM                        */
 #define WAVE_KERNEL_SEMI 7   /* the streaming kernel with the z terms of
                                 Eq. 3 summed by the semi-stencil (Sec. IV,
                                 "Semi-stencil"), along the streaming axis:
@@ -282,12 +273,33 @@ int wave_energy(wave_ctx *ctx, double *out);
                                 waves_per_group in {8, 16}, zchunk as for
                                 WAVE_KERNEL_STREAM; not with an eta array
                                 (EINVAL)                                 */
+#define WAVE_KERNEL_PERSIST 8 /* the streaming kernel (the same tile code,
+                                so the same results bit for bit) as one
+                                persistent launch: one workgroup per CU,
+                                each sweeping a fixed, rotated share of the
+                                (tile, z chunk) items one after the other,
+                                so no CU waits for a new workgroup to be
+                                dispatched; rows_per_wave = 1,
+                                waves_per_group in {8, 16}, zchunk as for
+                                WAVE_KERNEL_STREAM                        */
+#define WAVE_KERNEL_SHUFFLE 9 /* the streaming kernel with the x neighbours
+                                exchanged by wavefront shuffles
+                                (ds_bpermute across the lanes of a row
+                                segment, the x halo loaded by the segment's
+                                end lanes) instead of read from the staged
+                                plane; the same values, so the same results
+                                bit for bit; rows_per_wave = 1,
+                                waves_per_group in {8, 16}, zchunk as for
+                                WAVE_KERNEL_STREAM                        */
 
 /* Select the sweep kernel and its tile: rows_per_wave (RY) and
  * waves_per_group (NW) give a 64 x (RY*NW) xy tile; zchunk is the number of
  * z planes one workgroup streams (0 = automatic).  Only compiled
  * combinations are accepted (EINVAL otherwise): (RY, NW) in
- * {(1,16), (1,8), (2,8), (2,4)}; the default is (1,16).  The streaming
+ * {(1,16), (1,8), (2,8), (2,4)}, and (2,16) (64 x 32 tiles) without an eta
+ * array.  The default is WAVE_KERNEL_PERSIST with (1,16) tiles and its
+ * automatic chunk (half the streaming kernel's), or WAVE_KERNEL_STREAM with
+ * (1,16) where the CU count cannot be queried.  The streaming
  * kernel addresses a chunk's planes with 32-bit offsets, so zchunk is cut
  * to what keeps zchunk + 8 float planes below 2 GiB; a grid whose single
  * plane is too large for that runs the direct kernel.  With
@@ -300,12 +312,14 @@ int wave_set_kernel(wave_ctx *ctx, int32_t variant, int32_t rows_per_wave,
                     int32_t waves_per_group, int32_t zchunk);
 
 /* Autotuner: advance the simulation by one untimed and `trial_steps` timed
- * real steps under each compiled tile shape and a few z-chunk lengths, and,
- * with WAVE_TWO_STEP, under the two-step kernel with a few z-chunk lengths
- * (trial_steps rounded up to even there), under the two-points-per-lane
- * kernel (both tile heights, two z-chunk lengths; not with an eta array),
- * then under four of the paper's other code shapes (WAVE_KERNEL_GMEM 8x8x8
- * and 64x4x4, RING and SHIFT with 16 rows).  Every candidate computes
+ * real steps under the persistent launch (16 and 8 rows, two z-chunk
+ * lengths), each compiled streaming tile shape at a few z-chunk lengths,
+ * with WAVE_TWO_STEP the two-step kernel with a few z-chunk lengths
+ * (trial_steps rounded up to even there), the two-points-per-lane kernel
+ * (both tile heights, two z-chunk lengths; not with an eta array), the
+ * shuffle kernel (both tile heights), then four of the paper's other code
+ * shapes (WAVE_KERNEL_GMEM 8x8x8 and 64x4x4, RING and SHIFT with 16 rows);
+ * never WAVE_KERNEL_SEMI, which rounds differently.  Every candidate computes
  * identical results, so the trials are ordinary steps of the run.  Each is
  * timed with HIP events; the fastest per step is kept (a candidate later in
  * the list must be at least 1.5 % faster to replace an earlier one, so
@@ -336,6 +350,16 @@ double wave_sweep_bytes(const wave_ctx *ctx);
  * aligned) with a plain streaming kernel on `hip_stream`: the reference
  * point for measured memory bandwidth.  Does not wait. */
 int wave_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+/* Plain streams with other access mixes, the measured ceilings beside the
+ * copy (an empirical roofline in the sense of Sec. V-C's ERT figures):
+ * kind 0 reads `bytes` at a (dst: a 4-byte device sink, written only in a
+ * case that does not occur, so the loads stay); kind 1 writes
+ * dst = a + b c over `bytes` each (float4 words), the three-reads-one-write
+ * mix of an inner point of the sweep.  16-byte aligned pointers, bytes a
+ * multiple of 16 (EINVAL otherwise).  Does not wait. */
+int wave_stream_mix(int32_t kind, void *dst, const void *a, const void *b, const void *c,
+                    size_t bytes, void *hip_stream);
 
 /* ---- many shots per launch (batching) ------------------------------------------ */
 

@@ -132,12 +132,18 @@ struct EnergyArgs {
 hipError_t launch_sweep_direct(const SweepArgs& a, int storage, hipStream_t s);
 hipError_t launch_sweep_stream(const SweepArgs& a, int storage, int ry, int nw,
                                int zchunk, hipStream_t s);
-bool stream_config_supported(int ry, int nw);
+// Compiled tiles (rows_per_wave, waves_per_group); 2 x 16 (64 x 32 tiles)
+// only for contexts without a per-point eta array.
+bool stream_config_supported(int ry, int nw, bool eta_array);
 // The streaming kernel as one persistent launch of `groups` workgroups (a
 // multiple of 8; one per CU), each sweeping its share of the tiles in turn.
 // Tiles 64 x nw, ry = 1, nw in {8, 16}.
 hipError_t launch_sweep_persist(const SweepArgs& a, int storage, int ry, int nw, int zchunk,
                                 int groups, hipStream_t s);
+// The streaming kernel with the x neighbours exchanged by wavefront shuffles
+// (ds_bpermute) instead of read from the staged plane (64 x nw tiles, nw in
+// {8, 16}; the same results bit for bit).
+hipError_t launch_sweep_shuffle(const SweepArgs& a, int storage, int nw, int zchunk, hipStream_t s);
 // The streaming kernel with the z terms summed by the semi-stencil (64 x nw
 // tiles, nw in {8, 16}; default-profile tables or damping off only).
 hipError_t launch_sweep_semi(const SweepArgs& a, int storage, int nw, int zchunk, hipStream_t s);
@@ -174,14 +180,19 @@ hipError_t launch_sweep_batch_pair(const BatchShot* shots, BatchState* state, in
                                    int64_t total_blocks, int storage, int ty, hipStream_t s);
 hipError_t launch_energy(const EnergyArgs& a, int storage, hipStream_t s);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// kind 0: read a (bytes), d a 4-byte sink; kind 1: d = a + b c over bytes each.
+hipError_t launch_stream_mix(int kind, void* d, const void* a, const void* b, const void* c,
+                             size_t bytes, hipStream_t s);
 // Scatter a compact [nz][ny][nx] float field into a padded array whose
 // element (0, 0, 0) is at dst; with dt > 0 store fl32((v dt)^2) instead of v.
 hipError_t launch_setup_field(float* dst, const float* src, int nx, int ny, int nz, int pitch,
                               int64_t plane, double dt, hipStream_t s);
 int stream_chunk_count(int nz, int w, int zchunk, bool damping);
 int stream_tiles_y(int ny, int ry, int nw);
+// eta_array: some member holds a per-point eta array.
 hipError_t launch_sweep_batch(const BatchShot* shots, BatchState* state, int nshots,
-                              int64_t total_blocks, int storage, int ry, int nw, hipStream_t s);
+                              int64_t total_blocks, int storage, int ry, int nw, bool eta_array,
+                              hipStream_t s);
 hipError_t launch_inject_batch(const BatchShot* shots, BatchState* state, int nshots,
                                int storage, hipStream_t s);
 

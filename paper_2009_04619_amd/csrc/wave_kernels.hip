@@ -75,6 +75,13 @@ struct Slots {
   bool lay[RY];      // a damping-layer point
   bool phl[RY];      // phi is read and written back here: a layer point, or an
                      // inner point sharing a 128-byte line with an x-wall one
+  // x neighbours by wavefront shuffles (XS): the lane's position in its row
+  // segment of xw lanes (64, or 32 in a tile holding an x wall), and the
+  // in-plane offset of the x-halo cell this lane loads for its row segment
+  // (lanes 0..3: the 4 cells right of the segment, lanes xw-4..xw-1: the 4
+  // cells left of it; kHaloGhost for the others and for ghost cells)
+  int xli, xw;
+  uint32_t xho[RY];
 };
 
 // Halo offset marking a ghost cell (never a real in-plane offset).
@@ -107,7 +114,11 @@ typedef const float __attribute__((address_space(4))) CFloat;
 // kernels by rounding only.  The phi update is unchanged (its gradient
 // keeps the x, y, z order: the z difference u(p+1) - u(p-1) is added the
 // plane after p was staged).  Default-profile tables only (no eta array).
-template <class S, int RY, int NW, int EM, bool ZS = false>
+// XS: the x neighbours come from wavefront shuffles (ds_bpermute) of the
+// lanes' own values instead of the staged plane; a lane at the end of its row
+// segment takes the x-halo value another lane of the segment loaded.  The
+// values, and so the results, are the same as from LDS.
+template <class S, int RY, int NW, int EM, bool ZS = false, bool XS = false>
 __device__ __forceinline__ void stream_loop(const SweepArgs& a,
                                             float (*sm)[(RY * NW + 2 * kR) * (kTX + 2 * kR) + 64],
                                             const Slots<RY>& sl, const int* hl, const uint32_t* ho,
@@ -127,6 +138,7 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
   constexpr bool LAYER = EM != 0;
   constexpr bool EARR = EM == 1;
   static_assert(!ZS || EM != 1, "the z semi-stencil takes the default profile's tables only");
+  static_assert(!(ZS && XS), "one variant at a time");
   constexpr int ZD = ZS ? kR : 0;  // planes an output trails the staged plane
 
   const int64_t Q = a.plane;
@@ -204,6 +216,36 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
   // phi gradient of z-3..z), and dq_z of the staged planes
   float A[ZS ? 4 : 1][RY], F[ZS ? 4 : 1][RY], G[ZS && LAYER ? 4 : 1][RY];
   float dzs[ZS ? NR : 1] = {};
+  // XS: the x-halo values of the row segments, per operand slot, and the
+  // shuffle sources: for +m the lane reads lane (li + m) mod xw of its segment
+  // from a register that holds, in lanes li < m, the x-halo value (the right
+  // halo sits in lanes 0..3); for -m lane (li - m) mod xw of a register that
+  // holds the left halo in lanes li >= xw - m
+  float hx[XS ? NR : 1][RY];
+  uint32_t xhe[XS ? RY : 1];
+  int xap[XS ? kR : 1], xam[XS ? kR : 1];
+  bool xcp[XS ? kR : 1], xcm[XS ? kR : 1];
+  if constexpr (XS) {
+    const int lane = threadIdx.x & 63;
+    const int base = lane & ~(sl.xw - 1);
+#pragma unroll
+    for (int m = 1; m <= kR; ++m) {
+      xap[m - 1] = 4 * (base | ((sl.xli + m) & (sl.xw - 1)));
+      xam[m - 1] = 4 * (base | ((sl.xli - m) & (sl.xw - 1)));
+      xcp[m - 1] = sl.xli < m;
+      xcm[m - 1] = sl.xli >= sl.xw - m;
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) xhe[r] = sl.xho[r] == kHaloGhost ? kOOB : sl.xho[r] * ES;
+  }
+  // x neighbours (m = 1..4, +m and -m) of u value c with row-segment halo h
+  auto xshuffle = [&](float c, float h, float (&xp)[kR], float (&xm)[kR]) {
+#pragma unroll
+    for (int m = 0; m < kR; ++m) {
+      xp[m] = __int_as_float(__builtin_amdgcn_ds_bpermute(xap[m], __float_as_int(xcp[m] ? h : c)));
+      xm[m] = __int_as_float(__builtin_amdgcn_ds_bpermute(xam[m], __float_as_int(xcm[m] ? h : c)));
+    }
+  };
 
   // prologue: u(zb-4 .. zb+3+PD) into ring slots 0 .. L-2, operands of planes
   // zb .. zb+PD-1 into operand slots 0 .. PD-1, eta(zb-1 .. zb+PD) into eta
@@ -217,20 +259,27 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
 #pragma unroll
   for (int j = 0; j < PD; ++j) {
     // operands of the output plane zb - ZD + j, halo of the staged plane zb + j
+    // (ZS: output planes before the chunk are never written; their operand
+    // loads take an out-of-range offset and fetch nothing)
     const uint32_t kp = (uint32_t)min(j + kR - ZD, zlast);
     const uint32_t se = kp * pe, s4 = kp * p4;
     const uint32_t sh = (uint32_t)min(j + kR, zlast) * pe;
+    const bool none = ZS && j < ZD;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      pv[j][r] = S::bld1(rn, vo[r], se);
-      vv[j][r] = bld1_f32(rv, vo4[r], s4);
+      pv[j][r] = S::bld1(rn, none ? kOOB : vo[r], se);
+      vv[j][r] = bld1_f32(rv, none ? kOOB : vo4[r], s4);
     }
 #pragma unroll
     for (int k = 0; k < HPT; ++k) hh[j][k] = S::bld(ru, hoe[k], sh);
+    if constexpr (XS) {
+#pragma unroll
+      for (int r = 0; r < RY; ++r) hx[j][r] = S::bld(ru, xhe[r], sh);
+    }
     if (ZS && LAYER) dzs[j] = dqzt[min(zb + j, a.nz - 1)];
     if (LAYER) {
 #pragma unroll
-      for (int r = 0; r < RY; ++r) ph[j][r] = bld1_f32(rph, fo[r], s4);
+      for (int r = 0; r < RY; ++r) ph[j][r] = bld1_f32(rph, none ? kOOB : fo[r], s4);
     }
     if (EM == 2) {
       const int zt = zb - kR + (int)kp;
@@ -289,18 +338,23 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
       const uint32_t kh = (uint32_t)min(kz + PD, zlast);
       const uint32_t kp = (uint32_t)min(kz - ZD + PD, zlast);
       const uint32_t se = kp * pe, s4 = kp * p4, sh = kh * pe;
+      const bool none = ZS && kz - ZD + PD < kR;  // an output plane before the chunk
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
         q[(Sl + L - 1) % L][r] = S::bld(ru, vo[r], sh + 4u * pe);
-        pv[BP][r] = S::bld1(rn, vo[r], se);
-        vv[BP][r] = bld1_f32(rv, vo4[r], s4);
+        pv[BP][r] = S::bld1(rn, none ? kOOB : vo[r], se);
+        vv[BP][r] = bld1_f32(rv, none ? kOOB : vo4[r], s4);
       }
 #pragma unroll
       for (int k = 0; k < HPT; ++k) hh[BP][k] = S::bld(ru, hoe[k], sh);
+      if constexpr (XS) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r) hx[BP][r] = S::bld(ru, xhe[r], sh);
+      }
       if (ZS && LAYER) dzs[BP] = dqzt[min(zb - kR + (int)kh, a.nz - 1)];
       if (LAYER) {
 #pragma unroll
-        for (int r = 0; r < RY; ++r) ph[BP][r] = bld1_f32(rph, fo[r], s4);
+        for (int r = 0; r < RY; ++r) ph[BP][r] = bld1_f32(rph, none ? kOOB : fo[r], s4);
       }
       if (EM == 2) {
         const int zt = zb - kR + (int)kp;
@@ -396,9 +450,19 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
       for (int r = 0; r < RY; ++r) {
         const float* row = s + sl.ls[r];
         const float c = q[(Sl + kR) % L][r];
+        float xp[kR], xm[kR];
+        if constexpr (XS) {
+          xshuffle(c, hx[B][r], xp, xm);
+        } else {
+  #pragma unroll
+          for (int m = 0; m < kR; ++m) {
+            xp[m] = row[m + 1];
+            xm[m] = row[-(m + 1)];
+          }
+        }
         float lap = a.c[0] * c;
   #pragma unroll
-        for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(a.c[m], row[m] + row[-m], lap);
+        for (int m = 1; m <= kR; ++m) lap = __builtin_fmaf(a.c[m], xp[m - 1] + xm[m - 1], lap);
   #pragma unroll
         for (int m = 1; m <= kR; ++m)
           lap = __builtin_fmaf(a.c[4 + m], row[m * LW] + row[-m * LW], lap);
@@ -429,7 +493,7 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
           // only written back)
           const float phv = sl.lay[r] ? ph[B][r] : 0.0f;
           res = upd_layer(c, pu, vp, lap, e, phv);
-          const float nph = upd_phi(phv, e, gx, row[1] - row[-1], gy, row[LW] - row[-LW], gz,
+          const float nph = upd_phi(phv, e, gx, xp[0] - xm[0], gy, row[LW] - row[-LW], gz,
                                     q[(Sl + kR + 1) % L][r] - q[(Sl + kR - 1) % L][r]);
           // stored for every point; points where phi is not touched have an
           // out-of-range offset, so their store is dropped
@@ -459,7 +523,10 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
   }
 }
 
-template <class S, int RY, int NW, bool ZS = false>
+// EA: the kernel instance also serves contexts with a per-point eta array
+// (its loop holds more registers; contexts with the default profile's tables
+// run instances without it).
+template <class S, int RY, int NW, bool ZS = false, bool EA = false, bool XS = false>
 __device__ __forceinline__ void stream_tile(const SweepArgs& a,
                                             float (*sm)[(RY * NW + 2 * kR) * (kTX + 2 * kR) + 64],
                                             int x0, int y0, int zb, int ze, bool cap) {
@@ -508,6 +575,17 @@ __device__ __forceinline__ void stream_tile(const SweepArgs& a,
     sl.phl[r] = sl.lay[r] || (damp && sl.valid[r] && a.w > 0 &&
                               (x < ((a.w + 31) & ~31) || x >= ((a.nx - a.w) & ~31)));
     any_lay = any_lay || sl.lay[r];
+    if (XS) {
+      // the x-halo cell this lane loads for its row segment
+      sl.xw = split ? 32 : 64;
+      sl.xli = col & (sl.xw - 1);
+      const int xs0 = x - sl.xli;  // first column of the segment
+      const int xh = sl.xli < kR ? xs0 + sl.xw + sl.xli
+                     : sl.xli >= sl.xw - kR ? xs0 - kR + (sl.xli - (sl.xw - kR))
+                                            : -1;
+      sl.xho[r] = (xh < 0 || xh >= a.nx || y >= a.ny) ? kHaloGhost
+                                                       : (uint32_t)((y + kR) * P + xh);
+    }
   }
 
   // halo bookkeeping: LDS index and in-plane element offset
@@ -537,8 +615,10 @@ __device__ __forceinline__ void stream_tile(const SweepArgs& a,
       gx = x0 + lane;
     }
     // ghost cells (outside the grid) and the dump row are zero or unused:
-    // no load (a line of row padding would be fetched for 16 bytes)
-    const bool ghost = h >= NHALO || gx < 0 || gx >= a.nx || gy < 0 || gy >= a.ny;
+    // no load (a line of row padding would be fetched for 16 bytes); with
+    // XS the x halo is not staged (the row segments load it themselves)
+    const bool ghost = h >= NHALO || gx < 0 || gx >= a.nx || gy < 0 || gy >= a.ny ||
+                       (XS && h >= NYH);
     gy = min(gy, ylast);
     hl[k] = rl * LW + cl;
     ho[k] = ghost ? kHaloGhost : (uint32_t)((gy + kR) * P + gx);
@@ -546,19 +626,23 @@ __device__ __forceinline__ void stream_tile(const SweepArgs& a,
 
   // wavefront-uniform choice of the loop
   if (!__any(any_lay))
-    stream_loop<S, RY, NW, 0, ZS>(a, sm, sl, hl, ho, zb, ze);
-  else if (ZS || a.etab)
-    stream_loop<S, RY, NW, 2, ZS>(a, sm, sl, hl, ho, zb, ze);
+    stream_loop<S, RY, NW, 0, ZS, XS>(a, sm, sl, hl, ho, zb, ze);
+  else if (!EA || a.etab)
+    stream_loop<S, RY, NW, 2, ZS, XS>(a, sm, sl, hl, ho, zb, ze);
   else
-    stream_loop<S, RY, NW, ZS ? 2 : 1, ZS>(a, sm, sl, hl, ho, zb, ze);
+    stream_loop<S, RY, NW, EA && !ZS ? 1 : 2, ZS, XS>(a, sm, sl, hl, ho, zb, ze);
 }
+
+// Occupancy: one-row tiles and 16-wavefront workgroups run 4 wavefronts per
+// SIMD (at most 128 VGPRs), the other two-row tiles 2.
+#define WAVE_STREAM_WPS(RY, NW) ((RY) == 1 || (NW) == 16 ? WAVE_STREAM_WAVES_PER_SIMD : 2)
 
 // Occupancy target in wavefronts per SIMD for one-row tiles.
 #ifndef WAVE_STREAM_WAVES_PER_SIMD
 #define WAVE_STREAM_WAVES_PER_SIMD 4
 #endif
-template <class S, int RY, int NW, bool ZS = false>
-__global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) void k_sweep_stream(
+template <class S, int RY, int NW, bool ZS = false, bool EA = false, bool XS = false>
+__global__ __launch_bounds__(64 * NW, WAVE_STREAM_WPS(RY, NW)) void k_sweep_stream(
     SweepArgs a, int tiles_x, int tiles_y, int zchunk) {
   constexpr int TY = RY * NW;
   constexpr int LSZ = (TY + 2 * kR) * (kTX + 2 * kR) + 64;  // + a dump row
@@ -585,7 +669,7 @@ __global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) 
   const bool damp = a.damping != 0;
   const ChunkInfo c = chunk_of(ch, a.nz, a.w, zchunk, damp);
   if (c.zb >= c.ze) return;
-  stream_tile<S, RY, NW, ZS>(a, sm, x0, y0, c.zb, c.ze, damp && c.cap);
+  stream_tile<S, RY, NW, ZS, EA, XS>(a, sm, x0, y0, c.zb, c.ze, damp && c.cap);
 }
 
 // The same sweep as one persistent launch: 8 G workgroups (G per XCD, one
@@ -600,8 +684,8 @@ __global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) 
 // workgroups.  Each tile is swept by the same code as in k_sweep_stream, so
 // results are the same bit for bit.  No workgroup waits for the end of
 // another to start its next tile, and no atomics are needed.
-template <class S, int RY, int NW>
-__global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) void k_sweep_persist(
+template <class S, int RY, int NW, bool EA = false>
+__global__ __launch_bounds__(64 * NW, WAVE_STREAM_WPS(RY, NW)) void k_sweep_persist(
     SweepArgs a, int tiles_x, int tiles_y, int zchunk) {
   constexpr int TY = RY * NW;
   constexpr int LSZ = (TY + 2 * kR) * (kTX + 2 * kR) + 64;
@@ -621,7 +705,7 @@ __global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) 
     const int ty = ((xcd + 3 * ch) & 7) * sh + t2 % sh;
     const ChunkInfo c = chunk_of(ch, a.nz, a.w, zchunk, damp);
     if (ty >= tiles_y || c.zb >= c.ze) continue;
-    stream_tile<S, RY, NW, false>(a, sm, tx * kTX, ty * TY, c.zb, c.ze, damp && c.cap);
+    stream_tile<S, RY, NW, false, EA>(a, sm, tx * kTX, ty * TY, c.zb, c.ze, damp && c.cap);
     __syncthreads();  // the next tile's staging reuses the LDS planes
   }
 }
@@ -631,8 +715,8 @@ __global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) 
 // located in the members' block ranges, the member's parity picks u^n and
 // u^{n-1}, and the tile is swept exactly as in a single-shot launch.  Members that have taken their steps for this run exit
 // at once, so a captured sequence of launches stays valid as members finish.
-template <class S, int RY, int NW>
-__global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) void k_sweep_batch(
+template <class S, int RY, int NW, bool EA = false>
+__global__ __launch_bounds__(64 * NW, WAVE_STREAM_WPS(RY, NW)) void k_sweep_batch(
     const BatchShot* __restrict__ shots, const BatchState* __restrict__ state, int nshots) {
   constexpr int TY = RY * NW;
   constexpr int LSZ = (TY + 2 * kR) * (kTX + 2 * kR) + 64;
@@ -666,7 +750,7 @@ __global__ __launch_bounds__(64 * NW, RY == 1 ? WAVE_STREAM_WAVES_PER_SIMD : 2) 
   const bool damp = a.damping != 0;
   const ChunkInfo c = chunk_of(ch, a.nz, a.w, b.zchunk, damp);
   if (c.zb >= c.ze) return;
-  stream_tile<S, RY, NW>(a, sm, x0, y0, c.zb, c.ze, damp && c.cap);
+  stream_tile<S, RY, NW, false, EA>(a, sm, x0, y0, c.zb, c.ze, damp && c.cap);
 }
 
 // One workgroup per member: source add, receiver sample, then the member's
@@ -819,6 +903,29 @@ __global__ __launch_bounds__(256) void k_stream_copy(const float4* __restrict__ 
   if (i < n) d[i] = s[i];
 }
 
+// Plain streams with other access mixes (the measured ceilings an access
+// pattern can reach): read only (a sum that is stored only if it hits an
+// impossible value, which keeps the loads), and three reads with one write,
+// the mix of an inner point of the sweep (u^n, u^{n-1}, vp in; u^{n+1} out).
+__global__ __launch_bounds__(256) void k_stream_read(const float4* __restrict__ s,
+                                                     float* __restrict__ sink, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const float4 v = i < n ? s[i] : float4{0.0f, 0.0f, 0.0f, 0.0f};
+  const float t = (v.x + v.y) + (v.z + v.w);
+  if (t == -1.5e38f) sink[0] = t;
+}
+__global__ __launch_bounds__(256) void k_stream_mix31(const float4* __restrict__ a,
+                                                      const float4* __restrict__ b,
+                                                      const float4* __restrict__ c,
+                                                      float4* __restrict__ d, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    const float4 x = a[i], y = b[i], z = c[i];
+    d[i] = float4{__builtin_fmaf(y.x, z.x, x.x), __builtin_fmaf(y.y, z.y, x.y),
+                  __builtin_fmaf(y.z, z.z, x.z), __builtin_fmaf(y.w, z.w, x.w)};
+  }
+}
+
 template <class S>
 hipError_t sweep_direct_t(const SweepArgs& a, hipStream_t st) {
   dim3 block(kTX, 4, 1);
@@ -827,7 +934,7 @@ hipError_t sweep_direct_t(const SweepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <class S, int RY, int NW, bool ZS = false>
+template <class S, int RY, int NW, bool ZS = false, bool EA = false, bool XS = false>
 hipError_t sweep_stream_t(const SweepArgs& a, int zchunk, hipStream_t st) {
   constexpr int TY = RY * NW;
   const int tiles_x = (a.nx + kTX - 1) / kTX;
@@ -837,12 +944,12 @@ hipError_t sweep_stream_t(const SweepArgs& a, int zchunk, hipStream_t st) {
   // tile rows padded to a multiple of 8 (see k_sweep_stream)
   const int64_t blocks = (int64_t)tiles_x * 8 * ((tiles_y + 7) / 8) * chunks;
   if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_sweep_stream<S, RY, NW, ZS>), dim3((unsigned)blocks), dim3(64 * NW), 0, st,
-                     a, tiles_x, tiles_y, zchunk);
+  hipLaunchKernelGGL((k_sweep_stream<S, RY, NW, ZS, EA, XS>), dim3((unsigned)blocks), dim3(64 * NW),
+                     0, st, a, tiles_x, tiles_y, zchunk);
   return hipGetLastError();
 }
 
-template <class S, int RY, int NW>
+template <class S, int RY, int NW, bool EA = false>
 hipError_t sweep_persist_t(const SweepArgs& a, int zchunk, int groups, hipStream_t st) {
   constexpr int TY = RY * NW;
   const int tiles_x = (a.nx + kTX - 1) / kTX;
@@ -852,25 +959,33 @@ hipError_t sweep_persist_t(const SweepArgs& a, int zchunk, int groups, hipStream
   const int chunks = chunk_count(a.nz, a.w, zchunk, a.damping != 0);
   const int64_t blocks = (int64_t)tiles_x * 8 * ((tiles_y + 7) / 8) * chunks;
   if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_sweep_persist<S, RY, NW>), dim3((unsigned)groups), dim3(64 * NW), 0, st, a,
-                     tiles_x, tiles_y, zchunk);
+  hipLaunchKernelGGL((k_sweep_persist<S, RY, NW, EA>), dim3((unsigned)groups), dim3(64 * NW), 0, st,
+                     a, tiles_x, tiles_y, zchunk);
   return hipGetLastError();
 }
 
 template <class S>
 hipError_t sweep_stream_s(const SweepArgs& a, int ry, int nw, int zchunk, hipStream_t st) {
+  if (a.eta) {  // a per-point eta array
+    if (ry == 1 && nw == 16) return sweep_stream_t<S, 1, 16, false, true>(a, zchunk, st);
+    if (ry == 1 && nw == 8) return sweep_stream_t<S, 1, 8, false, true>(a, zchunk, st);
+    if (ry == 2 && nw == 8) return sweep_stream_t<S, 2, 8, false, true>(a, zchunk, st);
+    if (ry == 2 && nw == 4) return sweep_stream_t<S, 2, 4, false, true>(a, zchunk, st);
+    return hipErrorInvalidValue;
+  }
   if (ry == 1 && nw == 16) return sweep_stream_t<S, 1, 16>(a, zchunk, st);
   if (ry == 1 && nw == 8) return sweep_stream_t<S, 1, 8>(a, zchunk, st);
   if (ry == 2 && nw == 8) return sweep_stream_t<S, 2, 8>(a, zchunk, st);
   if (ry == 2 && nw == 4) return sweep_stream_t<S, 2, 4>(a, zchunk, st);
+  if (ry == 2 && nw == 16) return sweep_stream_t<S, 2, 16>(a, zchunk, st);
   return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-bool stream_config_supported(int ry, int nw) {
+bool stream_config_supported(int ry, int nw, bool eta_array) {
   return (ry == 1 && nw == 16) || (ry == 1 && nw == 8) || (ry == 2 && nw == 8) ||
-         (ry == 2 && nw == 4);
+         (ry == 2 && nw == 4) || (ry == 2 && nw == 16 && !eta_array);
 }
 
 int stream_zchunk_limit(int64_t plane) {
@@ -912,9 +1027,14 @@ hipError_t launch_sweep_stream(const SweepArgs& a, int storage, int ry, int nw, 
 hipError_t launch_sweep_persist(const SweepArgs& a, int storage, int ry, int nw, int zchunk,
                                 int groups, hipStream_t s) {
   if (zchunk <= 0) return hipErrorInvalidValue;
-#define WAVE_PERSIST_CASE(S_)                                                         \
-  if (ry == 1 && nw == 16) return sweep_persist_t<S_, 1, 16>(a, zchunk, groups, s); \
-  if (ry == 1 && nw == 8) return sweep_persist_t<S_, 1, 8>(a, zchunk, groups, s);   \
+#define WAVE_PERSIST_CASE(S_)                                                              \
+  if (a.eta) {                                                                               \
+    if (ry == 1 && nw == 16) return sweep_persist_t<S_, 1, 16, true>(a, zchunk, groups, s);  \
+    if (ry == 1 && nw == 8) return sweep_persist_t<S_, 1, 8, true>(a, zchunk, groups, s);    \
+    return hipErrorInvalidValue;                                                             \
+  }                                                                                          \
+  if (ry == 1 && nw == 16) return sweep_persist_t<S_, 1, 16>(a, zchunk, groups, s);          \
+  if (ry == 1 && nw == 8) return sweep_persist_t<S_, 1, 8>(a, zchunk, groups, s);            \
   return hipErrorInvalidValue;
   switch (storage) {
     case 0: { WAVE_PERSIST_CASE(StF32) }
@@ -922,6 +1042,23 @@ hipError_t launch_sweep_persist(const SweepArgs& a, int storage, int ry, int nw,
     case 2: { WAVE_PERSIST_CASE(StF16) }
   }
 #undef WAVE_PERSIST_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep_shuffle(const SweepArgs& a, int storage, int nw, int zchunk, hipStream_t s) {
+  if (zchunk <= 0 || (nw != 8 && nw != 16)) return hipErrorInvalidValue;
+#define WAVE_XS_CASE(S_)                                                                  \
+  if (a.eta)                                                                              \
+    return nw == 16 ? sweep_stream_t<S_, 1, 16, false, true, true>(a, zchunk, s)          \
+                    : sweep_stream_t<S_, 1, 8, false, true, true>(a, zchunk, s);          \
+  return nw == 16 ? sweep_stream_t<S_, 1, 16, false, false, true>(a, zchunk, s)           \
+                  : sweep_stream_t<S_, 1, 8, false, false, true>(a, zchunk, s);
+  switch (storage) {
+    case 0: { WAVE_XS_CASE(StF32) }
+    case 1: { WAVE_XS_CASE(StBF16) }
+    case 2: { WAVE_XS_CASE(StF16) }
+  }
+#undef WAVE_XS_CASE
   return hipErrorInvalidValue;
 }
 
@@ -975,6 +1112,22 @@ hipError_t launch_setup_field(float* dst, const float* src, int nx, int ny, int 
   return hipGetLastError();
 }
 
+hipError_t launch_stream_mix(int kind, void* d, const void* a, const void* b, const void* c,
+                             size_t bytes, hipStream_t s) {
+  const int64_t n = (int64_t)(bytes / 16);
+  if (n == 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  if (kind == 0)
+    hipLaunchKernelGGL(k_stream_read, dim3((unsigned)blocks), dim3(256), 0, s,
+                       static_cast<const float4*>(a), static_cast<float*>(d), n);
+  else
+    hipLaunchKernelGGL(k_stream_mix31, dim3((unsigned)blocks), dim3(256), 0, s,
+                       static_cast<const float4*>(a), static_cast<const float4*>(b),
+                       static_cast<const float4*>(c), static_cast<float4*>(d), n);
+  return hipGetLastError();
+}
+
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
   const int64_t n = (int64_t)(bytes / 16);
   if (n == 0) return hipSuccess;
@@ -993,29 +1146,35 @@ int stream_tiles_y(int ny, int ry, int nw) { return (ny + ry * nw - 1) / (ry * n
 
 template <class S>
 hipError_t sweep_batch_s(const BatchShot* shots, BatchState* state, int nshots, int64_t blocks,
-                         int ry, int nw, hipStream_t st) {
+                         int ry, int nw, bool eta_array, hipStream_t st) {
   if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 g((unsigned)blocks);
-#define WAVE_BATCH_CASE(RY_, NW_)                                                             \
-  if (ry == RY_ && nw == NW_) {                                                               \
-    hipLaunchKernelGGL((k_sweep_batch<S, RY_, NW_>), g, dim3(64 * NW_), 0, st, shots, state, \
-                       nshots);                                                               \
-    return hipGetLastError();                                                                 \
+#define WAVE_BATCH_CASE(RY_, NW_, EA_)                                                           \
+  if (ry == RY_ && nw == NW_ && eta_array == EA_) {                                              \
+    hipLaunchKernelGGL((k_sweep_batch<S, RY_, NW_, EA_>), g, dim3(64 * NW_), 0, st, shots, state, \
+                       nshots);                                                                  \
+    return hipGetLastError();                                                                    \
   }
-  WAVE_BATCH_CASE(1, 16)
-  WAVE_BATCH_CASE(1, 8)
-  WAVE_BATCH_CASE(2, 8)
-  WAVE_BATCH_CASE(2, 4)
+  WAVE_BATCH_CASE(1, 16, false)
+  WAVE_BATCH_CASE(1, 8, false)
+  WAVE_BATCH_CASE(2, 8, false)
+  WAVE_BATCH_CASE(2, 4, false)
+  WAVE_BATCH_CASE(2, 16, false)
+  WAVE_BATCH_CASE(1, 16, true)
+  WAVE_BATCH_CASE(1, 8, true)
+  WAVE_BATCH_CASE(2, 8, true)
+  WAVE_BATCH_CASE(2, 4, true)
 #undef WAVE_BATCH_CASE
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_sweep_batch(const BatchShot* shots, BatchState* state, int nshots,
-                              int64_t total_blocks, int storage, int ry, int nw, hipStream_t s) {
+                              int64_t total_blocks, int storage, int ry, int nw, bool eta_array,
+                              hipStream_t s) {
   switch (storage) {
-    case 0: return sweep_batch_s<StF32>(shots, state, nshots, total_blocks, ry, nw, s);
-    case 1: return sweep_batch_s<StBF16>(shots, state, nshots, total_blocks, ry, nw, s);
-    case 2: return sweep_batch_s<StF16>(shots, state, nshots, total_blocks, ry, nw, s);
+    case 0: return sweep_batch_s<StF32>(shots, state, nshots, total_blocks, ry, nw, eta_array, s);
+    case 1: return sweep_batch_s<StBF16>(shots, state, nshots, total_blocks, ry, nw, eta_array, s);
+    case 2: return sweep_batch_s<StF16>(shots, state, nshots, total_blocks, ry, nw, eta_array, s);
   }
   return hipErrorInvalidValue;
 }

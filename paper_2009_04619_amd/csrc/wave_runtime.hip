@@ -427,6 +427,7 @@ struct wave_batch {
   std::vector<wave::BatchShot> h_shots;
   std::vector<wave::BatchState> h_state;
   int ry, nw;
+  bool eta_any;               // some member holds a per-point eta array
   int64_t total_blocks;
   bool layout_dirty;          // membership or tile shape changed
   int graph_steps;            // steps per captured graph (0 = plain launches)
@@ -494,6 +495,16 @@ int stream_zchunk(const wave_ctx* c, int ry, int nw, int zchunk) {
   return std::min(zc, lim);
 }
 
+// Automatic z chunk of the persistent launch: half the streaming kernel's
+// (its workgroups do not wait for dispatch between items, so shorter items
+// cost little and balance the last round better; measured at 512^3 and
+// 1024^3), at least 16 planes.
+int persist_zchunk(const wave_ctx* c, int ry, int nw, int zchunk) {
+  if (zchunk > 0) return stream_zchunk(c, ry, nw, zchunk);
+  const int za = wave::auto_zchunk(c->L.nx, c->L.ny, c->L.nz, ry, nw);
+  return stream_zchunk(c, ry, nw, std::min(za, std::max(16, za / 2)));
+}
+
 // z-chunk length of the pair kernel (128 x ty tiles): as stream_zchunk, the
 // automatic length chosen for the tile count of 128-wide tiles; 0 when the
 // context holds an eta array (the kernel reads the default profile's tables
@@ -543,6 +554,8 @@ void batch_layout(wave_batch* b) {
     e.inj = inject_args(c);
   }
   b->total_blocks = begin;
+  b->eta_any = false;
+  for (wave_ctx* c : b->members) b->eta_any = b->eta_any || eta_array(&c->d);
   b->layout_dirty = false;
   batch_drop_graphs(b);
 }
@@ -553,7 +566,7 @@ hipError_t batch_launch_step(wave_batch* b, int k) {
                      ? wave::launch_sweep_batch_pair(b->d_shots, b->d_state, k, b->prefix_blocks[k],
                                                      b->storage, b->nw, b->stream)
                      : wave::launch_sweep_batch(b->d_shots, b->d_state, k, b->prefix_blocks[k],
-                                                b->storage, b->ry, b->nw, b->stream);
+                                                b->storage, b->ry, b->nw, b->eta_any, b->stream);
   if (e != hipSuccess) return e;
   return wave::launch_inject_batch(b->d_shots, b->d_state, k, b->storage, b->stream);
 }
@@ -719,9 +732,11 @@ int wave_alloc(const wave_desc* d, const float* vel, const float* eta, void* dev
   c->nsrc = c->nrec = c->trace_count = 0;
   c->src_host.clear();
   c->src_fit2 = true;
-  c->variant = WAVE_KERNEL_STREAM;
   c->shp[0] = c->shp[1] = c->shp[2] = 0;
   c->groups = persistent_groups();
+  // default: the streaming tiles as one persistent launch (the fastest
+  // measured at the benchmark sizes), where the CU count is known
+  c->variant = c->groups >= 8 ? WAVE_KERNEL_PERSIST : WAVE_KERNEL_STREAM;
   c->ry = 1;
   c->nw = 16;
   c->zchunk = 0;
@@ -943,7 +958,8 @@ int wave_step(wave_ctx* c, int32_t n) {
   }
   if (n == 0) return WAVE_OK;
   wave::SweepArgs sa = sweep_args(c);
-  const int zc = stream_zchunk(c, c->ry, c->nw, c->zchunk);
+  const int zc = c->variant == WAVE_KERNEL_PERSIST ? persist_zchunk(c, c->ry, c->nw, c->zchunk)
+                                                    : stream_zchunk(c, c->ry, c->nw, c->zchunk);
   const bool direct = c->variant == WAVE_KERNEL_DIRECT || zc < 1;
   const bool shape25 = c->variant == WAVE_KERNEL_RING || c->variant == WAVE_KERNEL_SHIFT;
   const int zcp = c->variant == WAVE_KERNEL_PAIR   ? pair_zchunk(c, c->shp[1], c->shp[2])
@@ -962,6 +978,9 @@ int wave_step(wave_ctx* c, int32_t n) {
       return wave::launch_sweep_pair(s, c->d.storage, c->shp[1], zcp, c->stream);
     if (c->variant == WAVE_KERNEL_SEMI)
       return wave::launch_sweep_semi(s, c->d.storage, c->shp[1], zcp, c->stream);
+    if (c->variant == WAVE_KERNEL_SHUFFLE)
+      return wave::launch_sweep_shuffle(s, c->d.storage, c->shp[1],
+                                        stream_zchunk(c, 1, c->shp[1], c->shp[2]), c->stream);
     if (c->variant == WAVE_KERNEL_PERSIST && !direct)
       return wave::launch_sweep_persist(s, c->d.storage, c->ry, c->nw, zc, c->groups, c->stream);
     return direct ? wave::launch_sweep_direct(s, c->d.storage, c->stream)
@@ -1144,6 +1163,16 @@ int wave_set_kernel(wave_ctx* c, int32_t variant, int32_t ry, int32_t nw, int32_
     c->shp[2] = zchunk;
     return WAVE_OK;
   }
+  if (variant == WAVE_KERNEL_SHUFFLE) {
+    if (ry != 1 || (nw != 8 && nw != 16)) return fail(WAVE_EINVAL, "shuffle kernel needs rows_per_wave 1, 8 or 16 rows");
+    if (zchunk < 0) return fail(WAVE_EINVAL, "zchunk < 0");
+    if (stream_zchunk(c, 1, nw, zchunk) < 1) return fail(WAVE_EINVAL, "planes too large to stream");
+    c->variant = variant;
+    c->shp[0] = 1;
+    c->shp[1] = nw;
+    c->shp[2] = zchunk;
+    return WAVE_OK;
+  }
   if (variant == WAVE_KERNEL_RING || variant == WAVE_KERNEL_SHIFT) {
     if (ry != 1 || (nw != 8 && nw != 16)) return fail(WAVE_EINVAL, "2.5-D shape needs rows_per_wave 1, 8 or 16 rows");
     if (zchunk < 0) return fail(WAVE_EINVAL, "zchunk < 0");
@@ -1154,10 +1183,11 @@ int wave_set_kernel(wave_ctx* c, int32_t variant, int32_t ry, int32_t nw, int32_
     return WAVE_OK;
   }
   if (variant == WAVE_KERNEL_PERSIST && (ry != 1 || (nw != 8 && nw != 16)))
-    return fail(WAVE_EINVAL, "persistent sweep needs rows_per_wave 1, 8 or 16 rows");
+    return fail(WAVE_EINVAL, "persistent sweep tiles: (1, 8), (1, 16)");
   if (variant != WAVE_KERNEL_STREAM && variant != WAVE_KERNEL_PERSIST)
     return fail(WAVE_EINVAL, "unknown kernel variant");
-  if (!wave::stream_config_supported(ry, nw)) return fail(WAVE_EINVAL, "tile (rows_per_wave, waves) not compiled");
+  if (!wave::stream_config_supported(ry, nw, eta_array(&c->d)))
+    return fail(WAVE_EINVAL, "tile (rows_per_wave, waves) not compiled for this context");
   if (zchunk < 0) return fail(WAVE_EINVAL, "zchunk < 0");
   c->variant = variant;
   c->ry = ry;
@@ -1168,7 +1198,7 @@ int wave_set_kernel(wave_ctx* c, int32_t variant, int32_t ry, int32_t nw, int32_
 
 namespace {
 // Tile shapes compiled into the library, in tuning order.
-constexpr int kShapes[][2] = {{1, 16}, {1, 8}, {2, 8}, {2, 4}};
+constexpr int kShapes[][2] = {{1, 16}, {2, 16}, {1, 8}, {2, 8}, {2, 4}};
 }  // namespace
 
 int wave_tune(wave_ctx* c, int32_t trial_steps, int32_t chosen[4]) {
@@ -1182,20 +1212,24 @@ int wave_tune(wave_ctx* c, int32_t trial_steps, int32_t chosen[4]) {
   auto add = [&](const std::array<int, 4>& e) {
     if (std::find(cand.begin(), cand.end(), e) == cand.end()) cand.push_back(e);
   };
+  const bool ea = eta_array(&c->d);
+  // the persistent launch first (the default), at its automatic chunk and
+  // twice that
+  for (const auto& t : {std::array<int, 2>{1, 16}, std::array<int, 2>{1, 8}}) {
+    if (c->groups < 8) continue;
+    const int za = persist_zchunk(c, t[0], t[1], 0);
+    for (int z : {za, std::min(nz, 2 * za)}) {
+      const int zc = stream_zchunk(c, t[0], t[1], z);
+      if (zc >= 1) add({WAVE_KERNEL_PERSIST, t[0], t[1], zc});
+    }
+  }
   for (int k = 0; k < nshape; ++k) {
     const int ry = kShapes[k][0], nw = kShapes[k][1];
+    if (!wave::stream_config_supported(ry, nw, ea)) continue;
     const int za = wave::auto_zchunk(c->L.nx, c->L.ny, nz, ry, nw);
     for (int z : {za, std::max(8, za / 2), std::min(nz, 2 * za)}) {
       const int zc = stream_zchunk(c, ry, nw, z);
       if (zc >= 1) add({WAVE_KERNEL_STREAM, ry, nw, zc});
-    }
-  }
-  // the same tiles as one persistent launch (one workgroup per CU)
-  for (int nw : {16, 8}) {
-    const int za = wave::auto_zchunk(c->L.nx, c->L.ny, nz, 1, nw);
-    for (int z : {za, std::max(8, za / 2)}) {
-      const int zc = stream_zchunk(c, 1, nw, z);
-      if (zc >= 1 && c->groups >= 8) add({WAVE_KERNEL_PERSIST, 1, nw, zc});
     }
   }
   if (stream2_zchunk(c, 0) >= 1) {
@@ -1212,6 +1246,11 @@ int wave_tune(wave_ctx* c, int32_t trial_steps, int32_t chosen[4]) {
     add({WAVE_KERNEL_PAIR, 1, ty, za});
     const int z2 = pair_zchunk(c, ty, std::min(nz, 2 * za));
     if (z2 != za) add({WAVE_KERNEL_PAIR, 1, ty, z2});
+  }
+  // x neighbours by wavefront shuffles, at the automatic chunk
+  for (int nw : {16, 8}) {
+    const int zc = stream_zchunk(c, 1, nw, 0);
+    if (zc >= 1) add({WAVE_KERNEL_SHUFFLE, 1, nw, zc});
   }
   // the paper's other code shapes, last (they must beat the streaming kernel
   // by the margin below to be picked)
@@ -1242,7 +1281,7 @@ int wave_tune(wave_ctx* c, int32_t trial_steps, int32_t chosen[4]) {
   const int shp0[3] = {c->shp[0], c->shp[1], c->shp[2]};
   auto is_shape = [](int v) {
     return v == WAVE_KERNEL_GMEM || v == WAVE_KERNEL_RING || v == WAVE_KERNEL_SHIFT ||
-           v == WAVE_KERNEL_PAIR || v == WAVE_KERNEL_SEMI;
+           v == WAVE_KERNEL_PAIR || v == WAVE_KERNEL_SEMI || v == WAVE_KERNEL_SHUFFLE;
   };
   float best = 0.0f;
   std::array<int, 4> pick = {variant, ry0, nw0, zc0};
@@ -1357,6 +1396,17 @@ int wave_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream)
   return WAVE_OK;
 }
 
+int wave_stream_mix(int32_t kind, void* dst, const void* a, const void* b, const void* c,
+                    size_t bytes, void* hip_stream) {
+  auto al = [](const void* p) { return p && ((uintptr_t)p & 15) == 0; };
+  if ((kind != 0 && kind != 1) || !al(dst) || !al(a) || (bytes % 16) ||
+      (kind == 1 && (!al(b) || !al(c))))
+    return fail(WAVE_EINVAL, "kind 0 or 1, 16-byte aligned pointers, a multiple of 16 bytes");
+  hipError_t e = wave::launch_stream_mix(kind, dst, a, b, c, bytes, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return dev_fail(nullptr, e, "stream launch");
+  return WAVE_OK;
+}
+
 size_t wave_batch_bytes_required(int32_t max_shots) {
   if (max_shots < 1 || max_shots > 65536) {
     g_last_error = "max_shots outside [1, 65536]";
@@ -1401,6 +1451,7 @@ int wave_batch_create(int32_t storage, int32_t max_shots, void* dev_arena, size_
   b->d_state = reinterpret_cast<wave::BatchState*>(b->arena + soff);
   b->ry = 1;
   b->nw = 16;
+  b->eta_any = false;
   b->total_blocks = 0;
   b->layout_dirty = true;
   b->graph_steps = 0;
@@ -1438,6 +1489,8 @@ int wave_batch_add(wave_batch* b, wave_ctx* c, int32_t nsteps) {
     return fail(WAVE_EINVAL, "z planes too large for the batched streaming kernel");
   if (b->ry == 0 && eta_array(&c->d))
     return fail(WAVE_EINVAL, "the batch runs the two-points-per-lane kernel, which takes no eta array");
+  if (b->ry > 0 && !wave::stream_config_supported(b->ry, b->nw, eta_array(&c->d)))
+    return fail(WAVE_EINVAL, "the batch's tile is not compiled for a member with an eta array");
   // the batch's launches come after everything queued so far on the member's stream
   JOIN_CTX(c);
   if (c->stream != b->user_stream) {
@@ -1489,8 +1542,11 @@ int wave_batch_set_kernel(wave_batch* b, int32_t ry, int32_t nw) {
     if (nw != 8 && nw != 16) return fail(WAVE_EINVAL, "two points per lane: 8 or 16 rows");
     for (wave_ctx* c : b->members)
       if (eta_array(&c->d)) return fail(WAVE_EINVAL, "a member holds an eta array (two points per lane takes none)");
-  } else if (!wave::stream_config_supported(ry, nw)) {
-    return fail(WAVE_EINVAL, "tile (rows_per_wave, waves) not compiled");
+  } else {
+    bool ea = false;
+    for (wave_ctx* c : b->members) ea = ea || eta_array(&c->d);
+    if (!wave::stream_config_supported(ry, nw, ea))
+      return fail(WAVE_EINVAL, "tile (rows_per_wave, waves) not compiled for these members");
   }
   b->ry = ry;
   b->nw = nw;
@@ -1617,9 +1673,11 @@ int wave_batch_tune(wave_batch* b, int32_t trial_steps, int32_t chosen[2]) {
   // the compiled one-point tiles, then two points per lane (128 x 16, 128 x 8)
   // when no member holds an eta array
   std::vector<std::array<int, 2>> shapes;
-  for (int k = 0; k < nshape; ++k) shapes.push_back({kShapes[k][0], kShapes[k][1]});
   bool pair_ok = true;
   for (wave_ctx* c : b->members) pair_ok = pair_ok && !eta_array(&c->d);
+  for (int k = 0; k < nshape; ++k)
+    if (wave::stream_config_supported(kShapes[k][0], kShapes[k][1], !pair_ok))
+      shapes.push_back({kShapes[k][0], kShapes[k][1]});
   if (pair_ok) {
     shapes.push_back({0, 16});
     shapes.push_back({0, 8});

@@ -31,7 +31,7 @@ WAVE_TWO_STEP = 4
 WAVE_FIELD_U, WAVE_FIELD_UPREV, WAVE_FIELD_PHI, WAVE_FIELD_VP, WAVE_FIELD_ETA = 0, 1, 2, 3, 4
 WAVE_KERNEL_DIRECT, WAVE_KERNEL_STREAM, WAVE_KERNEL_STREAM2 = 0, 1, 2
 WAVE_KERNEL_GMEM, WAVE_KERNEL_RING, WAVE_KERNEL_SHIFT, WAVE_KERNEL_PAIR = 3, 4, 5, 6
-WAVE_KERNEL_SEMI, WAVE_KERNEL_PERSIST = 7, 8
+WAVE_KERNEL_SEMI, WAVE_KERNEL_PERSIST, WAVE_KERNEL_SHUFFLE = 7, 8, 9
 STORAGE = {"f32": WAVE_F32, "bf16": WAVE_BF16, "f16": WAVE_F16}
 
 EXPORTED = [
@@ -39,7 +39,7 @@ EXPORTED = [
     "wave_alloc", "wave_free", "wave_inject", "wave_record", "wave_step", "wave_sync",
     "wave_step_count", "wave_read_field", "wave_write_field", "wave_read_traces",
     "wave_energy", "wave_set_kernel", "wave_set_timing", "wave_read_timing",
-    "wave_sweep_bytes", "wave_stream_copy", "wave_strerror", "wave_last_error",
+    "wave_sweep_bytes", "wave_stream_copy", "wave_stream_mix", "wave_strerror", "wave_last_error",
     "wave_batch_bytes_required", "wave_batch_create", "wave_batch_add", "wave_batch_remove",
     "wave_batch_run", "wave_batch_remaining", "wave_batch_set_kernel", "wave_batch_set_graph",
     "wave_batch_free", "wave_tune", "wave_batch_tune",
@@ -92,6 +92,7 @@ def _load():
         "wave_read_timing": (C.c_int, [P, C.POINTER(f64), C.POINTER(i64)]),
         "wave_sweep_bytes": (f64, [P]),
         "wave_stream_copy": (C.c_int, [P, P, sz, P]),
+        "wave_stream_mix": (C.c_int, [i32, P, P, P, P, sz, P]),
         "wave_batch_bytes_required": (sz, [i32]),
         "wave_batch_create": (C.c_int, [i32, i32, P, sz, P, C.POINTER(P)]),
         "wave_batch_add": (C.c_int, [P, P, i32]),
@@ -221,6 +222,13 @@ def wave_read_timing(ctx):
 
 def wave_sweep_bytes(ctx) -> float:
     return float(_lib.wave_sweep_bytes(ctx))
+
+
+def wave_stream_mix(kind: int, dst_ptr: int, a_ptr: int, b_ptr: int, c_ptr: int, nbytes: int,
+                    stream_ptr: int) -> int:
+    return int(_lib.wave_stream_mix(kind, C.c_void_p(dst_ptr), C.c_void_p(a_ptr),
+                                    C.c_void_p(b_ptr), C.c_void_p(c_ptr), nbytes,
+                                    C.c_void_p(stream_ptr)))
 
 
 def wave_stream_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream_ptr: int) -> int:

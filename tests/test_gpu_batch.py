@@ -72,11 +72,13 @@ def same(a, b, what):
 
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
 @pytest.mark.parametrize("graph", [0, 4])
-def test_batch_members_equal_solo_runs(W, storage, graph):
+@pytest.mark.parametrize("tile", [(1, 16), (2, 16)])
+def test_batch_members_equal_solo_runs(W, storage, graph, tile):
     shots = shots_for(SHAPES)
-    say(f"case batch storage={storage} graph={graph}")
+    say(f"case batch storage={storage} graph={graph} tile={tile}")
     ref = [solo(W, s, storage) for s in shots]
     b = W.Batch(storage=storage, max_shots=8)
+    b.set_kernel(*tile)
     b.set_graph(graph)
     members = []
     for s in shots:

@@ -99,8 +99,12 @@ RAGGED = [
 KERNELS = [(W_, ry, nw, zc) for (W_, ry, nw, zc) in [
     (0, 1, 16, 0), (1, 1, 16, 0), (1, 1, 8, 0), (1, 2, 8, 0), (1, 2, 4, 0),
     (1, 1, 16, 5), (1, 2, 8, 7), (1, 1, 8, 1), (1, 2, 4, 3),
+    # 64 x 32 tiles (two rows per wavefront, 16 wavefronts)
+    (1, 2, 16, 0), (1, 2, 16, 3),
     # the persistent launch of the same tiles
-    (8, 1, 16, 0), (8, 1, 8, 0), (8, 1, 16, 5), (8, 1, 8, 1)]]
+    (8, 1, 16, 0), (8, 1, 8, 0), (8, 1, 16, 5), (8, 1, 8, 1),
+    # x neighbours by wavefront shuffles
+    (9, 1, 16, 0), (9, 1, 8, 3)]]
 
 
 @pytest.mark.parametrize("case", RAGGED, ids=lambda c: "x".join(map(str, c[:3])) + f"_w{c[3]}")
@@ -130,8 +134,13 @@ def test_eta_array_mode_and_table_mode(W):
     eta = (e32 * (1.0 + 0.5 * rng.random(e32.shape))).astype(np.float32)
     say("case eta array mode")
     ref = oracle.run_shot(shot, precision="f32", eta=eta)
-    for k in [(0, 1, 16, 0), (1, 1, 16, 0), (1, 1, 8, 5), (1, 2, 8, 0), (1, 2, 4, 3)]:
+    for k in [(0, 1, 16, 0), (1, 1, 16, 0), (1, 1, 8, 5), (1, 2, 8, 0), (1, 2, 4, 3),
+              (8, 1, 16, 0), (9, 1, 16, 0), (9, 1, 8, 4)]:
         assert_same(gpu_run(W, shot, 25, kernel=k, eta=eta), ref, f"array mode {k}")
+    # 64 x 32 tiles take the default profile's tables only
+    sh = W.shot_from_synth(shot, eta=eta, max_steps=1)
+    assert W.wave_set_kernel(sh.ctx, 1, 2, 16, 0) == W.WAVE_EINVAL
+    sh.close()
     tab = gpu_run(W, shot, 25)
     arr = gpu_run(W, shot, 25, eta=e32)
     assert_same(tab, oracle.run_shot(shot, precision="f32"), "table mode vs oracle")
@@ -207,29 +216,41 @@ def random_state(shot, seed):
     return {"u": u, "u_prev": up, "phi": phi}
 
 
-def test_c2_full_size_few_steps_bitwise(W):
-    """512^3, 20-cell layer, layered model: every launch configuration the
-    benchmark's tuner can pick at this size -- the streaming tiles at their
-    z-chunk lengths, the persistent launch, two steps per launch, two points
-    per lane, and the paper's other code shapes it times (3-D 8x8x8 and
-    64x4x4, the LDS plane ring, the shifted register queue) -- 4 steps
-    against the float32 oracle on every point."""
+# wave_tune's candidates at 512^3: every compiled tile at the automatic chunk
+# (64 planes; 32 for the 64 x 32 tile), half and double; the persistent
+# launch at the automatic chunk and half; two steps per launch at 64, 32,
+# 128; two points per lane (16 rows: 32 and 64 planes, 8 rows: 64 and 128);
+# the four code shapes it times
+C2_CANDIDATES = (
+    [(1, ry, nw, z) for (ry, nw) in [(1, 16), (1, 8), (2, 8), (2, 4)] for z in (64, 32, 128)]
+    + [(1, 2, 16, z) for z in (32, 16, 64)]
+    + [(8, 1, 16, 64), (8, 1, 16, 32), (8, 1, 8, 64), (8, 1, 8, 32),
+       (2, 1, 16, 64), (2, 1, 16, 32), (2, 1, 16, 128),
+       (6, 1, 16, 32), (6, 1, 16, 64), (6, 1, 8, 64), (6, 1, 8, 128),
+       (9, 1, 16, 64), (9, 1, 8, 64),
+       (3, 8, 8, 8), (3, 64, 4, 4), (4, 1, 16, 0), (5, 1, 16, 0)])
+
+
+@pytest.fixture(scope="module")
+def c2_case():
+    """512^3, 20-cell layer, layered model, from a random state, and the
+    float32 oracle's result after 4 steps."""
     shot = synth.config_c2(steps=4)
     st = random_state(shot, 11)
-    o = oracle.run_shot(shot, precision="f32", state=st)
-    # wave_tune's candidates at 512^3: every compiled tile at the automatic
-    # chunk (64 planes), half and double; the persistent launch at 64 and 32;
-    # two steps per launch at 64, 32, 128; two points per lane (16 rows: 32
-    # and 64 planes, 8 rows: 64 and 128); the four code shapes
-    stream = [(1, ry, nw, z) for (ry, nw) in [(1, 16), (1, 8), (2, 8), (2, 4)] for z in (64, 32, 128)]
-    others = [(8, 1, 16, 64), (8, 1, 16, 32), (8, 1, 8, 64), (8, 1, 8, 32),
-              (2, 1, 16, 64), (2, 1, 16, 32), (2, 1, 16, 128),
-              (6, 1, 16, 32), (6, 1, 16, 64), (6, 1, 8, 64), (6, 1, 8, 128),
-              (3, 8, 8, 8), (3, 64, 4, 4), (4, 1, 16, 0), (5, 1, 16, 0)]
-    for k in stream + others:
-        say(f"case c2 512^3 4 steps kernel {k}")
-        assert_same(gpu_run(W, shot, 4, kernel=k, state=st, two_step=k[0] == 2), o,
-                    f"c2 512^3 {k}")
+    say("case c2 512^3: oracle, 4 steps")
+    return shot, st, oracle.run_shot(shot, precision="f32", state=st)
+
+
+@pytest.mark.parametrize("k", C2_CANDIDATES, ids=lambda k: "v{}_{}x{}_z{}".format(*k))
+def test_c2_full_size_few_steps_bitwise(W, c2_case, k):
+    """Every launch configuration the benchmark's tuner can pick at 512^3
+    (the streaming tiles at their z-chunk lengths, the persistent launch,
+    two steps per launch, two points per lane, and the paper's other code
+    shapes it times: 3-D 8x8x8 and 64x4x4, the LDS plane ring, the shifted
+    register queue), 4 steps against the float32 oracle on every point."""
+    shot, st, o = c2_case
+    say(f"case c2 512^3 4 steps kernel {k}")
+    assert_same(gpu_run(W, shot, 4, kernel=k, state=st, two_step=k[0] == 2), o, f"c2 512^3 {k}")
 
 
 def test_c3_size_few_steps_bitwise(W):

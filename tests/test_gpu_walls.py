@@ -83,7 +83,9 @@ def assert_same(a, b, what):
                                  f"{x[i]!r} vs {y[i]!r}")
 
 
-STREAM = [(1, 1, 16, 0), (1, 1, 8, 0), (1, 2, 8, 0), (1, 2, 4, 0), (1, 1, 8, 3)]
+STREAM_EA = [(1, 1, 16, 0), (1, 1, 8, 0), (1, 2, 8, 0), (1, 2, 4, 0), (1, 1, 8, 3)]
+# 64 x 32 tiles and the persistent launch take the default profile's tables only
+STREAM = STREAM_EA + [(1, 2, 16, 0), (8, 1, 16, 0), (8, 1, 8, 0), (9, 1, 16, 0), (9, 1, 8, 0)]
 PAIR = [(6, 1, 16, 0), (6, 1, 8, 0), (6, 1, 8, 5)]
 
 GRIDS = [  # nx, ny, nz, w, steps, storage
@@ -115,6 +117,6 @@ def test_wall_tiles_with_eta_array(W):
     eta = (e32 * (1.0 + 0.5 * rng.random(e32.shape))).astype(np.float32)
     st = random_state(shot, "f32", seed=4)
     expect = oracle.run_shot(shot, steps=steps, precision="f32", eta=eta, state=st)
-    for k in STREAM:
+    for k in STREAM_EA + [(8, 1, 16, 0), (8, 1, 8, 3), (9, 1, 16, 0), (9, 1, 8, 3)]:
         say(f"case walls {k} eta array")
         assert_same(run(W, shot, steps, k, eta=eta, state=st), expect, f"walls {k} eta array")

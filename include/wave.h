@@ -221,6 +221,20 @@ int wave_read_traces(wave_ctx *ctx, double *host_out, int32_t *steps_out);
  * reduction order).  Synchronises. */
 int wave_energy(wave_ctx *ctx, double *out);
 
+/* wave_energy for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels and reduction order, but the per-row partial sums go to a static
+ * workspace of the library (one per GPU, 16 MiB, held until the process
+ * ends) instead of the context's arena, nothing is allocated, and nothing
+ * waits: the kernels are enqueued on the context stream and write
+ * {kinetic, potential} to dev_out (device memory, 2 doubles), so that
+ * E = dev_out[0] - dev_out[1] equals wave_energy's value once the stream
+ * reaches that point.  Limit: ny * nz <= 1048576 rows (EINVAL beyond).
+ * Every call on one GPU shares that GPU's workspace: calls that can overlap
+ * on one GPU (contexts on different streams) race and must be ordered by
+ * the caller.  Errors: EINVAL (NULL dev_out, too many rows). */
+int wave_energy_noalloc(wave_ctx *ctx, double *dev_out);
+
 /* ---- kernel selection and timing ----------------------------------------- */
 
 /* Kernel variants for the sweep. */

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <array>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -1115,6 +1116,70 @@ int wave_energy(wave_ctx* c, double* out) {
   HIPCHK(c, hipMemcpyAsync(r, ea.result, 16, hipMemcpyDeviceToHost, c->stream), "hipMemcpyAsync");
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   *out = r[0] - r[1];
+  return WAVE_OK;
+}
+
+// ---- energy without allocation ---------------------------------------------
+// Workspace of wave_energy_noalloc: the per-row partial sums of the energy
+// (kinetic, potential) for up to kScratchRows rows (ny * nz), then the two
+// totals.  One copy per GPU, kept until the process ends (16 MiB).  In host
+// code `scratch` only names the symbol; its device address, per GPU, comes
+// from hipGetSymbolAddress with that GPU current.
+namespace {
+constexpr int64_t kScratchRows = int64_t(1) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[2 * kScratchRows + 2];
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the GPU that holds the context's arena,
+// looked up once per GPU.
+int scratch_for(wave_ctx* c, double** out) {
+  hipPointerAttribute_t at;
+  HIPCHK(c, hipPointerGetAttributes(&at, c->arena), "hipPointerGetAttributes");
+  const int dev = at.device;
+  if (dev < 0 || dev >= kMaxDevices) return fail(WAVE_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    HIPCHK(c, hipGetDevice(&cur), "hipGetDevice");
+    if (cur != dev) HIPCHK(c, hipSetDevice(dev), "hipSetDevice");
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) HIPCHK(c, hipSetDevice(cur), "hipSetDevice");
+    if (e != hipSuccess) return dev_fail(c, e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return WAVE_OK;
+}
+}  // namespace
+
+int wave_energy_noalloc(wave_ctx* c, double* dev_out) {
+  CHECK_CTX(c);
+  JOIN_CTX(c);
+  if (!dev_out) return fail(WAVE_EINVAL, "dev_out is NULL");
+  const int64_t rows = (int64_t)c->L.ny * c->L.nz;
+  if (rows > kScratchRows)
+    return fail(WAVE_EINVAL, "ny * nz = " + std::to_string(rows) + " exceeds the " +
+                                 std::to_string(kScratchRows) + " rows of the static workspace");
+  double* ws = nullptr;
+  const int rc = scratch_for(c, &ws);
+  if (rc != WAVE_OK) return rc;
+  wave::EnergyArgs ea;
+  ea.cur = c->u_origin(c->icur);
+  ea.prev = c->u_origin(c->iprev);
+  ea.vp = c->f_origin(c->plan.vp);
+  ea.nx = c->L.nx;
+  ea.ny = c->L.ny;
+  ea.nz = c->L.nz;
+  ea.pitch = c->L.pitch;
+  ea.plane = c->L.plane;
+  memcpy(ea.c, c->c64, sizeof(ea.c));
+  ea.partial = ws;
+  ea.result = dev_out;
+  const hipError_t e = wave::launch_energy(ea, c->d.storage, c->stream);
+  if (e != hipSuccess) return dev_fail(c, e, "energy launch");
   return WAVE_OK;
 }
 

@@ -38,7 +38,7 @@ EXPORTED = [
     "wave_bytes_required", "wave_admit", "wave_coefficients", "wave_stability", "wave_eta_default",
     "wave_alloc", "wave_free", "wave_inject", "wave_record", "wave_step", "wave_sync",
     "wave_step_count", "wave_read_field", "wave_write_field", "wave_read_traces",
-    "wave_energy", "wave_set_kernel", "wave_set_timing", "wave_read_timing",
+    "wave_energy", "wave_energy_noalloc", "wave_set_kernel", "wave_set_timing", "wave_read_timing",
     "wave_sweep_bytes", "wave_stream_copy", "wave_stream_mix", "wave_strerror", "wave_last_error",
     "wave_batch_bytes_required", "wave_batch_create", "wave_batch_add", "wave_batch_remove",
     "wave_batch_run", "wave_batch_remaining", "wave_batch_set_kernel", "wave_batch_set_graph",
@@ -87,6 +87,7 @@ def _load():
         "wave_write_field": (C.c_int, [P, i32, P]),
         "wave_read_traces": (C.c_int, [P, P, C.POINTER(i32)]),
         "wave_energy": (C.c_int, [P, C.POINTER(f64)]),
+        "wave_energy_noalloc": (C.c_int, [P, P]),
         "wave_set_kernel": (C.c_int, [P, i32, i32, i32, i32]),
         "wave_set_timing": (C.c_int, [P, i32]),
         "wave_read_timing": (C.c_int, [P, C.POINTER(f64), C.POINTER(i64)]),
@@ -203,6 +204,12 @@ def wave_energy(ctx):
     e = C.c_double()
     rc = _lib.wave_energy(ctx, C.byref(e))
     return int(rc), float(e.value)
+
+
+def wave_energy_noalloc(ctx, dev_out_ptr: int) -> int:
+    """Enqueue the energy into 2 doubles of device memory at dev_out_ptr
+    (kinetic, potential); no allocation, no wait."""
+    return int(_lib.wave_energy_noalloc(ctx, dev_out_ptr))
 
 
 def wave_set_kernel(ctx, variant: int, rows_per_wave: int = 1, waves_per_group: int = 16,

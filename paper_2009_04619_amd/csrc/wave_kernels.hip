@@ -648,28 +648,13 @@ __global__ __launch_bounds__(64 * NW, WAVE_STREAM_WPS(RY, NW)) void k_sweep_stre
   constexpr int LSZ = (TY + 2 * kR) * (kTX + 2 * kR) + 64;  // + a dump row
   __shared__ float sm[2][LSZ];
 
-  // XCD-aware tile order: dispatch sends block b to XCD b % 8.  The tile
-  // rows are padded to 8 slabs of sh = ceil(tiles_y / 8) rows (workgroups
-  // of padding rows exit at once), so every XCD gets the same number of
-  // workgroups.  Each XCD owns a slab of tile rows for every z chunk and
-  // walks it chunk by chunk: the tiles it runs at once are x and y
-  // neighbours, so halos come from its L2.  The slab an XCD owns moves on
-  // by 3 (coprime to 8) from one chunk to the next, so the slabs holding the
-  // y walls of the damping layer, which cost more, are spread over all XCDs
-  // instead of loading the first and the last.
-  const int bid = blockIdx.x;
-  const int xcd = bid & 7, slot = bid >> 3;
-  const int sh = (tiles_y + 7) >> 3;
-  const int tx = slot % tiles_x;
-  const int t2 = slot / tiles_x;
-  const int ch = t2 / sh;
-  const int ty = ((xcd + 3 * ch) & 7) * sh + t2 % sh;
-  if (ty >= tiles_y) return;
-  const int x0 = tx * kTX, y0 = ty * TY;
+  // XCD-aware tile order (tile_at)
+  const TileAt t = tile_at(blockIdx.x, tiles_x, tiles_y);
+  if (t.ty >= tiles_y) return;
   const bool damp = a.damping != 0;
-  const ChunkInfo c = chunk_of(ch, a.nz, a.w, zchunk, damp);
+  const ChunkInfo c = chunk_of(t.ch, a.nz, a.w, zchunk, damp);
   if (c.zb >= c.ze) return;
-  stream_tile<S, RY, NW, ZS, EA, XS>(a, sm, x0, y0, c.zb, c.ze, damp && c.cap);
+  stream_tile<S, RY, NW, ZS, EA, XS>(a, sm, t.tx * kTX, t.ty * TY, c.zb, c.ze, damp && c.cap);
 }
 
 // The same sweep as one persistent launch: 8 G workgroups (G per XCD, one
@@ -693,19 +678,16 @@ __global__ __launch_bounds__(64 * NW, WAVE_STREAM_WPS(RY, NW)) void k_sweep_pers
   const int xcd = blockIdx.x & 7;
   const int g = blockIdx.x >> 3;
   const int G = gridDim.x >> 3;
-  const int sh = (tiles_y + 7) >> 3;
+  const int sh = (tiles_y + 7) >> 3;  // tile rows per slab (tile_at)
   const bool damp = a.damping != 0;
   const int items = tiles_x * sh * chunk_count(a.nz, a.w, zchunk, damp);
   for (int k = 0; k * G < items; ++k) {
     const int slot = k * G + (g + 5 * k) % G;
     if (slot >= items) continue;
-    const int tx = slot % tiles_x;
-    const int t2 = slot / tiles_x;
-    const int ch = t2 / sh;
-    const int ty = ((xcd + 3 * ch) & 7) * sh + t2 % sh;
-    const ChunkInfo c = chunk_of(ch, a.nz, a.w, zchunk, damp);
-    if (ty >= tiles_y || c.zb >= c.ze) continue;
-    stream_tile<S, RY, NW, false, EA>(a, sm, tx * kTX, ty * TY, c.zb, c.ze, damp && c.cap);
+    const TileAt t = tile_at(8 * (int64_t)slot + xcd, tiles_x, tiles_y);
+    const ChunkInfo c = chunk_of(t.ch, a.nz, a.w, zchunk, damp);
+    if (t.ty >= tiles_y || c.zb >= c.ze) continue;
+    stream_tile<S, RY, NW, false, EA>(a, sm, t.tx * kTX, t.ty * TY, c.zb, c.ze, damp && c.cap);
     __syncthreads();  // the next tile's staging reuses the LDS planes
   }
 }
@@ -722,35 +704,21 @@ __global__ __launch_bounds__(64 * NW, WAVE_STREAM_WPS(RY, NW)) void k_sweep_batc
   constexpr int LSZ = (TY + 2 * kR) * (kTX + 2 * kR) + 64;
   __shared__ float sm[2][LSZ];
   const int64_t bid = blockIdx.x;
-  // member of this workgroup: last member whose first block is <= bid
-  int lo = 0, hi = nshots - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (shots[mid].block_begin <= bid) lo = mid; else hi = mid - 1;
-  }
-  const BatchShot& b = shots[lo];
-  const BatchState st = state[lo];
+  const int m = batch_member(shots, nshots, bid);
+  const BatchShot& b = shots[m];
+  const BatchState st = state[m];
   if (st.done >= b.target) return;
   SweepArgs a = b.sa;
   a.cur = b.u[st.cur];
   a.nxt = b.u[st.cur ^ 1];
   // each member's range starts at a multiple of 8 blocks, so the member-local
-  // index keeps the XCD in its low 3 bits; tiles follow k_sweep_stream's
-  // order (padded slabs of tile rows, rotated over the XCDs per z chunk)
-  const int64_t local = bid - b.block_begin;
-  const int xcd = (int)(local & 7);
-  const int64_t slot = local >> 3;
-  const int sh = (b.tiles_y + 7) >> 3;
-  const int tx = (int)(slot % b.tiles_x);
-  const int64_t t2 = slot / b.tiles_x;
-  const int ch = (int)(t2 / sh);
-  const int ty = ((xcd + 3 * ch) & 7) * sh + (int)(t2 % sh);
-  if (ty >= b.tiles_y) return;
-  const int x0 = tx * kTX, y0 = ty * TY;
+  // index keeps the XCD in its low 3 bits; tiles follow the single-shot order
+  const TileAt t = tile_at(bid - b.block_begin, b.tiles_x, b.tiles_y);
+  if (t.ty >= b.tiles_y) return;
   const bool damp = a.damping != 0;
-  const ChunkInfo c = chunk_of(ch, a.nz, a.w, b.zchunk, damp);
+  const ChunkInfo c = chunk_of(t.ch, a.nz, a.w, b.zchunk, damp);
   if (c.zb >= c.ze) return;
-  stream_tile<S, RY, NW, false, EA>(a, sm, x0, y0, c.zb, c.ze, damp && c.cap);
+  stream_tile<S, RY, NW, false, EA>(a, sm, t.tx * kTX, t.ty * TY, c.zb, c.ze, damp && c.cap);
 }
 
 // One workgroup per member: source add, receiver sample, then the member's

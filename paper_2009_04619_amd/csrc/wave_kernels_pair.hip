@@ -375,20 +375,13 @@ __global__ __launch_bounds__(64 * TY) void k_sweep_pair(SweepArgs a, int tiles_x
   // halo pair
   __shared__ __attribute__((aligned(16))) float sm[2][LR * kPW + 128];
 
-  // tile order as in k_sweep_stream: 8 slabs of tile rows rotating over the
-  // XCDs per z chunk
-  const int bid = blockIdx.x;
-  const int xcd = bid & 7, slot = bid >> 3;
-  const int sh = (tiles_y + 7) >> 3;
-  const int tx = slot % tiles_x;
-  const int t2 = slot / tiles_x;
-  const int ch = t2 / sh;
-  const int ty = ((xcd + 3 * ch) & 7) * sh + t2 % sh;
-  if (ty >= tiles_y) return;
+  // tile order as in k_sweep_stream (tile_at)
+  const TileAt t = tile_at(blockIdx.x, tiles_x, tiles_y);
+  if (t.ty >= tiles_y) return;
   const bool damp = a.damping != 0;
-  const ChunkInfo c = chunk_of(ch, a.nz, a.w, zchunk, damp);
+  const ChunkInfo c = chunk_of(t.ch, a.nz, a.w, zchunk, damp);
   if (c.zb >= c.ze) return;
-  pair_tile<S, TY>(a, sm, tx * kPX, ty * TY, c.zb, c.ze, damp && c.cap);
+  pair_tile<S, TY>(a, sm, t.tx * kPX, t.ty * TY, c.zb, c.ze, damp && c.cap);
 }
 
 // Batch: one grid over the members' block ranges (each a multiple of 8
@@ -400,30 +393,19 @@ __global__ __launch_bounds__(64 * TY) void k_sweep_batch_pair(const BatchShot* _
   constexpr int LR = TY + 2 * kR;
   __shared__ __attribute__((aligned(16))) float sm[2][LR * kPW + 128];
   const int64_t bid = blockIdx.x;
-  int lo = 0, hi = nshots - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (shots[mid].block_begin <= bid) lo = mid; else hi = mid - 1;
-  }
-  const BatchShot& b = shots[lo];
-  const BatchState st = state[lo];
+  const int m = batch_member(shots, nshots, bid);
+  const BatchShot& b = shots[m];
+  const BatchState st = state[m];
   if (st.done >= b.target) return;
   SweepArgs a = b.sa;
   a.cur = b.u[st.cur];
   a.nxt = b.u[st.cur ^ 1];
-  const int64_t local = bid - b.block_begin;
-  const int xcd = (int)(local & 7);
-  const int64_t slot = local >> 3;
-  const int sh = (b.tiles_y + 7) >> 3;
-  const int tx = (int)(slot % b.tiles_x);
-  const int64_t t2 = slot / b.tiles_x;
-  const int ch = (int)(t2 / sh);
-  const int ty = ((xcd + 3 * ch) & 7) * sh + (int)(t2 % sh);
-  if (ty >= b.tiles_y) return;
+  const TileAt t = tile_at(bid - b.block_begin, b.tiles_x, b.tiles_y);
+  if (t.ty >= b.tiles_y) return;
   const bool damp = a.damping != 0;
-  const ChunkInfo c = chunk_of(ch, a.nz, a.w, b.zchunk, damp);
+  const ChunkInfo c = chunk_of(t.ch, a.nz, a.w, b.zchunk, damp);
   if (c.zb >= c.ze) return;
-  pair_tile<S, TY>(a, sm, tx * kPX, ty * TY, c.zb, c.ze, damp && c.cap);
+  pair_tile<S, TY>(a, sm, t.tx * kPX, t.ty * TY, c.zb, c.ze, damp && c.cap);
 }
 
 template <class S, int TY>

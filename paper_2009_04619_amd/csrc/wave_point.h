@@ -205,5 +205,43 @@ __device__ inline ChunkInfo chunk_of(int ch, int nz, int w, int zc, bool damp) {
   return c;
 }
 
+// XCD-aware tile order of the streaming sweeps.  Dispatch sends block b to
+// XCD b % 8.  The tile rows are padded to 8 slabs of sh = ceil(tiles_y / 8)
+// rows (blocks of padding rows exit at once), so every XCD gets the same
+// number of blocks.  Each XCD owns a slab of tile rows for every z chunk and
+// walks it chunk by chunk: the tiles it runs at once are x and y
+// neighbours, so halos come from its L2.  The slab an XCD owns moves on by 3
+// (coprime to 8) from one chunk to the next, so the slabs holding the y
+// walls of the damping layer, which cost more, are spread over all XCDs
+// instead of loading the first and the last.  Block b (counted from a
+// multiple of 8) -> tile column tx, tile row ty (>= tiles_y: padding), z
+// chunk ch.
+struct TileAt {
+  int tx, ty, ch;
+};
+__device__ inline TileAt tile_at(int64_t b, int tiles_x, int tiles_y) {
+  const int xcd = (int)(b & 7);
+  const int64_t slot = b >> 3;
+  const int sh = (tiles_y + 7) >> 3;
+  const int64_t t2 = slot / tiles_x;
+  TileAt t;
+  t.tx = (int)(slot % tiles_x);
+  t.ch = (int)(t2 / sh);
+  t.ty = ((xcd + 3 * t.ch) & 7) * sh + (int)(t2 % sh);
+  return t;
+}
+
+// Member of a batch launch that block b belongs to: the last member whose
+// first block is <= b (members' ranges are back to back, in order).
+template <class Shot>
+__device__ inline int batch_member(const Shot* shots, int nshots, int64_t b) {
+  int lo = 0, hi = nshots - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (shots[mid].block_begin <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 }  // namespace
 }  // namespace wave

@@ -312,8 +312,10 @@ int wave_energy_noalloc(wave_ctx *ctx, double *dev_out);
  * combinations are accepted (EINVAL otherwise): (RY, NW) in
  * {(1,16), (1,8), (2,8), (2,4)}, and (2,16) (64 x 32 tiles) without an eta
  * array.  The default is WAVE_KERNEL_PERSIST with (1,16) tiles and its
- * automatic chunk (half the streaming kernel's), or WAVE_KERNEL_STREAM with
- * (1,16) where the CU count cannot be queried.  The streaming
+ * automatic chunk (half the streaming kernel's) on grids large enough for
+ * 64-plane chunks of 64 x 16 tiles with about 2048 workgroups (512^3 and
+ * up for cubes), else WAVE_KERNEL_STREAM with (1,8) tiles (also where the
+ * CU count cannot be queried).  The streaming
  * kernel addresses a chunk's planes with 32-bit offsets, so zchunk is cut
  * to what keeps zchunk + 8 float planes below 2 GiB; a grid whose single
  * plane is too large for that runs the direct kernel.  With

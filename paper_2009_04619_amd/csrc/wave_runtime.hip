@@ -735,11 +735,17 @@ int wave_alloc(const wave_desc* d, const float* vel, const float* eta, void* dev
   c->src_fit2 = true;
   c->shp[0] = c->shp[1] = c->shp[2] = 0;
   c->groups = persistent_groups();
-  // default: the streaming tiles as one persistent launch (the fastest
-  // measured at the benchmark sizes), where the CU count is known
-  c->variant = c->groups >= 8 ? WAVE_KERNEL_PERSIST : WAVE_KERNEL_STREAM;
+  // default launch (measured one shot at a time, 20-cell layer): the
+  // streaming tiles as one persistent launch of 64 x 16 tiles where the grid
+  // takes whole 64-plane chunks (512^3: 0.444 ms against 0.447 for one
+  // workgroup per tile); on smaller grids the persistent launch's short
+  // chunks and few items per workgroup cost more than its balance gains,
+  // and one workgroup per 64 x 8 tile is the fastest (160^3: 29.5 us
+  // against 44.9; 384^3: 181 against 209)
+  const bool large = wave::auto_zchunk(c->L.nx, c->L.ny, c->L.nz, 1, 16) >= 64;
+  c->variant = c->groups >= 8 && large ? WAVE_KERNEL_PERSIST : WAVE_KERNEL_STREAM;
   c->ry = 1;
-  c->nw = 16;
+  c->nw = large ? 16 : 8;
   c->zchunk = 0;
   c->timing = false;
   c->events_used = 0;

@@ -56,6 +56,22 @@ def test_c2_float32_within_tolerance_of_float64_after_1000_steps():
     assert arr["traces_f64"].shape[0] == 1000
 
 
+def test_c3_float32_within_tolerance_of_float64():
+    """The 1024^3 shot with a 32-cell layer (seed 1003): the stored distance
+    of the float32 mode from float64 after the stored step count meets the
+    bar, on the whole field and the traces, and the samples agree."""
+    p = os.path.join(GOLD, "c3_fp64_gap.json")
+    if not os.path.exists(p):
+        pytest.skip("c3 golden not generated")
+    meta, arr = load("c3")
+    s = synth.config_c3(steps=meta["steps"])
+    assert (meta["grid"], meta["layer"], meta["seed"]) == ([s.nx, s.ny, s.nz], s.w, s.seed)
+    assert meta["field_rel_l2"] <= TOL and meta["traces_rel_l2"] <= TOL
+    assert rel_l2(arr["plane_f32"], arr["plane_f64"]) <= TOL
+    assert rel_l2(arr["traces_f32"], arr["traces_f64"]) <= TOL
+    assert arr["traces_f64"].shape[0] == meta["steps"]
+
+
 def test_c2_16bit_storage_distance_is_recorded():
     """16-bit wavefield storage over the 1000 steps: the distance from float64
     is a measured figure (each stored value is rounded every step, and the

@@ -161,13 +161,27 @@ def c2_accuracy(W, shot, storage, kernel):
 
 
 def sampled_error(golden_entry, arr, u, traces):
-    """rel L2 of a GPU result against a float64 golden entry's samples
-    (plane through the source, traces of every few receivers)."""
+    """rel L2 of a GPU result against a float64 golden entry's samples: the
+    final field on a plane through the source, the traces of every few
+    receivers over the whole run, and how far the final field has decayed
+    (its sampled maximum over the traces' peak; a long run ends on the small
+    remainder the layer has not absorbed yet, whose relative error is large
+    for 16-bit storage although its absolute error is not)."""
     import numpy as np
     key = golden_entry["key"]
     ps = 8
     plane = u[::ps, golden_entry["plane_j"], ::ps]
-    return max(rel_l2(plane, arr[f"{key}_plane"]), rel_l2(traces[:, ::8], arr[f"{key}_traces"]))
+    g_plane, g_tr = arr[f"{key}_plane"], arr[f"{key}_traces"]
+    return {"field": round(rel_l2(plane, g_plane), 9),
+            "traces": round(rel_l2(traces[:, ::8], g_tr), 9),
+            "final_over_peak": float(f"{np.abs(g_plane).max() / max(np.abs(g_tr).max(), 1e-30):.3g}")}
+
+
+def error_summary(errs):
+    """Largest field and trace errors over a set of sampled_error results."""
+    return {"max_field_rel_l2": max(e["field"] for e in errs),
+            "max_traces_rel_l2": max(e["traces"] for e in errs),
+            "min_final_over_peak": min(e["final_over_peak"] for e in errs)}
 
 
 def build_shots(specs, threads=8):
@@ -306,7 +320,7 @@ def batched_rate(W, torch, count):
         errs = {}
         for e in check:
             m = members[e["index"]]
-            errs[e["key"]] = round(sampled_error(e, gold[1], m.read(W.WAVE_FIELD_U), m.traces()), 9)
+            errs[e["key"]] = sampled_error(e, gold[1], m.read(W.WAVE_FIELD_U), m.traces())
         for m in members:
             m.close()
         out[f"batched_{storage}"] = {"value": round(work / dt / 1e9, 3), "unit": "Gpoints/s",
@@ -314,8 +328,8 @@ def batched_rate(W, torch, count):
                                      "sweep_bytes_algorithmic": alg,
                                      "gbps_algorithmic_incl_tuning": round(alg / dt / 1e9, 1)}
         if errs:
-            out[f"batched_{storage}"]["max_rel_l2_vs_fp64"] = max(errs.values())
-            out[f"batched_{storage}"]["rel_l2_vs_fp64_per_shot"] = errs
+            out[f"batched_{storage}"]["error_vs_fp64"] = error_summary(list(errs.values()))
+            out[f"batched_{storage}"]["error_vs_fp64_per_shot"] = errs
         log(f"[bench] batched {storage}: {work / dt / 1e9:.1f} Gpt/s ({dt:.2f} s), errors {errs}")
     # the same shots one at a time, plain float32 launches (set-up untimed,
     # like the batched leg's)
@@ -334,9 +348,9 @@ def batched_rate(W, torch, count):
     out["batched_f32_over_one_at_a_time"] = round(out["batched_f32"]["value"] /
                                                   out["one_at_a_time_f32"]["value"], 4)
     if gold:
-        out["error_sample"] = (f"max over shots {[e['index'] for e in check]} of rel L2 vs the "
-                               "float64 oracle on an xz plane through the source (every 8th "
-                               "point) and every 8th receiver trace")
+        out["error_sample"] = (f"shots {[e['index'] for e in check]}: rel L2 vs the float64 "
+                               "oracle of the final field on an xz plane through the source "
+                               "(every 8th point) and of every 8th receiver's trace")
     log(f"[bench] one at a time f32: {work / solo / 1e9:.1f} Gpt/s ({solo:.2f} s)")
     return out
 
@@ -361,20 +375,29 @@ def serve_run(W, torch, count, rate=20.0, check_errors=True):
     ex = GpuExecutor(graph_steps=10)
     srv = Server(ex, budget_bytes=240 * 10 ** 9, block_steps=50)
     t0 = time.perf_counter()
-    done = srv.run(reqs, keep_fields=set(check))
+    done = srv.run(reqs)
     wall = time.perf_counter() - t0
     ex.close()
     out = summarize(done, wall)
     out["offered_gpoints_per_s"] = round(offered / 1e9, 3)
     out["arrival_rate_per_s"] = rate
     if check:
+        # errors from a second, untimed pass over the golden's requests (all
+        # arriving at once), so that reading whole fields back does not slow
+        # the timed loop; a served result does not depend on the batch it
+        # ran in (bit for bit, tested), so these are the timed pass's values
+        again = [Request(rid=q, arrival=0.0, shot=reqs[q].shot, storage=reqs[q].storage)
+                 for q in sorted(check)]
+        ex2 = GpuExecutor(graph_steps=10)
+        done2 = Server(ex2, budget_bytes=240 * 10 ** 9, block_steps=50).run(
+            again, keep_fields=set(check))
+        ex2.close()
         errs = {}
-        for r in done:
-            if r.rid in check and r.error is None:
-                e = sampled_error(check[r.rid], gold[1], r.field, r.traces)
-                errs.setdefault(r.storage, []).append(e)
-        out["max_rel_l2_vs_fp64"] = {k: round(max(v), 9) for k, v in errs.items()}
-        out["checked_requests"] = {k: len(v) for k, v in errs.items()}
+        for r in done2:
+            if r.error is None:
+                errs.setdefault(r.storage, []).append(
+                    sampled_error(check[r.rid], gold[1], r.field, r.traces))
+        out["error_vs_fp64"] = {k: dict(error_summary(v), requests=len(v)) for k, v in errs.items()}
     log(f"[bench] serve: {out}")
     return out
 

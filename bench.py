@@ -118,25 +118,26 @@ def rel_l2(a, b) -> float:
     return float(np.linalg.norm(a - b) / nb) if nb > 0 else float("nan")
 
 
-def c2_accuracy(W, shot, storage, kernel):
+def c2_accuracy(W, shot, storage, kernel, sr=False):
     """The benchmark shot run for the golden's step count (1000, the paper's
     protocol) on the GPU with the given launch, against the float64 oracle on
     the golden's samples, and whether it equals the oracle's own
-    float32-arithmetic mode there bit for bit."""
+    float32-arithmetic mode there bit for bit (not with stochastically
+    rounded bf16 storage, `sr`, whose golden holds the float64 samples only)."""
     import dataclasses
     import numpy as np
     import synth
     base = {(512, 20): "c2", (1024, 32): "c3"}.get((shot.nx, shot.w))
     if base is None:
         return None
-    g = load_golden(base if storage == "f32" else f"{base}_{storage}")
+    g = load_golden(base if storage == "f32" or sr else f"{base}_{storage}")
     if g is None or [shot.nx, shot.ny, shot.nz] != g[0]["grid"] or shot.w != g[0]["layer"] \
             or shot.seed != g[0]["seed"]:
         return None
     meta, arr = g
     steps = meta["steps"]
     s = dataclasses.replace(shot, steps=steps, wavelet=synth.ricker(steps, shot.dt)[None, :])
-    sh = W.shot_from_synth(s, storage=storage, max_steps=steps)
+    sh = W.shot_from_synth(s, storage=storage, max_steps=steps, stochastic_round=sr)
     sh.set_kernel(*kernel)
     sh.step(steps)
     u = sh.read(W.WAVE_FIELD_U)
@@ -145,16 +146,19 @@ def c2_accuracy(W, shot, storage, kernel):
     sm = meta["sample"]
     plane = np.ascontiguousarray(u[::sm["plane_stride"], sm["plane_j"], ::sm["plane_stride"]])
     trs = np.ascontiguousarray(tr[:, ::sm["receiver_stride"]])
-    same = bool(np.array_equal(plane, arr["plane_f32"]) and
-                np.array_equal(trs.astype(np.float32), arr["traces_f32"]))
+    same = None if sr else bool(np.array_equal(plane, arr["plane_f32"]) and
+                                np.array_equal(trs.astype(np.float32), arr["traces_f32"]))
     out = {"steps": steps,
            "rel_l2_vs_fp64": {"field_sample": round(rel_l2(plane, arr["plane_f64"]), 10),
                               "traces_sample": round(rel_l2(trs, arr["traces_f64"]), 10)},
-           "equals_oracle_same_arithmetic_on_sample": same,
+           "equals_oracle_same_arithmetic_on_sample": same}
+    if not sr:
+        out.update({
            "oracle_whole_field_rel_l2_vs_fp64": meta["field_rel_l2"],
-           "oracle_traces_rel_l2_vs_fp64": meta["traces_rel_l2"],
+           "oracle_traces_rel_l2_vs_fp64": meta["traces_rel_l2"]})
+    out.update({
            "sample": f"xz plane j={sm['plane_j']} every {sm['plane_stride']}th point, "
-                     f"every {sm['receiver_stride']}th receiver trace"}
+                     f"every {sm['receiver_stride']}th receiver trace"})
     log(f"[bench] {storage} {shot.nx}^3 x {steps} steps vs fp64: {out['rel_l2_vs_fp64']} "
         f"(equals oracle: {same})")
     return out
@@ -222,13 +226,15 @@ def copy_bandwidth(W, torch, nbytes=2 << 30, reps=10):
     return out
 
 
-def plain_rate(W, torch, n, w, storage, steps, seed=1002, accuracy=True):
-    """One shot, plain launches, given storage: Gpoints/s, the sweep
-    kernel's algorithmic GB/s, and (with a golden for the grid) the error of
-    a 1000-step run against float64."""
+def plain_rate(W, torch, n, w, storage, steps, seed=1002, accuracy=True, sr=False):
+    """One shot, plain launches, given storage (`sr`: bf16 rounded
+    stochastically): Gpoints/s, the sweep kernel's algorithmic GB/s, and
+    (with a golden for the grid) the error of a 1000-step run against
+    float64."""
     import synth
     shot = synth.config_c2(steps=steps + 20 + 256, n=n, w=w, seed=seed)
-    sh = W.shot_from_synth(shot, storage=storage, max_steps=steps + 20 + 50 + 256, two_step=True)
+    sh = W.shot_from_synth(shot, storage=storage, max_steps=steps + 20 + 50 + 256,
+                           two_step=not sr, stochastic_round=sr)
     cfg = sh.tune(2)
     sh.step(max(0, 20 - sh.step_count))
     sh.sync()
@@ -245,11 +251,12 @@ def plain_rate(W, torch, n, w, storage, steps, seed=1002, accuracy=True):
     sh.close()
     log(f"[bench] {storage} {n}^3: {shot.points * steps / ms / 1e6:.1f} Gpt/s, sweep {gbs:.0f} GB/s")
     out = {"value": round(shot.points * steps / ms / 1e6, 3), "unit": "Gpoints/s",
-           "storage": storage, "steps": steps, "kernel": describe(cfg),
+           "storage": storage + (" stochastic rounding" if sr else ""), "steps": steps,
+           "kernel": describe(cfg),
            "sweep_ms": round(kms / k, 5),
            "sweep_gbps_algorithmic": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
     if accuracy:
-        out["accuracy"] = c2_accuracy(W, shot, storage, cfg)
+        out["accuracy"] = c2_accuracy(W, shot, storage, cfg, sr=sr)
     return out
 
 
@@ -449,7 +456,7 @@ def main():
                     help="skip the bf16, batched and serving measurements")
     ap.add_argument("--batch-shots", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=256)
-    ap.add_argument("--extras", default="bf16,batched,serve,serve_low,shapes,large",
+    ap.add_argument("--extras", default="bf16,bf16_sr,batched,serve,serve_low,shapes,large",
                     help="comma-separated measurements beside the headline: bf16, batched, "
                          "serve, serve_low, shapes, large (1024^3)")
     ap.add_argument("--no-accuracy", action="store_true",
@@ -537,6 +544,8 @@ def main():
         extras = {}
         if "bf16" in legs:
             extras["bf16_plain"] = plain_rate(W, torch, args.n, args.w, "bf16", 200)
+        if "bf16_sr" in legs:
+            extras["bf16_sr_plain"] = plain_rate(W, torch, args.n, args.w, "bf16", 200, sr=True)
         if "batched" in legs:
             extras["batched"] = batched_rate(W, torch, args.batch_shots)
         if "serve" in legs:

@@ -62,6 +62,22 @@ typedef enum wave_storage { WAVE_F32 = 0, WAVE_BF16 = 1, WAVE_F16 = 2 } wave_sto
                               that wave_step can take two time steps per
                               launch (WAVE_KERNEL_STREAM2); not with an eta
                               array */
+#define WAVE_STOCH_ROUND 8 /* bf16 storage only: every u^{n+1} the sweep writes
+                              is rounded stochastically instead of to nearest
+                              even: its float32 value is truncated to bf16 and
+                              rounded up in magnitude with probability equal
+                              to the dropped fraction of the bf16 ulp.  The
+                              16 random bits of point (i, j, k) at step n are
+                              half number i mod 2 of pcg(q xor pcg(n)), pcg
+                              being the 32-bit hash of Jarzynski and Olano
+                              (JCGT 2020: a PCG step and its RXS-M-XS output
+                              permutation) and q = (k ny + j) ceil(nx / 2) +
+                              floor(i / 2) modulo 2^32.  So results are
+                              reproducible and do not depend on the launch
+                              shape.  The source add stays
+                              round-to-nearest.  Not with WAVE_TWO_STEP; the
+                              3-D code shapes (GMEM, RING, SHIFT) refuse such
+                              contexts */
 
 typedef struct wave_desc {
     int32_t nx, ny, nz;  /* total extents incl. the layer, 1..32768, and
@@ -70,7 +86,8 @@ typedef struct wave_desc {
     double dx, dy, dz;   /* grid spacing (m), > 0                          */
     double dt;           /* time step (s), > 0                             */
     int32_t storage;     /* wave_storage of u                              */
-    int32_t flags;       /* WAVE_DAMPING_OFF | WAVE_ETA_ARRAY | WAVE_TWO_STEP */
+    int32_t flags;       /* WAVE_DAMPING_OFF | WAVE_ETA_ARRAY | WAVE_TWO_STEP |
+                            WAVE_STOCH_ROUND */
     double refl;         /* target reflection of the default eta profile,
                             0 < refl < 1 (1e-3 is typical)                 */
     int32_t max_src;     /* source table capacity, >= 0                    */

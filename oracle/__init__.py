@@ -35,7 +35,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
-STORAGE = {"f32": 0, "bf16": 1, "f16": 2}
+STORAGE = {"f32": 0, "bf16": 1, "f16": 2, "bf16sr": 3}
 
 
 def build(force: bool = True) -> str:
@@ -77,6 +77,12 @@ def _load():
         lib.ora_round_f16.restype = C.c_float
         lib.ora_round_array.argtypes = [P, C.c_longlong, i32]
         lib.ora_round_array.restype = None
+        lib.ora_pcg_hash.argtypes = [C.c_uint32]
+        lib.ora_pcg_hash.restype = C.c_uint32
+        lib.ora_sr_bits.argtypes = [i32] * 7
+        lib.ora_sr_bits.restype = C.c_uint
+        lib.ora_round_bf16_sr.argtypes = [C.c_float, C.c_uint]
+        lib.ora_round_bf16_sr.restype = C.c_float
         lib.ora_run_f64.argtypes = [i32, i32, i32, i32, f64, f64, f64, P, P, P, f64,
                                     i32, P, P, i32, i32, P, P, i32, i32, P, P, P]
         lib.ora_run_f64.restype = i32
@@ -148,6 +154,21 @@ def round_bf16(x: float) -> float:
 
 def round_f16(x: float) -> float:
     return float(_load().ora_round_f16(float(x)))
+
+
+def pcg_hash(v: int) -> int:
+    """The 32-bit "pcg" hash (PCG step and RXS-M-XS permutation) of v."""
+    return int(_load().ora_pcg_hash(v & 0xFFFFFFFF))
+
+
+def sr_bits(n: int, nx: int, ny: int, nz: int, i: int, j: int, k: int) -> int:
+    """The 16 random bits of point (i, j, k) at step n (stochastic rounding)."""
+    return int(_load().ora_sr_bits(n, nx, ny, nz, i, j, k))
+
+
+def round_bf16_sr(x: float, r: int) -> float:
+    """Stochastic rounding of float32 x to bfloat16 with 16 random bits r."""
+    return float(_load().ora_round_bf16_sr(float(x), int(r)))
 
 
 def regions(nx, ny, nz, w, order: int = 0) -> np.ndarray:

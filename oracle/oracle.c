@@ -224,9 +224,56 @@ float ora_round_f16(float x)
     return (float)round_fmt((double)x, 11, -14, 65504.0);
 }
 
+/* ---- stochastic rounding to bfloat16 (the library's WAVE_STOCH_ROUND) ---
+ * The "pcg" hash of Jarzynski and Olano ("Hash functions for GPU
+ * rendering", JCGT 2020): one step of the PCG linear congruential generator
+ * (multiplier 747796405, increment 2891336453) followed by PCG's RXS-M-XS
+ * output permutation (O'Neill 2014: a random shift of 4..19 chosen by the top
+ * four bits, multiply by 277803737, xor-shift by 22). */
+uint32_t ora_pcg_hash(uint32_t v)
+{
+    uint32_t state = v * 747796405u + 2891336453u;
+    uint32_t shift = (state >> 28) + 4u;
+    uint32_t word = ((state >> shift) ^ state) * 277803737u;
+    return (word >> 22) ^ word;
+}
+
+/* The 16 random bits of point (i, j, k) at step n: the pair index
+ * q = (k ny + j) ceil(nx / 2) + floor(i / 2), taken modulo 2^32, gives the
+ * word pcg(q xor pcg(n)); point i takes its 16-bit half number i mod 2. */
+unsigned ora_sr_bits(int n, int nx, int ny, int nz, int i, int j, int k)
+{
+    (void)nz;
+    uint32_t half_row = (uint32_t)(nx + 1) / 2;
+    uint32_t q = ((uint32_t)k * (uint32_t)ny + (uint32_t)j) * half_row + (uint32_t)(i / 2);
+    uint32_t word = ora_pcg_hash(q ^ ora_pcg_hash((uint32_t)n));
+    return (word >> (16 * (i % 2))) & 0xFFFFu;
+}
+
+/* Stochastic rounding of a float to bfloat16 with 16 uniform random bits r:
+ * the two bfloat16 neighbours of a finite x are its truncation toward zero
+ * (its top 16 bits) and the next value away from zero; the farther one is
+ * taken with probability equal to the dropped fraction f / 2^16 of an ulp,
+ * i.e. exactly when f + r >= 2^16.  Infinities and NaN round to nearest. */
+float ora_round_bf16_sr(float x, unsigned r)
+{
+    if (!isfinite(x)) return ora_round_bf16(x);
+    uint32_t bits;
+    memcpy(&bits, &x, 4);
+    uint32_t f = bits & 0xFFFFu;
+    uint32_t t = bits - f;                               /* truncation toward zero */
+    uint32_t out = (f + (r & 0xFFFFu) >= 0x10000u) ? t + 0x10000u : t;
+    float y;
+    memcpy(&y, &out, 4);
+    return y;
+}
+
+/* storage: 0 float, 1 bfloat16, 2 binary16 (round to nearest even); 3
+ * bfloat16 written by the sweep with stochastic rounding, whose source add
+ * rounds to nearest like 1. */
 static inline float store16(float x, int storage)
 {
-    if (storage == 1) return ora_round_bf16(x);
+    if (storage == 1 || storage == 3) return ora_round_bf16(x);
     if (storage == 2) return ora_round_f16(x);
     return x;
 }
@@ -388,7 +435,8 @@ int ora_run_f64(int nx, int ny, int nz, int w, double dx, double dy, double dz,
 /* Same recurrence in float with the fixed operation order given at the top
  * of this file.  vp and eta are the float copies (rounded once from double).
  * storage: 0 = float, 1 = bfloat16, 2 = binary16 for u (values are kept in
- * float arrays but every written u is rounded to the storage format). */
+ * float arrays but every written u is rounded to the storage format); 3 =
+ * bfloat16 with the sweep's u^{n+1} rounded stochastically (see above). */
 int ora_run_f32(int nx, int ny, int nz, int w, double dx, double dy, double dz,
                 const float *vp, const float *eta, const double *etab, double eta_dt,
                 int storage,
@@ -397,7 +445,7 @@ int ora_run_f32(int nx, int ny, int nz, int w, double dx, double dy, double dz,
                 int n0, int steps, float *u_cur, float *u_prev, float *phi)
 {
     if (nx <= 0 || ny <= 0 || nz <= 0 || w < 0 || steps < 0) return -1;
-    if (storage < 0 || storage > 2) return -1;
+    if (storage < 0 || storage > 3) return -1;
     grid_t g = {nx, ny, nz, w};
     size_t n = (size_t)nx * ny * nz;
     double c64[13];
@@ -447,7 +495,9 @@ int ora_run_f32(int nx, int ny, int nz, int w, double dx, double dy, double dz,
                                   U32(u_cur, g, i, j, k + 1) - U32(u_cur, g, i, j, k - 1), gs);
                         phi_next[p] = (phi[p] - gs) / (1.0f + e);
                     }
-                    u_next[p] = store16(un, storage);
+                    u_next[p] = storage == 3
+                                    ? ora_round_bf16_sr(un, ora_sr_bits(step, nx, ny, nz, i, j, k))
+                                    : store16(un, storage);
                 }
         for (int s = 0; s < nsrc; ++s) {
             float wv = (step < nsamp) ? wavelets[(size_t)s * nsamp + step] : 0.0f;

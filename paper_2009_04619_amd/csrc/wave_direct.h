@@ -57,7 +57,12 @@ __device__ __forceinline__ void point_tail(const SweepArgs& a, int x, int y, int
   } else {
     r = upd_inner(c, pu, vp, lap);
   }
-  S::st(un, p, r);
+  if constexpr (S::kSR) {  // stochastic rounding of bf16 storage (WAVE_STOCH_ROUND)
+    const uint32_t r16 = sr_word(pcg_hash((uint32_t)a.step), a.nx, a.ny, x, y, z) >> (16 * (x & 1));
+    un[p] = f32_to_bf16_sr(r, r16);
+  } else {
+    S::st(un, p, r);
+  }
 }
 
 // Point (x, y, z) with every stencil operand read from memory.

@@ -62,6 +62,8 @@ struct SweepArgs {
   float ce;             // -(c[0] + 2 sum c[1..12]): removes the weights' residual
   float q[3];           // 1 / (4 h_a^2)
   int32_t damping;      // 0: Eq. 2 everywhere
+  int32_t step;         // time level n of u^n (counter of the random bits of
+                        // stochastically rounded bf16 storage)
 };
 
 // Two steps per launch (wave_kernels2.hip): u^{n-1}, u^n, phi^n in;

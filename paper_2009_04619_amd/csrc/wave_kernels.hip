@@ -4,7 +4,6 @@
 // source add and receiver sample, the float64 energy, set-up and copy.  The
 // per-point arithmetic they share is in wave_point.h.
 #include <algorithm>
-#include <type_traits>
 
 #include "wave_direct.h"
 #include "wave_internal.h"
@@ -247,6 +246,19 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
     }
   };
 
+  // store u^{n+1} of lane row r at output plane zo (window byte offset so):
+  // bf16 storage rounded stochastically when the context asks for it
+  const uint32_t srkey = S::kSR ? pcg_hash((uint32_t)a.step) : 0u;
+  auto store_u = [&](int r, uint32_t so, float v, int zo) {
+    if constexpr (S::kSR) {
+      const int x = sl.x[r];
+      const uint32_t r16 = sr_word(srkey, a.nx, a.ny, x, sl.y[r], zo) >> (16 * (x & 1));
+      __builtin_amdgcn_raw_buffer_store_b16(f32_to_bf16_sr(v, r16), rn, (int)vo[r], (int)so, kSt);
+    } else {
+      S::bst(rn, vo[r], so, v);
+    }
+  };
+
   // prologue: u(zb-4 .. zb+3+PD) into ring slots 0 .. L-2, operands of planes
   // zb .. zb+PD-1 into operand slots 0 .. PD-1, eta(zb-1 .. zb+PD) into eta
   // slots 0 .. PD+1 (window indices clamped to the window)
@@ -424,7 +436,7 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
           } else {
             res = upd_inner(cz, pu, vp, lap);
           }
-          S::bst(rn, vo[r], so, res);
+          store_u(r, so, res, z - ZD);
         }
         if (stage) {
           A[Sl % 4][r] = xy + F[Sl % 4][r];
@@ -503,7 +515,7 @@ __device__ __forceinline__ void stream_loop(const SweepArgs& a,
         }
         // points past the grid have an out-of-range offset: no branch around
         // the store
-        S::bst(rn, vo[r], sz, res);
+        store_u(r, sz, res, z);
       }
     }
   };
@@ -711,6 +723,7 @@ __global__ __launch_bounds__(64 * NW, WAVE_STREAM_WPS(RY, NW)) void k_sweep_batc
   SweepArgs a = b.sa;
   a.cur = b.u[st.cur];
   a.nxt = b.u[st.cur ^ 1];
+  a.step = st.step;
   // each member's range starts at a multiple of 8 blocks, so the member-local
   // index keeps the XCD in its low 3 bits; tiles follow the single-shot order
   const TileAt t = tile_at(bid - b.block_begin, b.tiles_x, b.tiles_y);
@@ -977,6 +990,7 @@ hipError_t launch_sweep_direct(const SweepArgs& a, int storage, hipStream_t s) {
     case 0: return sweep_direct_t<StF32>(a, s);
     case 1: return sweep_direct_t<StBF16>(a, s);
     case 2: return sweep_direct_t<StF16>(a, s);
+    case 3: return sweep_direct_t<StBF16SR>(a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -988,6 +1002,7 @@ hipError_t launch_sweep_stream(const SweepArgs& a, int storage, int ry, int nw, 
     case 0: return sweep_stream_s<StF32>(a, ry, nw, zchunk, s);
     case 1: return sweep_stream_s<StBF16>(a, ry, nw, zchunk, s);
     case 2: return sweep_stream_s<StF16>(a, ry, nw, zchunk, s);
+    case 3: return sweep_stream_s<StBF16SR>(a, ry, nw, zchunk, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1008,6 +1023,7 @@ hipError_t launch_sweep_persist(const SweepArgs& a, int storage, int ry, int nw,
     case 0: { WAVE_PERSIST_CASE(StF32) }
     case 1: { WAVE_PERSIST_CASE(StBF16) }
     case 2: { WAVE_PERSIST_CASE(StF16) }
+    case 3: { WAVE_PERSIST_CASE(StBF16SR) }
   }
 #undef WAVE_PERSIST_CASE
   return hipErrorInvalidValue;
@@ -1025,6 +1041,7 @@ hipError_t launch_sweep_shuffle(const SweepArgs& a, int storage, int nw, int zch
     case 0: { WAVE_XS_CASE(StF32) }
     case 1: { WAVE_XS_CASE(StBF16) }
     case 2: { WAVE_XS_CASE(StF16) }
+    case 3: { WAVE_XS_CASE(StBF16SR) }
   }
 #undef WAVE_XS_CASE
   return hipErrorInvalidValue;
@@ -1040,6 +1057,7 @@ hipError_t launch_sweep_semi(const SweepArgs& a, int storage, int nw, int zchunk
     case 0: WAVE_SEMI_CASE(StF32)
     case 1: WAVE_SEMI_CASE(StBF16)
     case 2: WAVE_SEMI_CASE(StF16)
+    case 3: WAVE_SEMI_CASE(StBF16SR)
   }
 #undef WAVE_SEMI_CASE
   return hipErrorInvalidValue;
@@ -1050,6 +1068,7 @@ hipError_t launch_inject_record(const InjectArgs& a, int storage, hipStream_t s)
     case 0: hipLaunchKernelGGL(k_inject_record<StF32>, dim3(1), dim3(256), 0, s, a); break;
     case 1: hipLaunchKernelGGL(k_inject_record<StBF16>, dim3(1), dim3(256), 0, s, a); break;
     case 2: hipLaunchKernelGGL(k_inject_record<StF16>, dim3(1), dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_inject_record<StBF16SR>, dim3(1), dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1061,6 +1080,7 @@ hipError_t launch_energy(const EnergyArgs& a, int storage, hipStream_t s) {
     case 0: hipLaunchKernelGGL(k_energy_rows<StF32>, grid, dim3(256), 0, s, a); break;
     case 1: hipLaunchKernelGGL(k_energy_rows<StBF16>, grid, dim3(256), 0, s, a); break;
     case 2: hipLaunchKernelGGL(k_energy_rows<StF16>, grid, dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_energy_rows<StBF16SR>, grid, dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
@@ -1143,6 +1163,7 @@ hipError_t launch_sweep_batch(const BatchShot* shots, BatchState* state, int nsh
     case 0: return sweep_batch_s<StF32>(shots, state, nshots, total_blocks, ry, nw, eta_array, s);
     case 1: return sweep_batch_s<StBF16>(shots, state, nshots, total_blocks, ry, nw, eta_array, s);
     case 2: return sweep_batch_s<StF16>(shots, state, nshots, total_blocks, ry, nw, eta_array, s);
+    case 3: return sweep_batch_s<StBF16SR>(shots, state, nshots, total_blocks, ry, nw, eta_array, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1154,6 +1175,7 @@ hipError_t launch_inject_batch(const BatchShot* shots, BatchState* state, int ns
     case 0: hipLaunchKernelGGL(k_inject_batch<StF32>, dim3(nshots), dim3(256), 0, s, shots, state); break;
     case 1: hipLaunchKernelGGL(k_inject_batch<StBF16>, dim3(nshots), dim3(256), 0, s, shots, state); break;
     case 2: hipLaunchKernelGGL(k_inject_batch<StF16>, dim3(nshots), dim3(256), 0, s, shots, state); break;
+    case 3: hipLaunchKernelGGL(k_inject_batch<StBF16SR>, dim3(nshots), dim3(256), 0, s, shots, state); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

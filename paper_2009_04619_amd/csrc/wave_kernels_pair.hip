@@ -19,7 +19,6 @@
 // rotate over the XCDs per chunk.  The default profile's tables only (no
 // eta array).
 #include <algorithm>
-#include <type_traits>
 
 #include "wave_internal.h"
 #include "wave_point.h"
@@ -74,6 +73,7 @@ template <> struct PairIO<StBF16> {
     __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)vo, (int)so, kSt);
   }
 };
+template <> struct PairIO<StBF16SR> : PairIO<StBF16> {};
 template <> struct PairIO<StF16> {
   static __device__ __forceinline__ f32x2 unpack(uint32_t v) {
     return f32x2{(float)__builtin_bit_cast(_Float16, (uint16_t)(v & 0xffffu)),
@@ -265,7 +265,15 @@ __device__ __forceinline__ void pair_loop(const SweepArgs& a, float (*sm)[(TY + 
       const u32x2 pw{__float_as_uint(nph[0]), __float_as_uint(nph[1])};
       __builtin_amdgcn_raw_buffer_store_b64(pw, rph, (int)fo, (int)sz4, kSt);
     }
-    IO::st(rn, vo, sz, res[0], res[1]);
+    if constexpr (S::kSR) {  // stochastic rounding of bf16 storage (WAVE_STOCH_ROUND);
+                             // x is even, so both points take their bits from one word
+      const uint32_t wd = sr_word(pcg_hash((uint32_t)a.step), a.nx, a.ny, sl.x, sl.y, z);
+      const uint32_t lo = f32_to_bf16_sr(res[0], wd);
+      const uint32_t hi = f32_to_bf16_sr(res[1], wd >> 16);
+      __builtin_amdgcn_raw_buffer_store_b32(lo | (hi << 16), rn, (int)vo, (int)sz, kSt);
+    } else {
+      IO::st(rn, vo, sz, res[0], res[1]);
+    }
   };
 
   using std::integral_constant;
@@ -400,6 +408,7 @@ __global__ __launch_bounds__(64 * TY) void k_sweep_batch_pair(const BatchShot* _
   SweepArgs a = b.sa;
   a.cur = b.u[st.cur];
   a.nxt = b.u[st.cur ^ 1];
+  a.step = st.step;
   const TileAt t = tile_at(bid - b.block_begin, b.tiles_x, b.tiles_y);
   if (t.ty >= b.tiles_y) return;
   const bool damp = a.damping != 0;
@@ -442,6 +451,7 @@ hipError_t launch_sweep_batch_pair(const BatchShot* shots, BatchState* state, in
     case 0: if (ty == 8) { WAVE_BATCH_PAIR(StF32, 8) } else { WAVE_BATCH_PAIR(StF32, 16) }
     case 1: if (ty == 8) { WAVE_BATCH_PAIR(StBF16, 8) } else { WAVE_BATCH_PAIR(StBF16, 16) }
     case 2: if (ty == 8) { WAVE_BATCH_PAIR(StF16, 8) } else { WAVE_BATCH_PAIR(StF16, 16) }
+    case 3: if (ty == 8) { WAVE_BATCH_PAIR(StBF16SR, 8) } else { WAVE_BATCH_PAIR(StBF16SR, 16) }
   }
 #undef WAVE_BATCH_PAIR
   return hipErrorInvalidValue;
@@ -453,6 +463,7 @@ hipError_t launch_sweep_pair(const SweepArgs& a, int storage, int ty, int zchunk
     case 0: return pair_s<StF32>(a, ty, zchunk, s);
     case 1: return pair_s<StBF16>(a, ty, zchunk, s);
     case 2: return pair_s<StF16>(a, ty, zchunk, s);
+    case 3: return pair_s<StBF16SR>(a, ty, zchunk, s);
   }
   return hipErrorInvalidValue;
 }

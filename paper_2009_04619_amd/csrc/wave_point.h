@@ -52,6 +52,7 @@ constexpr int kSt = 2;
 // ---- wavefield storage types ------------------------------------------------
 struct StF32 {
   using T = float;
+  static constexpr bool kSR = false;  // stochastic rounding of u^{n+1} (bf16 only)
   static __device__ __forceinline__ float ld(const T* p, int64_t i) { return p[i]; }
   static __device__ __forceinline__ void st(T* p, int64_t i, float v) { p[i] = v; }
   static __device__ __forceinline__ float cvt(T v) { return v; }
@@ -75,8 +76,38 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
   return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 
+// Stochastic rounding of bf16 storage (WAVE_STOCH_ROUND).  The random bits
+// come from the "pcg" hash of Jarzynski and Olano ("Hash functions for GPU
+// rendering", JCGT 2020): one step of the PCG linear congruential generator
+// followed by its RXS-M-XS output permutation (O'Neill 2014), a bijection of
+// 32-bit words.  The word of the point pair q = (k ny + j) ceil(nx / 2) +
+// floor(i / 2) at step n is pcg(q xor pcg(n)) (q taken modulo 2^32); point i
+// takes its 16-bit half i mod 2.  So the bits of a point depend on (n, k, j,
+// i) only, never on the tile that computes it.
+__host__ __device__ __forceinline__ uint32_t pcg_hash(uint32_t v) {
+  const uint32_t state = v * 747796405u + 2891336453u;
+  const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+  return (word >> 22u) ^ word;
+}
+// word of the pair holding x in row (y, z); key = pcg_hash(step)
+__device__ __forceinline__ uint32_t sr_word(uint32_t key, int nx, int ny, int x, int y, int z) {
+  const uint32_t q = ((uint32_t)z * (uint32_t)ny + (uint32_t)y) * (uint32_t)((nx + 1) >> 1) +
+                     (uint32_t)(x >> 1);
+  return pcg_hash(q ^ key);
+}
+
+// float -> bfloat16 truncated toward zero and raised by one ulp in magnitude
+// when the dropped 16 bits plus the random 16 bits carry; infinities and NaN
+// take the round-to-nearest path.
+__device__ __forceinline__ uint16_t f32_to_bf16_sr(float f, uint32_t r16) {
+  const uint32_t b = __float_as_uint(f);
+  if ((b & 0x7F800000u) == 0x7F800000u) return __builtin_bit_cast(uint16_t, (__bf16)f);
+  return (uint16_t)((b + (r16 & 0xFFFFu)) >> 16);
+}
+
 struct StBF16 {
   using T = uint16_t;
+  static constexpr bool kSR = false;
   static __device__ __forceinline__ float ld(const T* p, int64_t i) {
     return __uint_as_float((uint32_t)p[i] << 16);
   }
@@ -95,8 +126,15 @@ struct StBF16 {
   }
 };
 
+// bf16 storage whose sweeps round u^{n+1} stochastically (WAVE_STOCH_ROUND);
+// every other access, the source add included, is the bf16 one.
+struct StBF16SR : StBF16 {
+  static constexpr bool kSR = true;
+};
+
 struct StF16 {
   using T = _Float16;
+  static constexpr bool kSR = false;
   static __device__ __forceinline__ float ld(const T* p, int64_t i) { return (float)p[i]; }
   static __device__ __forceinline__ void st(T* p, int64_t i, float v) { p[i] = (_Float16)v; }
   static __device__ __forceinline__ float cvt(T v) { return (float)v; }

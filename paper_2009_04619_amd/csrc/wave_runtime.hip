@@ -63,7 +63,12 @@ bool desc_ok(const wave_desc* d, std::string* why) {
   if (!(d->dt > 0) || !isfinite(d->dt)) return bad("dt must be finite and > 0");
   if (d->storage != WAVE_F32 && d->storage != WAVE_BF16 && d->storage != WAVE_F16)
     return bad("unknown storage type");
-  if (d->flags & ~(WAVE_DAMPING_OFF | WAVE_ETA_ARRAY | WAVE_TWO_STEP)) return bad("unknown flags");
+  if (d->flags & ~(WAVE_DAMPING_OFF | WAVE_ETA_ARRAY | WAVE_TWO_STEP | WAVE_STOCH_ROUND))
+    return bad("unknown flags");
+  if ((d->flags & WAVE_STOCH_ROUND) && d->storage != WAVE_BF16)
+    return bad("WAVE_STOCH_ROUND applies to bf16 storage only");
+  if ((d->flags & WAVE_STOCH_ROUND) && (d->flags & WAVE_TWO_STEP))
+    return bad("WAVE_STOCH_ROUND is not available with WAVE_TWO_STEP");
   if ((d->flags & WAVE_TWO_STEP) && (d->flags & WAVE_ETA_ARRAY) && !(d->flags & WAVE_DAMPING_OFF))
     return bad("WAVE_TWO_STEP supports the default damping profile only, not an eta array");
   if (!(d->flags & WAVE_DAMPING_OFF) && d->w > 0 && !(d->refl > 0 && d->refl < 1))
@@ -76,6 +81,12 @@ bool desc_ok(const wave_desc* d, std::string* why) {
 bool damping_on(const wave_desc* d) { return !(d->flags & WAVE_DAMPING_OFF) && d->w > 0; }
 bool eta_array(const wave_desc* d) { return damping_on(d) && (d->flags & WAVE_ETA_ARRAY); }
 bool two_step(const wave_desc* d) { return (d->flags & WAVE_TWO_STEP) != 0; }
+bool stoch_round(const wave_desc* d) { return (d->flags & WAVE_STOCH_ROUND) != 0; }
+// Storage code of the kernel instances a context runs: the wave_storage
+// value, or 3 for bf16 storage rounded stochastically.
+int kernel_storage(const wave_desc* d) {
+  return d->storage == WAVE_BF16 && stoch_round(d) ? 3 : d->storage;
+}
 
 size_t eta_tables_bytes(const wave_desc* d);
 
@@ -380,6 +391,7 @@ wave::SweepArgs sweep_args(const wave_ctx* c) {
   sa.ce = (float)(-e);
   memcpy(sa.q, c->q, sizeof(sa.q));
   sa.damping = c->damp ? 1 : 0;
+  sa.step = (int32_t)c->step;
   return sa;
 }
 
@@ -412,6 +424,7 @@ bool in_grid(const wave_ctx* c, int i, int j, int k) {
 
 struct wave_batch {
   int32_t storage;
+  int32_t kstore;             // kernel storage code of the members (3: bf16 rounded stochastically)
   int32_t max_shots;
   hipStream_t user_stream;   // the members' stream
   hipStream_t stream;        // the batch's own stream (graphs can be captured on it)
@@ -565,11 +578,11 @@ void batch_layout(wave_batch* b) {
 hipError_t batch_launch_step(wave_batch* b, int k) {
   hipError_t e = b->ry == 0
                      ? wave::launch_sweep_batch_pair(b->d_shots, b->d_state, k, b->prefix_blocks[k],
-                                                     b->storage, b->nw, b->stream)
+                                                     b->kstore, b->nw, b->stream)
                      : wave::launch_sweep_batch(b->d_shots, b->d_state, k, b->prefix_blocks[k],
-                                                b->storage, b->ry, b->nw, b->eta_any, b->stream);
+                                                b->kstore, b->ry, b->nw, b->eta_any, b->stream);
   if (e != hipSuccess) return e;
-  return wave::launch_inject_batch(b->d_shots, b->d_state, k, b->storage, b->stream);
+  return wave::launch_inject_batch(b->d_shots, b->d_state, k, b->kstore, b->stream);
 }
 
 // The captured block of graph_steps steps for the first k members.
@@ -923,7 +936,7 @@ int step_pair(wave_ctx* c, int zc) {
     ia.step = (int32_t)c->step;
     ia.traces = traces;
     ia.trace_row = c->trace_count;
-    e = wave::launch_inject_record(ia, c->d.storage, c->stream);
+    e = wave::launch_inject_record(ia, kernel_storage(&c->d), c->stream);
     if (e != hipSuccess) return dev_fail(c, e, "record launch");
   }
   if (c->nsrc > 0 || c->nrec > 0) {   // sources and receivers of step n+1
@@ -932,7 +945,7 @@ int step_pair(wave_ctx* c, int zc) {
     ia.step = (int32_t)c->step + 1;
     ia.traces = traces;
     ia.trace_row = c->trace_count + (c->nrec > 0 ? 1 : 0);
-    e = wave::launch_inject_record(ia, c->d.storage, c->stream);
+    e = wave::launch_inject_record(ia, kernel_storage(&c->d), c->stream);
     if (e != hipSuccess) return dev_fail(c, e, "inject/record launch");
   }
   c->iprev = other[0];
@@ -977,21 +990,21 @@ int wave_step(wave_ctx* c, int32_t n) {
                                    : wave::auto_zchunk25(c->L.nx, c->L.ny, c->L.nz, c->shp[1]);
   auto launch_one = [&](const wave::SweepArgs& s) -> hipError_t {
     if (c->variant == WAVE_KERNEL_GMEM)
-      return wave::launch_sweep_gmem(s, c->d.storage, c->shp[0], c->shp[1], c->shp[2], c->stream);
+      return wave::launch_sweep_gmem(s, kernel_storage(&c->d), c->shp[0], c->shp[1], c->shp[2], c->stream);
     if (shape25)
-      return wave::launch_sweep_25d(s, c->d.storage, c->variant == WAVE_KERNEL_RING ? 0 : 1,
+      return wave::launch_sweep_25d(s, kernel_storage(&c->d), c->variant == WAVE_KERNEL_RING ? 0 : 1,
                                     c->shp[1], zc25, c->stream);
     if (c->variant == WAVE_KERNEL_PAIR)
-      return wave::launch_sweep_pair(s, c->d.storage, c->shp[1], zcp, c->stream);
+      return wave::launch_sweep_pair(s, kernel_storage(&c->d), c->shp[1], zcp, c->stream);
     if (c->variant == WAVE_KERNEL_SEMI)
-      return wave::launch_sweep_semi(s, c->d.storage, c->shp[1], zcp, c->stream);
+      return wave::launch_sweep_semi(s, kernel_storage(&c->d), c->shp[1], zcp, c->stream);
     if (c->variant == WAVE_KERNEL_SHUFFLE)
-      return wave::launch_sweep_shuffle(s, c->d.storage, c->shp[1],
+      return wave::launch_sweep_shuffle(s, kernel_storage(&c->d), c->shp[1],
                                         stream_zchunk(c, 1, c->shp[1], c->shp[2]), c->stream);
     if (c->variant == WAVE_KERNEL_PERSIST && !direct)
-      return wave::launch_sweep_persist(s, c->d.storage, c->ry, c->nw, zc, c->groups, c->stream);
-    return direct ? wave::launch_sweep_direct(s, c->d.storage, c->stream)
-                  : wave::launch_sweep_stream(s, c->d.storage, c->ry, c->nw, zc, c->stream);
+      return wave::launch_sweep_persist(s, kernel_storage(&c->d), c->ry, c->nw, zc, c->groups, c->stream);
+    return direct ? wave::launch_sweep_direct(s, kernel_storage(&c->d), c->stream)
+                  : wave::launch_sweep_stream(s, kernel_storage(&c->d), c->ry, c->nw, zc, c->stream);
   };
 
   wave::InjectArgs ia = inject_args(c);
@@ -999,6 +1012,7 @@ int wave_step(wave_ctx* c, int32_t n) {
   for (int t = 0; t < n; ++t) {
     sa.cur = c->u_origin(c->icur);
     sa.nxt = c->u_origin(c->iprev);
+    sa.step = (int32_t)c->step;
     hipEvent_t e1;
     int rc = timing_begin(c, &e1);
     if (rc) return rc;
@@ -1010,7 +1024,7 @@ int wave_step(wave_ctx* c, int32_t n) {
       ia.step = (int32_t)c->step;
       ia.traces = c->nrec > 0 ? reinterpret_cast<double*>(c->at(c->plan.traces)) : nullptr;
       ia.trace_row = c->trace_count;
-      e = wave::launch_inject_record(ia, c->d.storage, c->stream);
+      e = wave::launch_inject_record(ia, kernel_storage(&c->d), c->stream);
       if (e != hipSuccess) return dev_fail(c, e, "inject/record launch");
     }
     std::swap(c->icur, c->iprev);
@@ -1116,7 +1130,7 @@ int wave_energy(wave_ctx* c, double* out) {
   memcpy(ea.c, c->c64, sizeof(ea.c));
   ea.partial = reinterpret_cast<double*>(c->at(c->plan.partial));
   ea.result = reinterpret_cast<double*>(c->at(c->plan.eres));
-  hipError_t e = wave::launch_energy(ea, c->d.storage, c->stream);
+  hipError_t e = wave::launch_energy(ea, kernel_storage(&c->d), c->stream);
   if (e != hipSuccess) return dev_fail(c, e, "energy launch");
   double r[2];
   HIPCHK(c, hipMemcpyAsync(r, ea.result, 16, hipMemcpyDeviceToHost, c->stream), "hipMemcpyAsync");
@@ -1184,7 +1198,7 @@ int wave_energy_noalloc(wave_ctx* c, double* dev_out) {
   memcpy(ea.c, c->c64, sizeof(ea.c));
   ea.partial = ws;
   ea.result = dev_out;
-  const hipError_t e = wave::launch_energy(ea, c->d.storage, c->stream);
+  const hipError_t e = wave::launch_energy(ea, kernel_storage(&c->d), c->stream);
   if (e != hipSuccess) return dev_fail(c, e, "energy launch");
   return WAVE_OK;
 }
@@ -1514,6 +1528,7 @@ int wave_batch_create(int32_t storage, int32_t max_shots, void* dev_arena, size_
   if (arena_bytes < need) return fail(WAVE_ENOMEM, "batch arena too small");
   wave_batch* b = new wave_batch();
   b->storage = storage;
+  b->kstore = storage;
   b->max_shots = max_shots;
   b->user_stream = static_cast<hipStream_t>(hip_stream);
   b->arena = static_cast<char*>(dev_arena);
@@ -1551,6 +1566,8 @@ int wave_batch_add(wave_batch* b, wave_ctx* c, int32_t nsteps) {
   CHECK_CTX(c);
   if (c->batch) return fail(WAVE_EINVAL, "context already in a batch");
   if (c->d.storage != b->storage) return fail(WAVE_EINVAL, "storage type differs from the batch's");
+  if (!b->members.empty() && kernel_storage(&c->d) != b->kstore)
+    return fail(WAVE_EINVAL, "rounding (WAVE_STOCH_ROUND) differs from the batch members'");
   if ((int)b->members.size() >= b->max_shots) return fail(WAVE_EINVAL, "batch full");
   if (nsteps < 0) return fail(WAVE_EINVAL, "nsteps < 0");
   if (c->nrec > 0 && (int64_t)c->trace_count + nsteps > c->d.max_steps)
@@ -1569,6 +1586,7 @@ int wave_batch_add(wave_batch* b, wave_ctx* c, int32_t nsteps) {
     HIPCHK(c, hipEventRecord(c->ev_join, c->stream), "hipEventRecord");
     BCHK(b, hipStreamWaitEvent(b->stream, c->ev_join, 0), "hipStreamWaitEvent");
   }
+  if (b->members.empty()) b->kstore = kernel_storage(&c->d);
   b->members.push_back(c);
   b->remaining.push_back(nsteps);
   c->batch = b;

@@ -225,6 +225,7 @@ hipError_t launch_sweep_gmem(const SweepArgs& a, int storage, int bx, int by, in
     case 0: return gmem_s<StF32>(a, bx, by, bz, s);
     case 1: return gmem_s<StBF16>(a, bx, by, bz, s);
     case 2: return gmem_s<StF16>(a, bx, by, bz, s);
+    case 3: return gmem_s<StBF16SR>(a, bx, by, bz, s);
   }
   return hipErrorInvalidValue;
 }
@@ -236,6 +237,7 @@ hipError_t launch_sweep_25d(const SweepArgs& a, int storage, int shape, int ty, 
     case 0: return sweep25_s<StF32>(a, shape, ty, zchunk, s);
     case 1: return sweep25_s<StBF16>(a, shape, ty, zchunk, s);
     case 2: return sweep25_s<StF16>(a, shape, ty, zchunk, s);
+    case 3: return sweep25_s<StBF16SR>(a, shape, ty, zchunk, s);
   }
   return hipErrorInvalidValue;
 }

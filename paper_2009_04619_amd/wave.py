@@ -28,6 +28,7 @@ WAVE_F32, WAVE_BF16, WAVE_F16 = 0, 1, 2
 WAVE_DAMPING_OFF = 1
 WAVE_ETA_ARRAY = 2
 WAVE_TWO_STEP = 4
+WAVE_STOCH_ROUND = 8
 WAVE_FIELD_U, WAVE_FIELD_UPREV, WAVE_FIELD_PHI, WAVE_FIELD_VP, WAVE_FIELD_ETA = 0, 1, 2, 3, 4
 WAVE_KERNEL_DIRECT, WAVE_KERNEL_STREAM, WAVE_KERNEL_STREAM2 = 0, 1, 2
 WAVE_KERNEL_GMEM, WAVE_KERNEL_RING, WAVE_KERNEL_SHIFT, WAVE_KERNEL_PAIR = 3, 4, 5, 6
@@ -306,13 +307,14 @@ def wave_last_error() -> str:
 
 
 def make_desc(nx, ny, nz, w, dx, dy, dz, dt, storage="f32", damping=True, refl=1e-3,
-              max_src=4, max_rec=0, max_steps=0, eta_array=False, two_step=False) -> wave_desc:
+              max_src=4, max_rec=0, max_steps=0, eta_array=False, two_step=False,
+              stochastic_round=False) -> wave_desc:
     d = wave_desc()
     d.nx, d.ny, d.nz, d.w = int(nx), int(ny), int(nz), int(w)
     d.dx, d.dy, d.dz, d.dt = float(dx), float(dy), float(dz), float(dt)
     d.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     d.flags = ((0 if damping else WAVE_DAMPING_OFF) | (WAVE_ETA_ARRAY if (eta_array and damping) else 0)
-               | (WAVE_TWO_STEP if two_step else 0))
+               | (WAVE_TWO_STEP if two_step else 0) | (WAVE_STOCH_ROUND if stochastic_round else 0))
     d.refl = float(refl)
     d.max_src, d.max_rec, d.max_steps = int(max_src), int(max_rec), int(max_steps)
     d.reserved = 0
@@ -332,11 +334,12 @@ class Shot:
 
     def __init__(self, nx, ny, nz, w, dx, dy, dz, dt, vel, *, eta=None, storage="f32",
                  damping=True, refl=1e-3, max_src=4, max_rec=0, max_steps=0,
-                 device="cuda:0", stream=None, two_step=False):
+                 device="cuda:0", stream=None, two_step=False, stochastic_round=False):
         self.device = torch.device(device)
         self.desc = make_desc(nx, ny, nz, w, dx, dy, dz, dt, storage, damping, refl,
                               max_src, max_rec, max_steps,
-                              eta_array=eta is not None and damping, two_step=two_step)
+                              eta_array=eta is not None and damping, two_step=two_step,
+                              stochastic_round=stochastic_round)
         nbytes = wave_bytes_required(self.desc)
         if nbytes == 0:
             raise WaveError(WAVE_EINVAL, "wave_bytes_required")
@@ -429,14 +432,14 @@ class Shot:
 
 
 def shot_from_synth(s, storage="f32", damping=True, device="cuda:0", max_steps=None, eta=None,
-                    stream=None, two_step=False):
+                    stream=None, two_step=False, stochastic_round=False):
     """A `Shot` for a synth.Shot (sources injected, receivers set)."""
     steps = s.steps if max_steps is None else max_steps
     nrec = 0 if s.rec is None else len(s.rec)
     sh = Shot(s.nx, s.ny, s.nz, s.w, s.dx, s.dy, s.dz, s.dt, s.vel, eta=eta, storage=storage,
               damping=damping, max_src=max(1, len(s.src)), max_rec=nrec,
               max_steps=max(steps, s.wavelet.shape[1] if s.wavelet is not None else 0),
-              device=device, stream=stream, two_step=two_step)
+              device=device, stream=stream, two_step=two_step, stochastic_round=stochastic_round)
     for q, (i, j, k) in enumerate(s.src):
         sh.inject(i, j, k, s.wavelet[q])
     if nrec:

@@ -86,6 +86,18 @@ def test_bytes_required_and_validation(W):
     assert W.wave_bytes_required(d) == 0
 
 
+def test_stochastic_rounding_flag_only_with_bf16_and_single_steps(W):
+    """WAVE_STOCH_ROUND is a bf16-storage option: accepted there (same arena
+    as plain bf16), refused with float32 or binary16 storage and together
+    with WAVE_TWO_STEP."""
+    plain = W.wave_bytes_required(_desc(W, storage="bf16"))
+    assert W.wave_bytes_required(_desc(W, storage="bf16", stochastic_round=True)) == plain > 0
+    assert W.wave_bytes_required(_desc(W, storage="f32", stochastic_round=True)) == 0
+    assert W.wave_bytes_required(_desc(W, storage="f16", stochastic_round=True)) == 0
+    assert W.wave_bytes_required(_desc(W, storage="bf16", stochastic_round=True, two_step=True)) == 0
+    assert W.WAVE_STOCH_ROUND == 8
+
+
 def test_alloc_rejects_bad_arguments_before_touching_a_device(W):
     d = _desc(W, dt=1e-3)
     vel = np.full((44, 36, 40), 2000.0, np.float32)

@@ -423,9 +423,10 @@ size_t wave_batch_bytes_required(int32_t max_shots);
 int wave_batch_create(int32_t storage, int32_t max_shots, void *dev_arena, size_t arena_bytes,
                       void *hip_stream, wave_batch **out);
 
-/* Add ctx with `nsteps` steps still to take (EINVAL: wrong storage,
- * already a member, batch full, trace buffer too small, z planes too large
- * for the streaming kernel). */
+/* Add ctx with `nsteps` steps still to take (EINVAL: wrong storage, a
+ * WAVE_STOCH_ROUND flag that differs from the current members' (a batch
+ * runs one kernel instance), already a member, batch full, trace buffer
+ * too small, z planes too large for the streaming kernel). */
 int wave_batch_add(wave_batch *b, wave_ctx *ctx, int32_t nsteps);
 
 /* Remove ctx (it keeps its state and may step on its own again). */

@@ -251,13 +251,16 @@ __device__ inline ChunkInfo chunk_of(int ch, int nz, int w, int zc, bool damp) {
 // neighbours, so halos come from its L2.  The slab an XCD owns moves on by 3
 // (coprime to 8) from one chunk to the next, so the slabs holding the y
 // walls of the damping layer, which cost more, are spread over all XCDs
-// instead of loading the first and the last.  Block b (counted from a
-// multiple of 8) -> tile column tx, tile row ty (>= tiles_y: padding), z
-// chunk ch.
+// instead of loading the first and the last.  With hold = h the slab moves
+// on only every 2^h chunks, so the warm-up planes a chunk reads below its
+// first plane were written to this XCD's L2 by the chunk before (the
+// persistent sweep, which walks the chunks of a slab in order, takes h = 1).
+// Block b (counted from a multiple of 8) -> tile column tx, tile row ty
+// (>= tiles_y: padding), z chunk ch.
 struct TileAt {
   int tx, ty, ch;
 };
-__device__ inline TileAt tile_at(int64_t b, int tiles_x, int tiles_y) {
+__device__ inline TileAt tile_at(int64_t b, int tiles_x, int tiles_y, int hold = 0) {
   const int xcd = (int)(b & 7);
   const int64_t slot = b >> 3;
   const int sh = (tiles_y + 7) >> 3;
@@ -265,7 +268,7 @@ __device__ inline TileAt tile_at(int64_t b, int tiles_x, int tiles_y) {
   TileAt t;
   t.tx = (int)(slot % tiles_x);
   t.ch = (int)(t2 / sh);
-  t.ty = ((xcd + 3 * t.ch) & 7) * sh + (int)(t2 % sh);
+  t.ty = ((xcd + 3 * (t.ch >> hold)) & 7) * sh + (int)(t2 % sh);
   return t;
 }
 

@@ -27,13 +27,18 @@ batch  A subset of the 64-shot batch workload (each axis in {128, .., 384},
        (float32 and bf16 storage) against these.
 serve  A subset of the Poisson serving workload: the request with the
        largest grid and, for each storage type, the five requests with the
-       most steps among grids of at most 5e6 points; float64 samples as for
-       `batch`.
+       most steps among grids of at most 5e6 points (a type with fewer such
+       requests takes the ones of fewest point-steps next); float64 samples
+       as for `batch`.
+
+`--reuse` keeps the stored entries of a `batch` or `serve` golden whose
+request, grid, step count and seed are unchanged (results of an earlier run
+of this script) and runs the oracle only for the others.
 
     OMP_NUM_THREADS=8 python tests/golden/make_fp64_gap.py --config c2
     OMP_NUM_THREADS=8 python tests/golden/make_fp64_gap.py --config c2 --storage bf16
     OMP_NUM_THREADS=8 python tests/golden/make_fp64_gap.py --config batch
-    OMP_NUM_THREADS=8 python tests/golden/make_fp64_gap.py --config serve
+    OMP_NUM_THREADS=8 python tests/golden/make_fp64_gap.py --config serve [--reuse]
     OMP_NUM_THREADS=8 python tests/golden/make_fp64_gap.py --config c3 --scratch /big/dir
 
 Outputs `tests/golden/<name>_fp64_gap.json` (scalars) and `.npz` (samples),
@@ -198,13 +203,34 @@ def config_c3(args):
     os.remove(f64_path)
 
 
-def sampled_f64(name: str, items, what: str):
-    """float64 runs of a list of (key, shot, extra) and their samples."""
+def stored(name: str):
+    """The entries and arrays of a stored golden by key ({} when absent)."""
+    base = os.path.join(HERE, f"{name}_fp64_gap")
+    if not (os.path.exists(base + ".json") and os.path.exists(base + ".npz")):
+        return {}, {}
+    meta = json.load(open(base + ".json"))
+    arr = np.load(base + ".npz")
+    return {e["key"]: e for e in meta["members"]}, {k: arr[k] for k in arr.files}
+
+
+def sampled_f64(name: str, items, what: str, reuse: bool = False):
+    """float64 runs of a list of (key, shot, extra) and their samples;
+    with `reuse`, a stored entry of the same key, grid, steps and seed is
+    kept instead of run again."""
     plane_stride, rec_stride = 8, 8
     entries, arrays = [], {}
+    old_entries, old_arrays = stored(name) if reuse else ({}, {})
     t_start = time.time()
     for key, s, extra in items:
         t0 = time.time()
+        e = old_entries.get(key)
+        if e and e["grid"] == [s.nx, s.ny, s.nz] and e["steps"] == s.steps \
+                and e["seed"] == s.seed and all(e.get(k) == v for k, v in extra.items()):
+            entries.append(e)
+            for part in ("plane", "traces"):
+                arrays[f"{key}_{part}"] = old_arrays[f"{key}_{part}"]
+            print(f"{key}: kept", flush=True)
+            continue
         r = oracle.run_shot(s, precision="f64")
         jsrc = s.src[0][1]
         arrays[f"{key}_plane"] = sample_plane(r["u"], jsrc, plane_stride).astype(np.float32)
@@ -237,7 +263,7 @@ def config_batch(args):
         nx, ny, nz, st, seed = shapes[i]
         items.append((f"b{i}", synth.shot_from_shape(nx, ny, nz, st, seed), {"index": i}))
     sampled_f64("batch", items, "float64 oracle results of a subset of the 64-shot batch "
-                "(synth.batch_shapes, 5 % perturbed layered models)")
+                "(synth.batch_shapes, 5 % perturbed layered models)", reuse=args.reuse)
 
 
 def config_serve(args):
@@ -247,19 +273,24 @@ def config_serve(args):
     for kind in range(3):
         small = [i for i, r in enumerate(reqs) if r["storage"] == kind and grid[i] <= 5_000_000]
         small.sort(key=lambda i: (-reqs[i]["steps"], i))
-        pick += [i for i in small[:5] if i not in pick]
+        more = [i for i, r in enumerate(reqs) if r["storage"] == kind and i not in small]
+        more.sort(key=lambda i: (grid[i] * reqs[i]["steps"], i))
+        take = [i for i in small + more if i not in pick][:5]
+        pick += take
     items = []
     for i in pick:
         r = reqs[i]
         items.append((f"r{i}", synth.shot_from_shape(r["nx"], r["ny"], r["nz"], r["steps"], r["seed"]),
                       {"index": i, "storage": ["f32", "bf16", "f16"][r["storage"]]}))
     sampled_f64("serve", items, "float64 oracle results of a subset of the serving requests "
-                "(synth.serve_requests, 5 % perturbed layered models)")
+                "(synth.serve_requests, 5 % perturbed layered models)", reuse=args.reuse)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--config", default="c2", choices=["c2", "c3", "batch", "serve"])
+    ap.add_argument("--reuse", action="store_true",
+                    help="batch/serve: keep stored entries whose request is unchanged")
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--segment", type=int, default=100, help="steps between checkpoints")
     ap.add_argument("--steps", type=int, default=None, help="override the config's steps")

@@ -126,3 +126,10 @@ def test_batch_and_serve_goldens_match_their_workloads():
             assert tr.shape == (s["steps"], -(-s["nx"] // rs))
             assert np.isfinite(plane).all() and np.abs(plane).max() > 0
             assert np.isfinite(tr).all() and np.abs(tr).max() > 0
+        if name == "serve":
+            # at least 16 requests: the largest grid and five of each storage type
+            grid = [r["nx"] * r["ny"] * r["nz"] for r in spec]
+            idx = [e["index"] for e in meta["members"]]
+            assert len(set(idx)) >= 16 and int(np.argmax(grid)) in idx
+            for kind in range(3):
+                assert sum(spec[i]["storage"] == kind for i in idx) >= 5, kind

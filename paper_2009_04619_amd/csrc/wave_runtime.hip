@@ -297,72 +297,117 @@ int dev_fail(wave_ctx* c, hipError_t e, const char* what) {
     if (_e != hipSuccess) return dev_fail((c), _e, (what)); \
   } while (0)
 
-// Copy a compact host plane sequence into a padded device array.
-int upload_plane(wave_ctx* c, char* dev_base, int esz, int k, const void* host_plane) {
+// Whole-field transfers between a compact host array [nz][ny][nx] and a
+// padded device array.  They go through a pinned host buffer laid out as a
+// run of padded planes (rows y = -4 .. ny+3 of `pitch` elements, zero outside
+// the grid), so each run moves as one contiguous copy.  The ghost rows and
+// the row padding it writes are zero, as the device layout holds them.  (A
+// pitched copy straight from pageable memory moves row by row: at 512^3 a
+// field took about a second that way.)  fill(k, y, row) writes the nx
+// elements of row y of plane k into a row of the buffer; take(k, y, row)
+// reads them back.
+constexpr size_t kStageBytes = size_t(64) << 20;
+
+template <class Fill>
+int upload_field(wave_ctx* c, char* dev_base, int esz, Fill fill) {
   const Layout& L = c->L;
-  char* dst = dev_base + ((size_t)L.origin + (size_t)k * L.plane) * esz;
-  HIPCHK(c,
-         hipMemcpy2DAsync(dst, (size_t)L.pitch * esz, host_plane, (size_t)L.nx * esz,
-                          (size_t)L.nx * esz, L.ny, hipMemcpyHostToDevice, c->stream),
-         "hipMemcpy2DAsync H2D");
-  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
-  return WAVE_OK;
+  const size_t plane_b = (size_t)L.plane * esz;
+  const int run = (int)std::max<size_t>(1, std::min<size_t>(L.nz, kStageBytes / plane_b));
+  void* stage = nullptr;
+  if (hipHostMalloc(&stage, (size_t)run * plane_b, hipHostMallocDefault) != hipSuccess)
+    return fail(WAVE_EDEVICE, "hipHostMalloc of the transfer buffer failed");
+  memset(stage, 0, (size_t)run * plane_b);
+  hipError_t e = hipSuccess;
+  for (int k0 = 0; k0 < L.nz && e == hipSuccess; k0 += run) {
+    const int nk = std::min(run, L.nz - k0);
+    for (int k = 0; k < nk; ++k)
+      for (int y = 0; y < L.ny; ++y)
+        fill(k0 + k, y, static_cast<char*>(stage) +
+                            ((size_t)k * L.plane + (size_t)(y + wave::kR) * L.pitch) * esz);
+    char* dst = dev_base + ((size_t)L.origin + (size_t)k0 * L.plane - (size_t)wave::kR * L.pitch) * esz;
+    e = hipMemcpyAsync(dst, stage, (size_t)nk * plane_b, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // the buffer is refilled next
+  }
+  (void)hipHostFree(stage);
+  return e == hipSuccess ? WAVE_OK : dev_fail(c, e, "field upload");
 }
 
-int download_plane(wave_ctx* c, const char* dev_base, int esz, int k, void* host_plane) {
+template <class Take>
+int download_field(wave_ctx* c, const char* dev_base, int esz, Take take) {
   const Layout& L = c->L;
-  const char* src = dev_base + ((size_t)L.origin + (size_t)k * L.plane) * esz;
-  HIPCHK(c,
-         hipMemcpy2DAsync(host_plane, (size_t)L.nx * esz, src, (size_t)L.pitch * esz,
-                          (size_t)L.nx * esz, L.ny, hipMemcpyDeviceToHost, c->stream),
-         "hipMemcpy2DAsync D2H");
-  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
-  return WAVE_OK;
+  const size_t plane_b = (size_t)L.plane * esz;
+  const int run = (int)std::max<size_t>(1, std::min<size_t>(L.nz, kStageBytes / plane_b));
+  void* stage = nullptr;
+  if (hipHostMalloc(&stage, (size_t)run * plane_b, hipHostMallocDefault) != hipSuccess)
+    return fail(WAVE_EDEVICE, "hipHostMalloc of the transfer buffer failed");
+  hipError_t e = hipSuccess;
+  for (int k0 = 0; k0 < L.nz && e == hipSuccess; k0 += run) {
+    const int nk = std::min(run, L.nz - k0);
+    const char* src =
+        dev_base + ((size_t)L.origin + (size_t)k0 * L.plane - (size_t)wave::kR * L.pitch) * esz;
+    e = hipMemcpyAsync(stage, src, (size_t)nk * plane_b, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) break;
+    for (int k = 0; k < nk; ++k)
+      for (int y = 0; y < L.ny; ++y)
+        take(k0 + k, y, static_cast<const char*>(stage) +
+                            ((size_t)k * L.plane + (size_t)(y + wave::kR) * L.pitch) * esz);
+  }
+  (void)hipHostFree(stage);
+  return e == hipSuccess ? WAVE_OK : dev_fail(c, e, "field download");
+}
+
+// A float field [nz][ny][nx] to or from a padded float array.
+int upload_f32(wave_ctx* c, char* dev_base, const float* host) {
+  const size_t nx = c->L.nx, ny = c->L.ny;
+  return upload_field(c, dev_base, 4, [&](int k, int y, char* row) {
+    memcpy(row, host + ((size_t)k * ny + y) * nx, nx * 4);
+  });
+}
+
+int download_f32(wave_ctx* c, const char* dev_base, float* host) {
+  const size_t nx = c->L.nx, ny = c->L.ny;
+  return download_field(c, dev_base, 4, [&](int k, int y, const char* row) {
+    memcpy(host + ((size_t)k * ny + y) * nx, row, nx * 4);
+  });
 }
 
 // Upload a float field into a u buffer, rounding to the storage format.
 int upload_u(wave_ctx* c, int idx, const float* host) {
-  const size_t pn = (size_t)c->L.nx * c->L.ny;
-  std::vector<uint16_t> tmp;
-  if (c->es == 2) tmp.resize(pn);
-  for (int k = 0; k < c->L.nz; ++k) {
-    const float* src = host + (size_t)k * pn;
-    const void* plane = src;
-    if (c->d.storage == WAVE_BF16) {
-      for (size_t p = 0; p < pn; ++p) tmp[p] = host_bf16(src[p]);
-      plane = tmp.data();
-    } else if (c->d.storage == WAVE_F16) {
-      for (size_t p = 0; p < pn; ++p) {
-        _Float16 h = (_Float16)src[p];
-        memcpy(&tmp[p], &h, 2);
+  const size_t nx = c->L.nx, ny = c->L.ny;
+  const int storage = c->d.storage;
+  if (c->es == 4) return upload_f32(c, c->u_base(idx), host);
+  return upload_field(c, c->u_base(idx), 2, [&](int k, int y, char* row) {
+    const float* src = host + ((size_t)k * ny + y) * nx;
+    uint16_t* dst = reinterpret_cast<uint16_t*>(row);
+    if (storage == WAVE_BF16) {
+      for (size_t i = 0; i < nx; ++i) dst[i] = host_bf16(src[i]);
+    } else {
+      for (size_t i = 0; i < nx; ++i) {
+        const _Float16 h = (_Float16)src[i];
+        memcpy(&dst[i], &h, 2);
       }
-      plane = tmp.data();
     }
-    int rc = upload_plane(c, c->u_base(idx), c->es, k, plane);
-    if (rc) return rc;
-  }
-  return WAVE_OK;
+  });
 }
 
 int download_u(wave_ctx* c, int idx, float* host) {
-  const size_t pn = (size_t)c->L.nx * c->L.ny;
-  std::vector<uint16_t> tmp;
-  if (c->es == 2) tmp.resize(pn);
-  for (int k = 0; k < c->L.nz; ++k) {
-    float* dst = host + (size_t)k * pn;
-    int rc = download_plane(c, c->u_base(idx), c->es, k, c->es == 4 ? (void*)dst : (void*)tmp.data());
-    if (rc) return rc;
-    if (c->d.storage == WAVE_BF16) {
-      for (size_t p = 0; p < pn; ++p) dst[p] = host_from_bf16(tmp[p]);
-    } else if (c->d.storage == WAVE_F16) {
-      for (size_t p = 0; p < pn; ++p) {
+  const size_t nx = c->L.nx, ny = c->L.ny;
+  const int storage = c->d.storage;
+  if (c->es == 4) return download_f32(c, c->u_base(idx), host);
+  return download_field(c, c->u_base(idx), 2, [&](int k, int y, const char* row) {
+    float* dst = host + ((size_t)k * ny + y) * nx;
+    const uint16_t* src = reinterpret_cast<const uint16_t*>(row);
+    if (storage == WAVE_BF16) {
+      for (size_t i = 0; i < nx; ++i) dst[i] = host_from_bf16(src[i]);
+    } else {
+      for (size_t i = 0; i < nx; ++i) {
         _Float16 h;
-        memcpy(&h, &tmp[p], 2);
-        dst[p] = (float)h;
+        memcpy(&h, &src[i], 2);
+        dst[i] = (float)h;
       }
     }
-  }
-  return WAVE_OK;
+  });
 }
 
 // Sweep arguments of a context (cur/nxt are set per step).
@@ -1065,11 +1110,7 @@ int wave_read_field(wave_ctx* c, int32_t which, float* out) {
         memset(out, 0, pn * c->L.nz * sizeof(float));
         return WAVE_OK;
       }
-      for (int k = 0; k < c->L.nz; ++k) {
-        int rc = download_plane(c, c->at(off), 4, k, out + (size_t)k * pn);
-        if (rc) return rc;
-      }
-      return WAVE_OK;
+      return download_f32(c, c->at(off), out);
     }
   }
   return fail(WAVE_EINVAL, "unknown field id");
@@ -1083,17 +1124,12 @@ int wave_write_field(wave_ctx* c, int32_t which, const float* in) {
   for (size_t p = 0; p < n; ++p)
     if (!isfinite(in[p])) return fail(WAVE_EINVAL, "non-finite value");
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
-  const size_t pn = (size_t)c->L.nx * c->L.ny;
   switch (which) {
     case WAVE_FIELD_U: return upload_u(c, c->icur, in);
     case WAVE_FIELD_UPREV: return upload_u(c, c->iprev, in);
     case WAVE_FIELD_PHI: {
       if (c->plan.phi[c->iphi] == (size_t)-1) return fail(WAVE_EINVAL, "no phi field with damping off");
-      for (int k = 0; k < c->L.nz; ++k) {
-        int rc = upload_plane(c, c->at(c->plan.phi[c->iphi]), 4, k, in + (size_t)k * pn);
-        if (rc) return rc;
-      }
-      return WAVE_OK;
+      return upload_f32(c, c->at(c->plan.phi[c->iphi]), in);
     }
   }
   return fail(WAVE_EINVAL, "field is read-only or unknown");

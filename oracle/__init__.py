@@ -18,6 +18,12 @@ marshals numpy arrays.  Every function cites what it follows:
 * `energy`         -- discrete energy of Eq. 2 with damping off (a closed
   form of the scheme, used by the pins).
 * `regions`        -- Sec. III-B, the third decomposition (inner + 6 slabs).
+
+Each of these is pinned to something other than itself in
+`tests/test_oracle_pins.py` (P1-P14 and closed forms).  The layer is a
+reading: its update is pinned by the dense matrix form, the eta = 0
+reduction, energy decay and symmetry; its absorption by P14 against a rigid
+box, with bounds of the test's own (the paper prints no reflection figure).
 """
 from __future__ import annotations
 

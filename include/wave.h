@@ -217,12 +217,18 @@ int64_t wave_step_count(const wave_ctx *ctx);
 #define WAVE_FIELD_ETA 4    /* eta (read only)                   */
 
 /* Copy a field to a host float array [nz][ny][nx] (16-bit storage is
- * widened exactly).  Synchronises.  Errors: EINVAL. */
+ * widened exactly).  Synchronises.  The copy goes through a pinned host
+ * buffer of at most 64 MB (or one padded plane, if larger), allocated and
+ * freed by the call.  Errors: EINVAL; EDEVICE when a copy fails (sticky,
+ * as for every device error) or no pinned memory is left for the buffer
+ * (not sticky). */
 int wave_read_field(wave_ctx *ctx, int32_t which, float *host_out);
 
 /* Overwrite u^n, u^{n-1} or phi^n from a host float array [nz][ny][nx]
  * (rounded to nearest-even into 16-bit storage).  For restarts and tests.
- * Synchronises.  Errors: EINVAL (read-only field, non-finite values). */
+ * Synchronises; the copy goes through a pinned buffer as in
+ * wave_read_field.  Errors: EINVAL (read-only field, non-finite values),
+ * EDEVICE as for wave_read_field. */
 int wave_write_field(wave_ctx *ctx, int32_t which, const float *host_in);
 
 /* Copy the traces recorded since wave_record: float64 [steps][nrec].

@@ -277,6 +277,31 @@ def test_c3_size_few_steps_bitwise(W):
         del g
 
 
+def test_paper_shape_one_step_bitwise(W):
+    """The paper's 1000^3 grid with a 27-cell layer (Sec. V-B, Table III):
+    its width is not a multiple of the 64-column tiles, so the last tile
+    column holds 40 columns and lanes past the grid.  From a random state,
+    one step of the default launch (persistent) and of the per-tile launch
+    against the float32 oracle on every point."""
+    n, w = 1000, 27
+    vel = synth.constant_velocity(n, n, n, 3000.0)
+    dt = synth._dt_for(3000.0)
+    c = n // 2
+    shot = synth.Shot("paper_shape", n, n, n, w, synth.H, synth.H, synth.H, dt, vel, 1,
+                      src=[(c, c, w + 5), (n - 3, n - 5, 2)],
+                      wavelet=np.stack([synth.ricker(1, dt, t0=0.0), synth.ricker(1, dt, t0=0.0)]),
+                      rec=synth.receiver_line(n, c, w + 5), seed=0)
+    say("case paper shape 1000^3 1 step: random state")
+    st = random_state(shot, 13)
+    say("case paper shape 1000^3 1 step: oracle")
+    o = oracle.run_shot(shot, steps=1, precision="f32", state=st)
+    for k in (None, (1, 1, 8, 0)):
+        say(f"case paper shape 1000^3 1 step: GPU kernel {k or 'default'}")
+        g = gpu_run(W, shot, 1, state=st, kernel=k)
+        assert_same(g, o, f"1000^3 {k}")
+        del g
+
+
 def test_long_run_medium_grid_vs_oracles(W):
     """500 steps in 100-step segments: exact against the float32 oracle, and
     within 1e-5 relative L2 of the float64 oracle at every checkpoint."""
